@@ -1,0 +1,166 @@
+/*
+ * c4m.h -- C ABI of the MI355X stepper for the compact fourth-order
+ * staggered (Yee) scheme of Versano, Turkel and Tsynkov, "Fourth order
+ * accurate compact scheme for first-order Maxwell's equations"
+ * (arXiv 2306.17263).
+ *
+ * One call to c4m_step advances the PEC cavity problem by whole time steps.
+ * Each step is the paper's Step 1 followed by Step 2 (Section 3.4):
+ *   E^{n+1}   = E^n + r Phi_E,       M Phi_E = Z curl^A G(H^{n+1/2})
+ *   H^{n+3/2} = H^{n+1/2} + r Phi_H,  M Phi_H = -(1/Z) curl^A (alpha E^{n+1} + l^{n+1}/12)
+ * with r = h_tau/h, alpha = 1 + 2/r^2, beta = r^2/24,
+ *   M   = alpha I - beta L9    (eq:ell times h_tau^2/24; L9 the 9/19-point
+ *                               Singer-Turkel stencil, Definition def:operatorsP),
+ *   G u = alpha u + L5 u / 12  (P2 of Definition def:operatorsP, h^2-scaled),
+ *   curl^A                     (the Pade curl of Appendix A.1, eq:lhs, times h),
+ *   l   = h^2 Delta E          (carried from step to step as printed in Step 1,
+ *                               or recomputed as L5 E in the DISCRETE variant).
+ * Boundary treatment: tangential E = 0 on the walls (eq:bc_E=0), normal H
+ * constant in time (eq:BC_H), even ghosts for the Neumann directions
+ * (Corollary cor:ghost_cor).  Only J = rho = 0 is supported.
+ *
+ * Memory and streams: the caller owns the device workspace (size from
+ * c4m_workspace_bytes, 256-byte aligned) and the HIP stream; the library
+ * allocates no device memory and keeps only a small host handle.  Device
+ * pointers are plain `void*` / `double*` in the current HIP device.
+ *
+ * Field layout at the ABI: FP64, row-major (nz, ny, nx) with x fastest,
+ * walls included.  Component s of E sits at half points along s and nodes
+ * along the other axes; component s of H at nodes along s and half points
+ * along the others (eq:meshes).  A node axis has N+1 points, a half axis N.
+ * In 2D (TM: Ez, Hx, Hy) nz = 1.
+ *
+ * Errors: every function returns a c4m_status; nothing throws across the
+ * ABI.  c4m_last_error() returns a thread-local text for the last failure.
+ * Threading: one problem handle must not be used by two threads at once.
+ */
+#ifndef C4M_H
+#define C4M_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    C4M_OK = 0,
+    C4M_EINVAL = -1,       /* bad argument, shape or configuration              */
+    C4M_ENOMEM = -2,       /* workspace too small                               */
+    C4M_EDEVICE = -3,      /* a HIP call failed                                 */
+    C4M_ESTATE = -4,       /* call not valid in the handle's state              */
+    C4M_ENOCONV = -5,      /* CG did not reach its tolerance (sticky, see info) */
+    C4M_EUNSTABLE = -6,    /* CFL number above the paper's stability bound      */
+    C4M_ENONFINITE = -7    /* a non-finite value was detected (sticky)          */
+} c4m_status;
+
+typedef enum {
+    C4M_EX = 0, C4M_EY = 1, C4M_EZ = 2,
+    C4M_HX = 3, C4M_HY = 4, C4M_HZ = 5,
+    C4M_LX = 6, C4M_LY = 7, C4M_LZ = 8     /* l_s = h^2 (Delta E)_s on E_s's grid */
+} c4m_field;
+
+enum { C4M_CLOSURE_PAPER = 0,    /* printed closure rows (26,-5,4,-1)/24 of eq:lhs  */
+       C4M_CLOSURE_REFLECT = 1 };/* image closure (23,1)/24 or (22,1)/24            */
+enum { C4M_LAP_TRACKED = 0,      /* carry l = h^2 Delta E as in Step 1              */
+       C4M_LAP_DISCRETE = 1 };   /* recompute l = L5 E (second-order Laplacian)     */
+enum { C4M_FP64 = 0,             /* all arithmetic in FP64                          */
+       C4M_FP32_REFINED = 1 };   /* FP32 sweeps, FP64 residuals and state           */
+enum { C4M_SOLVER_CHEBYSHEV = 0, /* reduction-free Chebyshev on the closed-form     *
+                                  * spectral bounds of M (Appendix A.2)             */
+       C4M_SOLVER_PCG = 1 };     /* Jacobi-preconditioned CG with device dot products */
+
+#define C4M_FLAG_ALLOW_ANY_CFL 0x1u   /* skip the CFL guard of create               */
+#define C4M_FLAG_CHECK_FINITE  0x2u   /* scan the fields for NaN/Inf after each call */
+
+typedef struct {
+    int32_t dim;        /* 2 = TM (Ez, Hx, Hy), 3 = full Maxwell                       */
+    int32_t n;          /* cells per side, h = 1/n; 8 <= n <= 16384 (2D), 1024 (3D)     */
+    double cfl;         /* r = h_tau / h; rejected above 5/(6 sqrt 2) in 2D and         *
+                         * 5/(6 sqrt 3) in 3D (Section 4) unless ALLOW_ANY_CFL          */
+    double z;           /* impedance Z > 0                                              */
+    int32_t closure;    /* C4M_CLOSURE_*                                               */
+    int32_t lap_mode;   /* C4M_LAP_*                                                   */
+    int32_t precision;  /* C4M_FP64 or C4M_FP32_REFINED                                */
+    int32_t solver;     /* C4M_SOLVER_*                                                */
+    int32_t sweeps;     /* Chebyshev M-applications per solve (0 = enough for 1e-16)   */
+    int32_t max_iter;   /* PCG iteration cap (0 = 50)                                  */
+    double rtol;        /* PCG relative residual target (0 = 1e-14)                    */
+    int32_t tile_x;     /* kernel tile override (0 = built-in / autotuned)             */
+    int32_t tile_y;
+    uint32_t flags;     /* C4M_FLAG_*                                                  */
+    int32_t reserved[5];
+} c4m_config;
+
+typedef struct {
+    int64_t steps;            /* whole steps taken since create                       */
+    double tau_e, tau_h;      /* time of E and of H relative to the initial data      */
+    int32_t sweeps;           /* Chebyshev applications per solve in use              */
+    int32_t last_iters;       /* PCG: iterations of the last solve                    */
+    int32_t max_iters;        /* PCG: most iterations of any solve so far             */
+    double last_rel_residual; /* PCG: relative residual of the last solve             */
+    int32_t nonfinite;        /* sticky: a NaN/Inf was seen                           */
+    int32_t noconv;           /* sticky: a PCG solve hit max_iter                     */
+    size_t workspace_bytes;   /* bytes of the caller's workspace in use               */
+} c4m_info;
+
+typedef struct c4m_problem c4m_problem;
+typedef struct c4m_batch c4m_batch;
+
+/* Fill *cfg with the defaults: dim 2, n 64, cfl 0.5, z 1, PAPER closure,
+ * carried Laplacian, FP64, Chebyshev. */
+c4m_status c4m_config_default(c4m_config* cfg);
+
+/* Bytes of device workspace a problem with this configuration needs. */
+c4m_status c4m_workspace_bytes(const c4m_config* cfg, size_t* bytes);
+
+/* Create a problem on `d_workspace` (caller-owned, >= c4m_workspace_bytes,
+ * 256-byte aligned, on the current device) and `hip_stream` (NULL = the
+ * null stream).  Uploads the Pade coefficient tables asynchronously on the
+ * stream and zeroes every field.  No kernel runs before this returns except
+ * those uploads and fills.  EUNSTABLE when cfl exceeds the paper's bound. */
+c4m_status c4m_create(const c4m_config* cfg, void* d_workspace, size_t bytes,
+                      void* hip_stream, c4m_problem** out);
+
+/* Stored extent of a field as (nz, ny, nx).  EINVAL for a field the
+ * dimension does not have (e.g. C4M_EX in 2D). */
+c4m_status c4m_field_shape(const c4m_problem* p, c4m_field f, int64_t shape[3]);
+
+/* Copy a whole field in (E at tau = 0, H at tau = h_tau/2, l at tau = 0).
+ * `src` is a device pointer when src_on_device != 0, else host memory (the
+ * call then synchronises the stream).  Tangential E and l are forced to zero
+ * on the walls.  If l is never set after E, the library uses l = L5 E. */
+c4m_status c4m_set_field(c4m_problem* p, c4m_field f, const double* src, int src_on_device);
+
+/* Copy a whole field out; a host destination synchronises the stream. */
+c4m_status c4m_get_field(c4m_problem* p, c4m_field f, double* dst, int dst_on_device);
+
+/* Enqueue nsteps whole steps on the problem's stream (asynchronous). */
+c4m_status c4m_step(c4m_problem* p, int64_t nsteps);
+
+/* Counters and sticky flags; synchronises the stream when PCG statistics
+ * or the finite check are involved. */
+c4m_status c4m_get_info(c4m_problem* p, c4m_info* info);
+
+/* Release the host handle (the workspace stays the caller's). */
+c4m_status c4m_destroy(c4m_problem* p);
+
+/* Batched form: `count` independent problems (2D, any mix of n) on one
+ * workspace, advanced together by one persistent launch per half-step. */
+c4m_status c4m_batch_workspace_bytes(const c4m_config* cfgs, int32_t count, size_t* bytes);
+c4m_status c4m_batch_create(const c4m_config* cfgs, int32_t count, void* d_workspace,
+                            size_t bytes, void* hip_stream, c4m_batch** out);
+/* Borrow the handle of problem i (owned by the batch; use it for set/get). */
+c4m_status c4m_batch_problem(c4m_batch* b, int32_t i, c4m_problem** out);
+/* Advance every problem of the batch by nsteps steps. */
+c4m_status c4m_batch_step(c4m_batch* b, int64_t nsteps);
+c4m_status c4m_batch_destroy(c4m_batch* b);
+
+const char* c4m_status_string(c4m_status s);
+const char* c4m_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

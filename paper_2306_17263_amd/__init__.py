@@ -1,0 +1,6 @@
+"""MI355X stepper for the compact fourth-order staggered scheme of Versano,
+Turkel and Tsynkov (arXiv 2306.17263).  The scheme runs in the gfx950
+library libc4m.so (C ABI in include/c4m.h); this package only marshals
+arguments, with PyTorch providing device memory and streams."""
+from ._lib import C4mError, EXPORTS, load  # noqa: F401
+from .problem import Problem, make_config, workspace_bytes  # noqa: F401

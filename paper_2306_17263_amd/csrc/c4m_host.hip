@@ -1,0 +1,604 @@
+// c4m_host.hip -- host runtime behind the C ABI of include/c4m.h:
+// configuration checks, workspace carving, the Pade coefficient tables, the
+// Chebyshev schedule and the launch sequence of one step.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "c4m_internal.h"
+
+namespace c4m {
+
+// kernels (c4m_kernels_2d.hip, c4m_kernels_3d.hip, c4m_kernels_common.hip)
+hipError_t launch_e_half_2d(hipStream_t st, bool tracked, const double* hx, const double* hy,
+                            double* ez, double* ge, double* t0, double* t1, int N, int P,
+                            const Coef& cf, const PadeTaps& taps, const PadeLine& line_h2n,
+                            const ChebSchedule& cs);
+hipError_t launch_h_half_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy,
+                            double* t0, double* t1, int N, int P, const Coef& cf,
+                            const PadeTaps& taps, const PadeLine& line_n2h, const ChebSchedule& cs);
+hipError_t launch_zero_walls(hipStream_t st, double* a, const Box& bx, int P, size_t plane);
+hipError_t launch_lap_convert(hipStream_t st, double* a, const double* e, double* out, const Box& bx,
+                              int P, size_t plane, double alpha, int mode);
+hipError_t launch_count_nonfinite(hipStream_t st, const double* a, const Box& bx, int P,
+                                  size_t plane, int* count);
+
+namespace {
+
+thread_local std::string g_last_error;
+
+c4m_status fail(c4m_status s, const std::string& msg)
+{
+    g_last_error = msg;
+    return s;
+}
+
+c4m_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(C4M_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+// ---------------------------------------------------------------------------
+// Pade tables.  A is the matrix of eq:lhs for one line kind; the rows of
+// A^{-1} needed near the two ends are computed exactly from a band LU of A
+// (A is strictly diagonally dominant, so no pivoting), the interior row from
+// the middle of a long line.  Row m of the folded operator acts on the line
+// values f[m-R .. m+R+1]: c_m[u] = W(m, m+u-1) - W(m, m+u), W = A^{-1}
+// truncated to |j - m| <= R.
+// ---------------------------------------------------------------------------
+struct BandLU {
+    int n;
+    std::vector<double> a;   // [n][7], entry (i, j) at a[i*7 + (j - i + 3)]
+    double& at(int i, int j) { return a[(size_t)i * 7 + (j - i + 3)]; }
+};
+
+BandLU pade_matrix(int n_out, int closure, bool node_to_half)
+{
+    BandLU m{n_out, std::vector<double>((size_t)n_out * 7, 0.0)};
+    for (int i = 0; i < n_out; ++i) {
+        m.at(i, i) = 22.0 / 24.0;
+        if (i > 0) m.at(i, i - 1) = 1.0 / 24.0;
+        if (i + 1 < n_out) m.at(i, i + 1) = 1.0 / 24.0;
+    }
+    if (closure == C4M_CLOSURE_PAPER) {
+        const double r0[4] = {26.0, -5.0, 4.0, -1.0};
+        for (int t = 0; t < 4; ++t) {
+            m.at(0, t) = r0[t] / 24.0;
+            m.at(n_out - 1, n_out - 1 - t) = r0[t] / 24.0;
+        }
+    } else {
+        const double corner = node_to_half ? 23.0 : 22.0;
+        m.at(0, 0) = corner / 24.0;
+        m.at(n_out - 1, n_out - 1) = corner / 24.0;
+    }
+    // in-place LU (Doolittle) on the band
+    for (int k = 0; k < n_out; ++k) {
+        const double piv = m.at(k, k);
+        for (int i = k + 1; i <= std::min(k + 3, n_out - 1); ++i) {
+            const double l = m.at(i, k) / piv;
+            m.at(i, k) = l;
+            if (l == 0.0) continue;
+            for (int j = k + 1; j <= std::min(k + 3, n_out - 1); ++j) m.at(i, j) -= l * m.at(k, j);
+        }
+    }
+    return m;
+}
+
+// column `col` of A^{-1}
+void inverse_column(BandLU& lu, int col, std::vector<double>& x)
+{
+    const int n = lu.n;
+    x.assign(n, 0.0);
+    x[col] = 1.0;
+    for (int i = 0; i < n; ++i)
+        for (int k = std::max(0, i - 3); k < i; ++k) x[i] -= lu.at(i, k) * x[k];
+    for (int i = n - 1; i >= 0; --i) {
+        double s = x[i];
+        for (int k = i + 1; k <= std::min(i + 3, n - 1); ++k) s -= lu.at(i, k) * x[k];
+        x[i] = s / lu.at(i, i);
+    }
+}
+
+struct PadeHost {
+    std::vector<double> rows;   // [n_rows][PADE_TAPS]
+    int n_in = 0, n_out = 0, b = 0, all = 0;
+    PadeTaps taps{};
+};
+
+// W(m, j) for the needed (m, j) pairs, folded into line taps.
+PadeHost build_pade(int n_in, int closure, bool node_to_half)
+{
+    PadeHost ph;
+    ph.n_in = n_in;
+    ph.n_out = n_in - 1;
+    const int n_out = ph.n_out;
+    ph.all = n_out <= 2 * PADE_B;
+    ph.b = ph.all ? n_out : PADE_B;
+    BandLU lu = pade_matrix(n_out, closure, node_to_half);
+    std::vector<int> row_ids;
+    if (ph.all) {
+        for (int m = 0; m < n_out; ++m) row_ids.push_back(m);
+    } else {
+        for (int m = 0; m < PADE_B; ++m) row_ids.push_back(m);
+        for (int m = n_out - PADE_B; m < n_out; ++m) row_ids.push_back(m);
+    }
+    // columns needed: every j within R of a requested row
+    std::vector<std::vector<double>> cols(n_out);
+    std::vector<double> tmp;
+    auto W = [&](int m, int j) -> double {
+        if (j < 0 || j >= n_out || std::abs(j - m) > PADE_R) return 0.0;
+        if (cols[j].empty()) {
+            inverse_column(lu, j, tmp);
+            cols[j] = tmp;
+        }
+        return cols[j][m];
+    };
+    ph.rows.assign(row_ids.size() * PADE_TAPS, 0.0);
+    for (size_t r = 0; r < row_ids.size(); ++r) {
+        const int m = row_ids[r];
+        for (int u = -PADE_R; u <= PADE_R + 1; ++u)
+            ph.rows[r * PADE_TAPS + (u + PADE_R)] = W(m, m + u - 1) - W(m, m + u);
+    }
+    // interior taps from the middle row of a long line of the same kind
+    const int nl = 4 * PADE_B + 1;
+    BandLU lul = pade_matrix(nl, closure, node_to_half);
+    const int mid = nl / 2;
+    std::vector<double> wrow(2 * PADE_R + 1);
+    for (int k = -PADE_R; k <= PADE_R; ++k) {
+        inverse_column(lul, mid + k, tmp);
+        wrow[k + PADE_R] = tmp[mid];
+    }
+    auto Wi = [&](int k) { return (k < -PADE_R || k > PADE_R) ? 0.0 : wrow[k + PADE_R]; };
+    for (int u = -PADE_R; u <= PADE_R + 1; ++u) ph.taps.c[u + PADE_R] = Wi(u - 1) - Wi(u);
+    return ph;
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev schedule on [alpha, alpha + 16/3 beta] (Saad's Chebyshev
+// acceleration); the number of M-applications is the smallest K with
+// 1 / T_{K+1}(theta/delta) <= tol.
+// ---------------------------------------------------------------------------
+ChebSchedule chebyshev(double alpha, double beta, int sweeps, double tol)
+{
+    ChebSchedule cs{};
+    const double lmin = alpha, lmax = alpha + 16.0 / 3.0 * beta;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    const double sigma = theta / delta;
+    if (sweeps <= 0) {
+        sweeps = 1;
+        while (sweeps < MAX_SWEEPS && 1.0 / cosh((sweeps + 1) * acosh(sigma)) > tol) ++sweeps;
+    }
+    cs.sweeps = sweeps;
+    cs.inv_theta = 1.0 / theta;
+    cs.inv_thetaf = (float)cs.inv_theta;
+    double rho = 1.0 / sigma;
+    for (int k = 0; k < sweeps; ++k) {
+        const double rn = 1.0 / (2.0 * sigma - rho);
+        cs.c1[k] = rn * rho;
+        cs.c2[k] = 2.0 * rn / delta;
+        cs.c1f[k] = (float)cs.c1[k];
+        cs.c2f[k] = (float)cs.c2[k];
+        rho = rn;
+    }
+    return cs;
+}
+
+}  // namespace
+}  // namespace c4m
+
+using namespace c4m;
+
+// ---------------------------------------------------------------------------
+// Problem handle.
+// ---------------------------------------------------------------------------
+enum { LAP_UNSET = 0, LAP_RAW = 1, LAP_GE = 2 };
+
+struct c4m_problem {
+    c4m_config cfg{};
+    int dim = 0, N = 0, P = 0;
+    size_t plane = 0, arr = 0;          // elements per plane / per array
+    hipStream_t stream = nullptr;
+    char* ws = nullptr;
+    size_t ws_bytes = 0, used = 0;
+    double* f[6] = {};                  // Ex Ey Ez Hx Hy Hz
+    double* ge[3] = {};                 // G_E per E component (carried Laplacian)
+    double* tmp[5] = {};
+    double* pade_dev[2] = {};           // [0] node->half (n_in N+1), [1] half->node (n_in N)
+    int* counter = nullptr;
+    PadeHost pade_host[2];
+    PadeLine line[2]{};
+    ChebSchedule cheb{};
+    Coef coef{};
+    Box box[6]{};
+    int lap_state[3] = {LAP_UNSET, LAP_UNSET, LAP_UNSET};
+    int64_t steps = 0;
+    int nonfinite = 0;
+    bool owned_by_batch = false;
+};
+
+namespace {
+
+bool has_field(int dim, int f)
+{
+    if (f < 0 || f > 8) return false;
+    if (dim == 3) return true;
+    return f == C4M_EZ || f == C4M_HX || f == C4M_HY || f == C4M_LZ;
+}
+
+int field_comp(int f) { return f >= C4M_LX ? f - C4M_LX : f; }
+
+Box make_box(int dim, int N, int comp)
+{
+    Box b{};
+    const int s = comp % 3;
+    const bool is_e = comp < 3;
+    for (int d = 0; d < 3; ++d) {
+        b.active[d] = d < dim;
+        if (!b.active[d]) {
+            b.n[d] = 1;
+            continue;
+        }
+        b.half[d] = is_e ? (d == s) : (d != s);
+        b.n[d] = b.half[d] ? N : N + 1;
+    }
+    return b;
+}
+
+c4m_status validate(const c4m_config* c)
+{
+    if (!c) return fail(C4M_EINVAL, "null config");
+    if (c->dim != 2 && c->dim != 3) return fail(C4M_EINVAL, "dim must be 2 or 3");
+    const int nmax = c->dim == 2 ? 16384 : 1024;
+    if (c->n < 8 || c->n > nmax) return fail(C4M_EINVAL, "n out of range");
+    if (!(c->cfl > 0.0) || !(c->z > 0.0)) return fail(C4M_EINVAL, "cfl and z must be positive");
+    if (c->closure != C4M_CLOSURE_PAPER && c->closure != C4M_CLOSURE_REFLECT)
+        return fail(C4M_EINVAL, "bad closure");
+    if (c->lap_mode != C4M_LAP_TRACKED && c->lap_mode != C4M_LAP_DISCRETE)
+        return fail(C4M_EINVAL, "bad lap_mode");
+    if (c->precision != C4M_FP64 && c->precision != C4M_FP32_REFINED)
+        return fail(C4M_EINVAL, "bad precision");
+    if (c->solver != C4M_SOLVER_CHEBYSHEV && c->solver != C4M_SOLVER_PCG)
+        return fail(C4M_EINVAL, "bad solver");
+    if (c->sweeps < 0 || c->sweeps > MAX_SWEEPS) return fail(C4M_EINVAL, "sweeps out of range");
+    // Section 4: r <= 1/(sqrt(d) ||A^{-1}||) with ||A^{-1}|| ~ 6/5
+    const double bound = 5.0 / (6.0 * sqrt((double)c->dim));
+    if (!(c->flags & C4M_FLAG_ALLOW_ANY_CFL) && c->cfl > bound * (1.0 + 1e-12))
+        return fail(C4M_EUNSTABLE, "cfl above the stability bound 5/(6 sqrt(dim))");
+    if (c->dim == 3 || c->precision != C4M_FP64 || c->solver != C4M_SOLVER_CHEBYSHEV)
+        return fail(C4M_EINVAL, "configuration not supported by this build");
+    return C4M_OK;
+}
+
+struct Layout {
+    int P;
+    size_t plane, arr, arr_bytes, table_bytes[2], total;
+    int n_fields, n_ge, n_tmp;
+};
+
+Layout layout(const c4m_config* c)
+{
+    Layout L{};
+    const int N = c->n;
+    L.P = (N + 1 + 15) / 16 * 16;
+    L.plane = (size_t)(N + 1) * L.P;
+    L.arr = c->dim == 2 ? L.plane : L.plane * (N + 1);
+    L.arr_bytes = align256(L.arr * sizeof(double));
+    L.n_fields = c->dim == 2 ? 3 : 6;
+    L.n_ge = c->lap_mode == C4M_LAP_TRACKED ? (c->dim == 2 ? 1 : 3) : 0;
+    L.n_tmp = c->dim == 2 ? 2 : 5;
+    for (int k = 0; k < 2; ++k) {
+        const int n_out = (k == 0 ? N + 1 : N) - 1;
+        const int rows = n_out <= 2 * PADE_B ? n_out : 2 * PADE_B;
+        L.table_bytes[k] = align256((size_t)rows * PADE_TAPS * sizeof(double));
+    }
+    L.total = (size_t)(L.n_fields + L.n_ge + L.n_tmp) * L.arr_bytes + L.table_bytes[0] +
+              L.table_bytes[1] + 256;
+    return L;
+}
+
+c4m_status memset_async(c4m_problem* p, void* dst, size_t bytes)
+{
+    hipError_t e = hipMemsetAsync(dst, 0, bytes, p->stream);
+    return e == hipSuccess ? C4M_OK : hip_fail(e, "hipMemsetAsync");
+}
+
+// make every E component's G_E array hold G_E
+c4m_status ensure_ge(c4m_problem* p)
+{
+    if (p->cfg.lap_mode != C4M_LAP_TRACKED) return C4M_OK;
+    for (int s = 0; s < 3; ++s) {
+        if (!p->f[s] || p->lap_state[s] == LAP_GE) continue;
+        const int mode = p->lap_state[s] == LAP_RAW ? 0 : 2;
+        hipError_t e = launch_lap_convert(p->stream, p->ge[s], p->f[s], nullptr, p->box[s], p->P,
+                                          p->plane, p->coef.alpha, mode);
+        if (e != hipSuccess) return hip_fail(e, "lap_convert");
+        p->lap_state[s] = LAP_GE;
+    }
+    return C4M_OK;
+}
+
+c4m_status copy_field(c4m_problem* p, double* dev, const Box& bx, const double* host_or_dev,
+                      bool to_device, bool other_on_device)
+{
+    const size_t w = (size_t)bx.n[0] * sizeof(double);
+    const size_t dpitch = (size_t)p->P * sizeof(double);
+    const hipMemcpyKind kind = other_on_device ? hipMemcpyDeviceToDevice
+                                               : (to_device ? hipMemcpyHostToDevice
+                                                            : hipMemcpyDeviceToHost);
+    for (int k = 0; k < bx.n[2]; ++k) {
+        double* d = dev + k * p->plane;
+        const double* o = host_or_dev + (size_t)k * bx.n[1] * bx.n[0];
+        hipError_t e;
+        if (to_device)
+            e = hipMemcpy2DAsync(d, dpitch, o, w, w, bx.n[1], kind, p->stream);
+        else
+            e = hipMemcpy2DAsync((void*)o, w, d, dpitch, w, bx.n[1], kind, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync");
+    }
+    if (!other_on_device) {
+        hipError_t e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    }
+    return C4M_OK;
+}
+
+c4m_status step_once(c4m_problem* p)
+{
+    const int N = p->N, P = p->P;
+    const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+    hipError_t e;
+    if (p->dim == 2) {
+        e = launch_e_half_2d(p->stream, tracked, p->f[C4M_HX], p->f[C4M_HY], p->f[C4M_EZ], p->ge[2],
+                             p->tmp[0], p->tmp[1], N, P, p->coef, p->pade_host[1].taps, p->line[1],
+                             p->cheb);
+        if (e != hipSuccess) return hip_fail(e, "E half-step");
+        e = launch_h_half_2d(p->stream, tracked, tracked ? p->ge[2] : p->f[C4M_EZ], p->f[C4M_HX],
+                             p->f[C4M_HY], p->tmp[0], p->tmp[1], N, P, p->coef,
+                             p->pade_host[0].taps, p->line[0], p->cheb);
+        if (e != hipSuccess) return hip_fail(e, "H half-step");
+        return C4M_OK;
+    }
+    return fail(C4M_EINVAL, "3D stepping not supported by this build");
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* c4m_status_string(c4m_status s)
+{
+    switch (s) {
+        case C4M_OK: return "ok";
+        case C4M_EINVAL: return "invalid argument";
+        case C4M_ENOMEM: return "workspace too small";
+        case C4M_EDEVICE: return "device error";
+        case C4M_ESTATE: return "invalid state";
+        case C4M_ENOCONV: return "solver did not converge";
+        case C4M_EUNSTABLE: return "cfl above the stability bound";
+        case C4M_ENONFINITE: return "non-finite value";
+    }
+    return "unknown status";
+}
+
+const char* c4m_last_error(void) { return g_last_error.c_str(); }
+
+c4m_status c4m_config_default(c4m_config* cfg)
+{
+    if (!cfg) return fail(C4M_EINVAL, "null config");
+    memset(cfg, 0, sizeof(*cfg));
+    cfg->dim = 2;
+    cfg->n = 64;
+    cfg->cfl = 0.5;
+    cfg->z = 1.0;
+    cfg->closure = C4M_CLOSURE_PAPER;
+    cfg->lap_mode = C4M_LAP_TRACKED;
+    cfg->precision = C4M_FP64;
+    cfg->solver = C4M_SOLVER_CHEBYSHEV;
+    return C4M_OK;
+}
+
+c4m_status c4m_workspace_bytes(const c4m_config* cfg, size_t* bytes)
+{
+    c4m_status s = validate(cfg);
+    if (s != C4M_OK) return s;
+    if (!bytes) return fail(C4M_EINVAL, "null bytes");
+    *bytes = layout(cfg).total;
+    return C4M_OK;
+}
+
+c4m_status c4m_create(const c4m_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+                      c4m_problem** out)
+{
+    c4m_status s = validate(cfg);
+    if (s != C4M_OK) return s;
+    if (!out) return fail(C4M_EINVAL, "null out");
+    *out = nullptr;
+    if (!d_workspace || ((uintptr_t)d_workspace & 255)) return fail(C4M_EINVAL, "workspace must be 256-byte aligned");
+    const Layout L = layout(cfg);
+    if (bytes < L.total) return fail(C4M_ENOMEM, "workspace smaller than c4m_workspace_bytes");
+    c4m_problem* p = new (std::nothrow) c4m_problem();
+    if (!p) return fail(C4M_ENOMEM, "host allocation");
+    p->cfg = *cfg;
+    p->dim = cfg->dim;
+    p->N = cfg->n;
+    p->P = L.P;
+    p->plane = L.plane;
+    p->arr = L.arr;
+    p->stream = (hipStream_t)hip_stream;
+    p->ws = (char*)d_workspace;
+    p->ws_bytes = bytes;
+    char* cur = p->ws;
+    auto take = [&](size_t nbytes) {
+        char* r = cur;
+        cur += nbytes;
+        return r;
+    };
+    for (int c = 0; c < 6; ++c)
+        if (has_field(p->dim, c)) {
+            p->f[c] = (double*)take(L.arr_bytes);
+            p->box[c] = make_box(p->dim, p->N, c);
+        }
+    if (cfg->lap_mode == C4M_LAP_TRACKED)
+        for (int c = 0; c < 3; ++c)
+            if (p->f[c]) p->ge[c] = (double*)take(L.arr_bytes);
+    for (int t = 0; t < L.n_tmp; ++t) p->tmp[t] = (double*)take(L.arr_bytes);
+    p->pade_dev[0] = (double*)take(L.table_bytes[0]);
+    p->pade_dev[1] = (double*)take(L.table_bytes[1]);
+    p->counter = (int*)take(256);
+    p->used = (size_t)(cur - p->ws);
+
+    const double r = cfg->cfl;
+    p->coef.alpha = 1.0 + 2.0 / (r * r);
+    p->coef.beta = r * r / 24.0;
+    p->coef.cfl = r;
+    p->coef.z = cfg->z;
+    p->coef.ge_gain = 1.0 + 4.0 / (r * r);
+    p->coef.ge_curl = 2.0 / r * cfg->z;
+    p->cheb = chebyshev(p->coef.alpha, p->coef.beta, cfg->sweeps, 1e-16);
+
+    for (int k = 0; k < 2; ++k) {
+        const int n_in = k == 0 ? p->N + 1 : p->N;
+        p->pade_host[k] = build_pade(n_in, cfg->closure, k == 0);
+        const PadeHost& ph = p->pade_host[k];
+        p->line[k] = PadeLine{p->pade_dev[k], ph.n_in, ph.n_out, ph.b, ph.all};
+        hipError_t e = hipMemcpyAsync(p->pade_dev[k], ph.rows.data(), ph.rows.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, p->stream);
+        if (e != hipSuccess) {
+            delete p;
+            return hip_fail(e, "table upload");
+        }
+    }
+    // zero fields, G_E and temporaries
+    const size_t zero_bytes = (size_t)((char*)p->pade_dev[0] - p->ws);
+    s = memset_async(p, p->ws, zero_bytes);
+    if (s == C4M_OK) s = memset_async(p, p->counter, 256);
+    if (s == C4M_OK) {
+        hipError_t e = hipStreamSynchronize(p->stream);   // host tables may be released after this
+        if (e != hipSuccess) s = hip_fail(e, "hipStreamSynchronize");
+    }
+    if (s != C4M_OK) {
+        delete p;
+        return s;
+    }
+    *out = p;
+    return C4M_OK;
+}
+
+c4m_status c4m_field_shape(const c4m_problem* p, c4m_field f, int64_t shape[3])
+{
+    if (!p || !shape || !has_field(p->dim, f)) return fail(C4M_EINVAL, "bad field");
+    const Box& b = p->box[field_comp(f)];
+    shape[0] = b.n[2];
+    shape[1] = b.n[1];
+    shape[2] = b.n[0];
+    return C4M_OK;
+}
+
+c4m_status c4m_set_field(c4m_problem* p, c4m_field f, const double* src, int src_on_device)
+{
+    if (!p || !src || !has_field(p->dim, f)) return fail(C4M_EINVAL, "bad field");
+    const int c = field_comp(f);
+    const bool is_lap = f >= C4M_LX;
+    if (is_lap && p->cfg.lap_mode != C4M_LAP_TRACKED) return C4M_OK;   // recomputed each step
+    if (!is_lap && c < 3 && p->cfg.lap_mode == C4M_LAP_TRACKED && p->lap_state[c] == LAP_GE) {
+        // keep l: convert G_E back to l with the old E before E changes
+        hipError_t e = launch_lap_convert(p->stream, p->ge[c], p->f[c], p->ge[c], p->box[c], p->P,
+                                          p->plane, p->coef.alpha, 1);
+        if (e != hipSuccess) return hip_fail(e, "lap_convert");
+        p->lap_state[c] = LAP_RAW;
+    }
+    double* dst = is_lap ? p->ge[c] : p->f[c];
+    c4m_status s = copy_field(p, dst, p->box[c], src, true, src_on_device != 0);
+    if (s != C4M_OK) return s;
+    if (c < 3) {
+        hipError_t e = launch_zero_walls(p->stream, dst, p->box[c], p->P, p->plane);
+        if (e != hipSuccess) return hip_fail(e, "zero_walls");
+    }
+    if (is_lap) p->lap_state[c] = LAP_RAW;
+    return C4M_OK;
+}
+
+c4m_status c4m_get_field(c4m_problem* p, c4m_field f, double* dst, int dst_on_device)
+{
+    if (!p || !dst || !has_field(p->dim, f)) return fail(C4M_EINVAL, "bad field");
+    const int c = field_comp(f);
+    const bool is_lap = f >= C4M_LX;
+    const double* srcp = p->f[c];
+    if (is_lap) {
+        if (p->cfg.lap_mode != C4M_LAP_TRACKED || p->lap_state[c] == LAP_UNSET) {
+            // l = L5 E, produced in a temporary (as G_E, then converted)
+            hipError_t e = launch_lap_convert(p->stream, p->tmp[0], p->f[c], nullptr, p->box[c], p->P,
+                                              p->plane, p->coef.alpha, 2);
+            if (e == hipSuccess)
+                e = launch_lap_convert(p->stream, p->tmp[0], p->f[c], p->tmp[0], p->box[c], p->P,
+                                       p->plane, p->coef.alpha, 1);
+            if (e != hipSuccess) return hip_fail(e, "lap_convert");
+            srcp = p->tmp[0];
+        } else if (p->lap_state[c] == LAP_GE) {
+            hipError_t e = launch_lap_convert(p->stream, p->ge[c], p->f[c], p->tmp[0], p->box[c], p->P,
+                                              p->plane, p->coef.alpha, 1);
+            if (e != hipSuccess) return hip_fail(e, "lap_convert");
+            srcp = p->tmp[0];
+        } else {
+            srcp = p->ge[c];
+        }
+    }
+    return copy_field(p, (double*)srcp, p->box[c], dst, false, dst_on_device != 0);
+}
+
+c4m_status c4m_step(c4m_problem* p, int64_t nsteps)
+{
+    if (!p || nsteps < 0) return fail(C4M_EINVAL, "bad step count");
+    c4m_status s = ensure_ge(p);
+    if (s != C4M_OK) return s;
+    for (int64_t t = 0; t < nsteps; ++t) {
+        s = step_once(p);
+        if (s != C4M_OK) return s;
+        ++p->steps;
+    }
+    if (p->cfg.flags & C4M_FLAG_CHECK_FINITE) {
+        hipError_t e = hipMemsetAsync(p->counter, 0, sizeof(int), p->stream);
+        for (int c = 0; c < 6 && e == hipSuccess; ++c)
+            if (p->f[c])
+                e = launch_count_nonfinite(p->stream, p->f[c], p->box[c], p->P, p->plane, p->counter);
+        int h = 0;
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(&h, p->counter, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return hip_fail(e, "finite check");
+        if (h) {
+            p->nonfinite = 1;
+            return fail(C4M_ENONFINITE, "non-finite field values");
+        }
+    }
+    return C4M_OK;
+}
+
+c4m_status c4m_get_info(c4m_problem* p, c4m_info* info)
+{
+    if (!p || !info) return fail(C4M_EINVAL, "null argument");
+    memset(info, 0, sizeof(*info));
+    info->steps = p->steps;
+    info->tau_e = p->steps * p->cfg.cfl / p->N;
+    info->tau_h = (p->steps + 0.5) * p->cfg.cfl / p->N;
+    info->sweeps = p->cheb.sweeps;
+    info->nonfinite = p->nonfinite;
+    info->workspace_bytes = p->used;
+    return C4M_OK;
+}
+
+c4m_status c4m_destroy(c4m_problem* p)
+{
+    if (!p) return fail(C4M_EINVAL, "null problem");
+    if (p->owned_by_batch) return fail(C4M_ESTATE, "problem belongs to a batch");
+    delete p;
+    return C4M_OK;
+}
+
+// batched form: filled in by c4m_batch.hip
+}  // extern "C"

@@ -1,0 +1,72 @@
+// c4m_internal.h -- shared between the host runtime and the gfx950 kernels.
+//
+// Device layout: every field of a problem lives in one padded array shape,
+// (nz, ny, P) with row pitch P = round_up(N + 1, 16) doubles and ny = N + 1
+// (nz = N + 1 in 3D, 1 in 2D), so all components share the strides
+// sy = P and sz = (N + 1) P and differ only in their valid extents.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "c4m.h"
+
+namespace c4m {
+
+// Truncated inverse of the Pade matrix A (Appendix A.1, eq:lhs).  The
+// interior rows of A^{-1} decay like |rho|^k with rho = -11 + sqrt(120)
+// (|rho| ~ 0.0455), so entries beyond |k| = PADE_R (< 5e-18 relative) are
+// dropped.  Folding the two-point difference D into the rows gives
+// 2 PADE_R + 2 taps on the undifferenced line values.
+constexpr int PADE_R = 12;
+constexpr int PADE_TAPS = 2 * PADE_R + 2;
+constexpr int PADE_B = 2 * PADE_R;   // explicit rows at each end of a line
+
+struct PadeTaps {
+    double c[PADE_TAPS];             // interior (Toeplitz) row, tap u at c[u + PADE_R]
+};
+
+// Device view of one line kind (a given n_in and node/half orientation).
+// Rows m < b and m >= n_out - b use rows[] (b rows at each end, stored left
+// block then right block); if `all` is set every row is explicit (short
+// lines) and rows[m] is row m.
+struct PadeLine {
+    const double* rows;              // [n_rows][PADE_TAPS]
+    int n_in, n_out, b, all;
+};
+
+// Spectral bounds of M = alpha I - beta L9: [alpha, alpha + 16/3 beta]
+// (symbol S in [0, 16/3], Appendix A.2); Chebyshev schedule on them.
+constexpr int MAX_SWEEPS = 8;
+struct ChebSchedule {
+    double inv_theta;                // 1 / theta, theta = (lmax + lmin) / 2
+    double c1[MAX_SWEEPS];           // d <- c1 d + c2 r after apply k
+    double c2[MAX_SWEEPS];
+    float c1f[MAX_SWEEPS];
+    float c2f[MAX_SWEEPS];
+    float inv_thetaf;
+    int sweeps;
+};
+
+// Unknown range of one component grid along x, y, z and the boundary type:
+// Dirichlet (node axis, walls excluded, value 0 beyond) or Neumann (half
+// axis, even ghost).
+struct UGrid {
+    int lo[3], hi[3];
+    int neumann[3];
+};
+
+// Extent and half-point flags of one component on the common padded layout.
+struct Box {
+    int n[3];
+    int half[3];
+    int active[3];
+};
+
+struct Coef {
+    double alpha, beta, cfl, z;
+    double ge_gain;                  // 1 + 4/r^2 : G_E += ge_gain * dE - ...
+    double ge_curl;                  // (2/r) Z   : ... - ge_curl * curl^A H
+};
+
+}  // namespace c4m

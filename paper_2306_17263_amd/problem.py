@@ -1,0 +1,114 @@
+"""Python handle over one c4m problem.  PyTorch supplies the device workspace
+and the HIP stream; every step of the scheme runs in libc4m.so."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def make_config(dim: int = 2, n: int = 64, cfl: float = 0.5, z: float = 1.0,
+                closure: str = "paper", lap_mode: str = "tracked", precision: str = "fp64",
+                solver: str = "chebyshev", sweeps: int = 0, max_iter: int = 0, rtol: float = 0.0,
+                tile_x: int = 0, tile_y: int = 0, flags: int = 0) -> L.C4mConfig:
+    lib = L.load()
+    cfg = L.C4mConfig()
+    L.check(lib.c4m_config_default(ctypes.byref(cfg)), "c4m_config_default")
+    cfg.dim, cfg.n, cfg.cfl, cfg.z = dim, n, cfl, z
+    cfg.closure = L.CLOSURE[closure]
+    cfg.lap_mode = L.LAP[lap_mode]
+    cfg.precision = L.PRECISION[precision]
+    cfg.solver = L.SOLVER[solver]
+    cfg.sweeps, cfg.max_iter, cfg.rtol = sweeps, max_iter, rtol
+    cfg.tile_x, cfg.tile_y, cfg.flags = tile_x, tile_y, flags
+    return cfg
+
+
+def workspace_bytes(cfg: L.C4mConfig) -> int:
+    lib = L.load()
+    out = ctypes.c_size_t()
+    L.check(lib.c4m_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)), "c4m_workspace_bytes")
+    return out.value
+
+
+def _stream_ptr(stream) -> int:
+    return int(stream.cuda_stream)
+
+
+class Problem:
+    """One PEC cavity problem resident on the device."""
+
+    def __init__(self, dim: int = 2, n: int = 64, cfl: float = 0.5, *, device="cuda",
+                 stream=None, **kw):
+        self._lib = L.load()
+        self.cfg = make_config(dim, n, cfl, **kw)
+        self.device = torch.device(device)
+        self.nbytes = workspace_bytes(self.cfg)
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self._h = ctypes.c_void_p()
+        L.check(self._lib.c4m_create(ctypes.byref(self.cfg), ctypes.c_void_p(self.workspace.data_ptr()),
+                                     self.nbytes, ctypes.c_void_p(_stream_ptr(self.stream)),
+                                     ctypes.byref(self._h)), "c4m_create")
+        self.dim, self.n, self.cfl = dim, n, cfl
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            L.check(self._lib.c4m_destroy(self._h), "c4m_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def shape(self, name: str):
+        s = (ctypes.c_int64 * 3)()
+        L.check(self._lib.c4m_field_shape(self._h, L.FIELD[name], s), f"c4m_field_shape({name})")
+        return (s[0], s[1], s[2])
+
+    def set(self, name: str, value):
+        shp = self.shape(name)
+        if isinstance(value, torch.Tensor) and value.is_cuda:
+            t = value.to(torch.float64).contiguous().reshape(shp)
+            self._keep = t
+            L.check(self._lib.c4m_set_field(self._h, L.FIELD[name], ctypes.c_void_p(t.data_ptr()), 1),
+                    f"c4m_set_field({name})")
+            return
+        a = np.ascontiguousarray(np.asarray(value, dtype=np.float64).reshape(shp))
+        L.check(self._lib.c4m_set_field(self._h, L.FIELD[name], a.ctypes.data_as(ctypes.c_void_p), 0),
+                f"c4m_set_field({name})")
+
+    def get(self, name: str, device: bool = False):
+        shp = self.shape(name)
+        if device:
+            out = torch.empty(shp, dtype=torch.float64, device=self.device)
+            L.check(self._lib.c4m_get_field(self._h, L.FIELD[name], ctypes.c_void_p(out.data_ptr()), 1),
+                    f"c4m_get_field({name})")
+            return out
+        out = np.empty(shp, dtype=np.float64)
+        L.check(self._lib.c4m_get_field(self._h, L.FIELD[name], out.ctypes.data_as(ctypes.c_void_p), 0),
+                f"c4m_get_field({name})")
+        return out
+
+    def step(self, nsteps: int = 1):
+        L.check(self._lib.c4m_step(self._h, int(nsteps)), "c4m_step")
+
+    def info(self) -> dict:
+        inf = L.C4mInfo()
+        L.check(self._lib.c4m_get_info(self._h, ctypes.byref(inf)), "c4m_get_info")
+        return {f: getattr(inf, f) for f, _ in L.C4mInfo._fields_}
+
+    def fields(self):
+        names = ["ez", "hx", "hy"] if self.dim == 2 else ["ex", "ey", "ez", "hx", "hy", "hz"]
+        if self.cfg.lap_mode == L.LAP["tracked"]:
+            names += ["lz"] if self.dim == 2 else ["lx", "ly", "lz"]
+        return names

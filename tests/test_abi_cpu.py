@@ -1,0 +1,54 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every symbol include/c4m.h declares, and rejects bad configurations before
+touching the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    from paper_2306_17263_amd import _lib as L
+    if not os.path.exists(L.LIB_PATH):
+        pytest.skip("libc4m.so not built (run __graft_entry__.build())")
+    return L, L.load()
+
+
+def test_header_declarations_are_exported():
+    L, lib = _lib()
+    header = open(os.path.join(ROOT, "include", "c4m.h")).read()
+    declared = set(re.findall(r"\b(c4m_[a-z_]+)\s*\(", header))
+    assert declared == set(L.EXPORTS)
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_config_validation_without_device():
+    from paper_2306_17263_amd.problem import make_config
+    L, lib = _lib()
+    out = ctypes.c_size_t()
+    cfg = make_config(dim=2, n=64)
+    assert lib.c4m_workspace_bytes(ctypes.byref(cfg), ctypes.byref(out)) == L.OK
+    assert out.value > 4 * 65 * 80 * 8
+    bad = make_config(dim=2, n=4)
+    assert lib.c4m_workspace_bytes(ctypes.byref(bad), ctypes.byref(out)) == L.EINVAL
+    unstable = make_config(dim=2, n=64, cfl=0.70)
+    assert lib.c4m_workspace_bytes(ctypes.byref(unstable), ctypes.byref(out)) == L.EUNSTABLE
+    assert b"stability" in lib.c4m_last_error()
+    forced = make_config(dim=2, n=64, cfl=0.70, flags=L.FLAG_ALLOW_ANY_CFL)
+    assert lib.c4m_workspace_bytes(ctypes.byref(forced), ctypes.byref(out)) == L.OK
+    cfg3 = make_config(dim=3, n=32, cfl=0.5)
+    assert lib.c4m_workspace_bytes(ctypes.byref(cfg3), ctypes.byref(out)) == L.EUNSTABLE
+    # create rejects a misaligned or small workspace before any device call
+    h = ctypes.c_void_p()
+    assert lib.c4m_create(ctypes.byref(cfg), ctypes.c_void_p(16), 1 << 30, None, ctypes.byref(h)) == L.EINVAL
+    assert lib.c4m_create(ctypes.byref(cfg), ctypes.c_void_p(4096), 16, None, ctypes.byref(h)) == L.ENOMEM
+
+
+def test_status_strings():
+    L, lib = _lib()
+    for s in range(0, -8, -1):
+        assert lib.c4m_status_string(s)

@@ -1,0 +1,59 @@
+"""Parity of the gfx950 2D TM stepper (through the C ABI) with the CPU oracle.
+
+Tolerance: 1e-12 relative L2 over E and H (the FP64 bar), element-wise
+max error <= 1e-12 of the field scale.  The carried Laplacian is compared at
+1e-9 relative: the device stores G_E = alpha E + l/12 and recovers l as
+12 (G_E - alpha E), which cancels about log10(12 alpha |E| / |l|) digits.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import rel_l2, rel_l2_all, run_pair
+
+pytestmark = pytest.mark.gpu
+
+EH = ["ez", "hx", "hy"]
+
+
+def _check(gf, of, tol=1e-12, lap_tol=1e-9):
+    assert rel_l2_all(gf, of, EH) <= tol, {a: rel_l2(gf[a], of[a]) for a in EH}
+    scale = max(np.max(np.abs(of[a])) for a in EH)
+    for a in EH:
+        assert np.max(np.abs(gf[a] - of[a])) <= tol * scale * 10, a
+    if "lz" in gf:
+        assert rel_l2(gf["lz"], of["lz"]) <= lap_tol
+
+
+@pytest.mark.parametrize("closure", ["paper", "reflect"])
+@pytest.mark.parametrize("lap", ["tracked", "discrete"])
+@pytest.mark.parametrize("n", [8, 33, 96, 130])
+def test_mode_parity(closure, lap, n):
+    gf, of = run_pair(2, n, 0.5, 24, closure=closure, lap=lap, k=(3, 2))
+    _check(gf, of)
+
+
+@pytest.mark.parametrize("closure", ["paper", "reflect"])
+@pytest.mark.parametrize("lap", ["tracked", "discrete"])
+def test_random_data_parity(closure, lap):
+    # rough seeded data exercise every mode of the operators and every tile edge
+    gf, of = run_pair(2, 77, 0.45, 10, closure=closure, lap=lap, seed=1234)
+    _check(gf, of)
+
+
+def test_config1_cpu_oracle_size():
+    # 2D TM PEC unit-square cavity, N = 32, mode (1,1), CFL 0.5, T = 1 (64 steps)
+    gf, of = run_pair(2, 32, 0.5, 64, k=(1, 1))
+    _check(gf, of)
+
+
+def test_impedance_and_cfl_bound():
+    gf, of = run_pair(2, 40, 5 / (6 * np.sqrt(2)), 16, k=(2, 5), z=2.5)
+    _check(gf, of)
+
+
+@pytest.mark.parametrize("sweeps", [3, 8])
+def test_explicit_sweep_counts(sweeps):
+    # fewer sweeps leave a larger (bounded) solve error, more sweeps change nothing
+    gf, of = run_pair(2, 64, 0.5, 8, k=(4, 3), sweeps=sweeps)
+    tol = 1e-12 if sweeps >= 5 else 1e-7
+    assert rel_l2_all(gf, of, EH) <= tol
