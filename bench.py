@@ -1,0 +1,217 @@
+"""Throughput benchmark of the compact fourth-order Yee stepper on one MI355X.
+
+Default workload: 2D TM PEC unit-square cavity, N = 2048, mode (k, l) = (4, 3),
+CFL 0.5, FP64, PAPER closure with the carried Laplacian; one bench step is
+one time step (Step 1 + Step 2) of that problem, and the default K = 4096
+steps covers T = 1.  The fields are resident in HBM before the timed region.
+
+Prints ONE JSON line with the metric, the roofline block of the dominant
+kernel (per-kernel HIP-event timing on the problem's stream, in a profiled
+pass of the same steps right after the timed region) and the CPU baseline
+(the oracle on the host cores over a bounded sample of the same workload,
+also used as a full-size parity check of the device result).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2306_17263_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str, workload: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            data = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = data.get(workload, {}).get(kernel)
+    if not ent or ent.get("source_hash") != kernel_source_hash():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def exact_fields(n, k, tau_e, tau_h):
+    from workloads import mode_fields
+    return mode_fields(2, n, k, tau_e, tau_h)
+
+
+def rel_l2(a: dict, b: dict, names):
+    num = sum(float(np.sum((a[x] - b[x]) ** 2)) for x in names)
+    den = sum(float(np.sum(b[x] ** 2)) for x in names)
+    return float(np.sqrt(num / den))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None)
+    ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--n", type=int, default=2048)
+    ap.add_argument("--mode", type=str, default="4,3")
+    ap.add_argument("--cfl", type=float, default=0.5)
+    ap.add_argument("--closure", default="paper")
+    ap.add_argument("--lap", default="tracked")
+    ap.add_argument("--profile-steps", type=int, default=256)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(2)
+    from paper_2306_17263_amd import Problem
+    from paper_2306_17263_amd import _lib as L
+
+    n = args.n
+    k = tuple(int(v) for v in args.mode.split(","))
+    cfl = args.cfl
+    h = 1.0 / n
+    ht = cfl * h
+    steps = args.steps if args.steps is not None else int(round(1.0 / ht))
+    names = ["ez", "hx", "hy"]
+    init = exact_fields(n, k, 0.0, ht / 2)
+    kw = dict(closure=args.closure, lap_mode=args.lap)
+
+    prob = Problem(2, n, cfl, **kw)
+
+    def load_initial(p):
+        for name in p.fields():
+            p.set(name, init[name])
+
+    load_initial(prob)
+    prob.step(args.warmup)
+    torch.cuda.synchronize()
+    load_initial(prob)                         # timed run starts from the initial data
+    torch.cuda.synchronize()
+    stream = prob.stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    prob.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gpu_ms = ev0.elapsed_time(ev1)
+    elapsed = max(wall, gpu_ms / 1e3)
+    cells = n * n
+    value = cells * steps / elapsed / 1e6
+    got = {x: prob.get(x) for x in names}
+    ex = exact_fields(n, k, steps * ht, (steps + 0.5) * ht)
+    l2_exact = rel_l2(got, ex, names)
+    sweeps = prob.info()["sweeps"]
+    prob.close()
+
+    # ---- profiled pass: per-kernel durations from HIP events on the stream
+    pp = Problem(2, n, cfl, flags=L.FLAG_PROFILE, **kw)
+    load_initial(pp)
+    pp.step(args.profile_steps)
+    inf = pp.info()
+    pp.close()
+    per = {}
+    for ci, cname in enumerate(L.KERNEL_CLASSES):
+        cnt = inf["kernel_launches"][ci]
+        if cnt:
+            per[cname] = {"avg_us": 1e3 * inf["kernel_ms"][ci] / cnt, "launches": cnt,
+                          "alg_bytes": inf["kernel_alg_bytes"][ci]}
+    dom = max(per, key=lambda c: per[c]["avg_us"] * per[c]["launches"])
+    dom_ach = per[dom]["alg_bytes"] / (per[dom]["avg_us"] * 1e-6) / 1e9
+    workload_key = f"2d_n{n}_{args.closure}_{args.lap}"
+    traffic = measured_traffic(dom, workload_key)
+    roofline = {"bound": "hbm", "achieved": round(dom_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom_ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "avg_us": round(per[dom]["avg_us"], 3),
+                "step_alg_bytes_per_cell": sum(per[c]["alg_bytes"] for c in per) / cells,
+                "per_kernel_avg_us": {c: round(v["avg_us"], 3) for c, v in per.items()}}
+    step_alg = sum(per[c]["alg_bytes"] for c in per)
+    roofline["step_frac"] = round(step_alg * value * 1e6 / cells / 1e9 / HBM_PEAK_GBS, 4)
+
+    # ---- CPU baseline: the oracle on the host cores, bounded sample of the
+    # same workload; the device result after the same steps is compared.
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        o = oracle.OracleProblem(2, n, cfl, 1.0, closure=oracle.CLOSURE_PAPER if args.closure == "paper"
+                                 else oracle.CLOSURE_REFLECT,
+                                 lap_mode=oracle.LAP_TRACKED if args.lap == "tracked" else oracle.LAP_DISCRETE)
+        for name in o.fields():
+            o.set(name, init[name])
+        t1 = time.perf_counter()
+        done = 0
+        while True:
+            o.step(1)
+            done += 1
+            spent = time.perf_counter() - t1
+            if spent >= args.cpu_seconds or done >= steps:
+                break
+        cores = len(os.sched_getaffinity(0))
+        cpu = {"value": round(cells * done / spent / 1e6, 3), "unit": "Mcell-steps/s", "cores": cores,
+               "kind": "oracle",
+               "sample": f"{done} steps of the N={n} workload from the initial data ({spent:.1f} s, "
+                         f"OpenMP over lines, {cores} threads)"}
+        g = Problem(2, n, cfl, **kw)
+        load_initial(g)
+        g.step(done)
+        gf = {x: g.get(x) for x in names}
+        g.close()
+        of = {x: o.get(x) for x in names}
+        parity = {"steps": done, "rel_l2_vs_oracle": rel_l2(gf, of, names),
+                  "max_abs_vs_oracle": max(float(np.max(np.abs(gf[x] - of[x]))) for x in names)}
+
+    line = {
+        "metric": "Mcell-steps/s at fixed L2 error vs FP64 oracle + % HBM roofline",
+        "value": round(value, 2),
+        "unit": "Mcell-steps/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic (exact PEC cavity mode sampled on the Yee grids)",
+        "config": {"workload": f"2D TM PEC cavity N={n}, mode {k}, CFL {cfl}, T={steps * ht:g} "
+                               f"({steps} steps), {args.closure} closure, {args.lap} Laplacian, FP64",
+                   "n": n, "mode": list(k), "cfl": cfl, "closure": args.closure,
+                   "lap_mode": args.lap, "solver": f"chebyshev x{sweeps}"},
+        "l2_vs_exact": l2_exact,
+        "parity_sample": parity,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

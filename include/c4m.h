@@ -73,6 +73,18 @@ enum { C4M_SOLVER_CHEBYSHEV = 0, /* reduction-free Chebyshev on the closed-form 
 
 #define C4M_FLAG_ALLOW_ANY_CFL 0x1u   /* skip the CFL guard of create               */
 #define C4M_FLAG_CHECK_FINITE  0x2u   /* scan the fields for NaN/Inf after each call */
+#define C4M_FLAG_PROFILE       0x4u   /* time every kernel launch with HIP events on  *
+                                       * the problem's stream (see c4m_info)           */
+
+/* Kernel classes reported by the profiling counters of c4m_info. */
+enum { C4M_K_RHS_E = 0,      /* Pade curl of G(H): Step 1 right-hand side          */
+       C4M_K_SOLVE_E = 1,    /* compact solve + E (and G_E) update                 */
+       C4M_K_RHS_H = 2,      /* Pade curl of G_E: Step 2 right-hand side           */
+       C4M_K_SOLVE_H = 3,    /* compact solve + H update                           */
+       C4M_K_STEP_E = 4,     /* fused Step 1 (right-hand side, solve, update)      */
+       C4M_K_STEP_H = 5,     /* fused Step 2                                       */
+       C4M_K_OTHER = 6,      /* everything else (conversions, reductions)          */
+       C4M_K_COUNT = 8 };
 
 typedef struct {
     int32_t dim;        /* 2 = TM (Ez, Hx, Hy), 3 = full Maxwell                       */
@@ -103,6 +115,13 @@ typedef struct {
     int32_t nonfinite;        /* sticky: a NaN/Inf was seen                           */
     int32_t noconv;           /* sticky: a PCG solve hit max_iter                     */
     size_t workspace_bytes;   /* bytes of the caller's workspace in use               */
+    /* With C4M_FLAG_PROFILE: summed kernel time (ms) and launch count per
+     * C4M_K_* class since create (get_info synchronises the stream). */
+    double kernel_ms[C4M_K_COUNT];
+    int64_t kernel_launches[C4M_K_COUNT];
+    /* Algorithmic HBM bytes per launch of each class: the compulsory FP64
+     * state traffic of the scheme (temporaries excluded). */
+    double kernel_alg_bytes[C4M_K_COUNT];
 } c4m_info;
 
 typedef struct c4m_problem c4m_problem;

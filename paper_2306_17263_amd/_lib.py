@@ -15,6 +15,8 @@ PRECISION = {"fp64": 0, "fp32_refined": 1}
 SOLVER = {"chebyshev": 0, "pcg": 1}
 FLAG_ALLOW_ANY_CFL = 0x1
 FLAG_CHECK_FINITE = 0x2
+FLAG_PROFILE = 0x4
+KERNEL_CLASSES = ["rhs_e", "solve_e", "rhs_h", "solve_h", "step_e", "step_h", "other", "spare"]
 
 # every symbol include/c4m.h declares
 EXPORTS = [
@@ -41,6 +43,8 @@ class C4mInfo(ctypes.Structure):
         ("sweeps", ctypes.c_int32), ("last_iters", ctypes.c_int32), ("max_iters", ctypes.c_int32),
         ("last_rel_residual", ctypes.c_double), ("nonfinite", ctypes.c_int32),
         ("noconv", ctypes.c_int32), ("workspace_bytes", ctypes.c_size_t),
+        ("kernel_ms", ctypes.c_double * 8), ("kernel_launches", ctypes.c_int64 * 8),
+        ("kernel_alg_bytes", ctypes.c_double * 8),
     ]
 
 

@@ -13,13 +13,16 @@
 namespace c4m {
 
 // kernels (c4m_kernels_2d.hip, c4m_kernels_3d.hip, c4m_kernels_common.hip)
-hipError_t launch_e_half_2d(hipStream_t st, bool tracked, const double* hx, const double* hy,
-                            double* ez, double* ge, double* t0, double* t1, int N, int P,
-                            const Coef& cf, const PadeTaps& taps, const PadeLine& line_h2n,
-                            const ChebSchedule& cs);
-hipError_t launch_h_half_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy,
-                            double* t0, double* t1, int N, int P, const Coef& cf,
-                            const PadeTaps& taps, const PadeLine& line_n2h, const ChebSchedule& cs);
+hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const double* hy, double* t0,
+                           double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
+                           const PadeLine& line_h2n);
+hipError_t launch_solve_e_2d(hipStream_t st, bool tracked, double* ez, double* ge, const double* t0,
+                             const double* t1, int N, int P, const Coef& cf, const ChebSchedule& cs);
+hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, double* t0, double* t1,
+                           int N, int P, const Coef& cf, const PadeTaps& taps,
+                           const PadeLine& line_n2h);
+hipError_t launch_solve_h_2d(hipStream_t st, double* hx, double* hy, const double* t0,
+                             const double* t1, int N, int P, const Coef& cf, const ChebSchedule& cs);
 hipError_t launch_zero_walls(hipStream_t st, double* a, const Box& bx, int P, size_t plane);
 hipError_t launch_lap_convert(hipStream_t st, double* a, const double* e, double* out, const Box& bx,
                               int P, size_t plane, double alpha, int mode);
@@ -219,6 +222,15 @@ struct c4m_problem {
     int64_t steps = 0;
     int nonfinite = 0;
     bool owned_by_batch = false;
+    // profiling (C4M_FLAG_PROFILE): event pairs not yet read, and the sums
+    struct Rec {
+        int cls;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> pending;
+    double kernel_ms[C4M_K_COUNT] = {};
+    int64_t kernel_launches[C4M_K_COUNT] = {};
+    double alg_bytes[C4M_K_COUNT] = {};
 };
 
 namespace {
@@ -347,23 +359,94 @@ c4m_status copy_field(c4m_problem* p, double* dev, const Box& bx, const double* 
     return C4M_OK;
 }
 
+c4m_status flush_profile(c4m_problem* p)
+{
+    if (p->pending.empty()) return C4M_OK;
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (auto& r : p->pending) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            p->kernel_ms[r.cls] += ms;
+            p->kernel_launches[r.cls] += 1;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    p->pending.clear();
+    return C4M_OK;
+}
+
+// Run one launch; with profiling on, bracket it by events on the stream.
+template <class F>
+c4m_status timed(c4m_problem* p, int cls, const char* what, F&& launch)
+{
+    const bool prof = (p->cfg.flags & C4M_FLAG_PROFILE) != 0;
+    c4m_problem::Rec r{cls, nullptr, nullptr};
+    if (prof) {
+        if (p->pending.size() >= 4096) {
+            c4m_status s = flush_profile(p);
+            if (s != C4M_OK) return s;
+        }
+        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess)
+            return fail(C4M_EDEVICE, "hipEventCreate");
+        if (hipEventRecord(r.a, p->stream) != hipSuccess) return fail(C4M_EDEVICE, "hipEventRecord");
+    }
+    hipError_t e = launch();
+    if (e != hipSuccess) return hip_fail(e, what);
+    if (prof) {
+        if (hipEventRecord(r.b, p->stream) != hipSuccess) return fail(C4M_EDEVICE, "hipEventRecord");
+        p->pending.push_back(r);
+    }
+    return C4M_OK;
+}
+
 c4m_status step_once(c4m_problem* p)
 {
     const int N = p->N, P = p->P;
     const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
-    hipError_t e;
     if (p->dim == 2) {
-        e = launch_e_half_2d(p->stream, tracked, p->f[C4M_HX], p->f[C4M_HY], p->f[C4M_EZ], p->ge[2],
-                             p->tmp[0], p->tmp[1], N, P, p->coef, p->pade_host[1].taps, p->line[1],
-                             p->cheb);
-        if (e != hipSuccess) return hip_fail(e, "E half-step");
-        e = launch_h_half_2d(p->stream, tracked, tracked ? p->ge[2] : p->f[C4M_EZ], p->f[C4M_HX],
-                             p->f[C4M_HY], p->tmp[0], p->tmp[1], N, P, p->coef,
-                             p->pade_host[0].taps, p->line[0], p->cheb);
-        if (e != hipSuccess) return hip_fail(e, "H half-step");
-        return C4M_OK;
+        double *hx = p->f[C4M_HX], *hy = p->f[C4M_HY], *ez = p->f[C4M_EZ], *ge = p->ge[2];
+        double *t0 = p->tmp[0], *t1 = p->tmp[1];
+        c4m_status s = timed(p, C4M_K_RHS_E, "rhs E", [&] {
+            return launch_rhs_e_2d(p->stream, tracked, hx, hy, t0, t1, N, P, p->coef,
+                                   p->pade_host[1].taps, p->line[1]);
+        });
+        if (s == C4M_OK)
+            s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
+                return launch_solve_e_2d(p->stream, tracked, ez, ge, t0, t1, N, P, p->coef, p->cheb);
+            });
+        if (s == C4M_OK)
+            s = timed(p, C4M_K_RHS_H, "rhs H", [&] {
+                return launch_rhs_h_2d(p->stream, tracked, tracked ? ge : ez, t0, t1, N, P, p->coef,
+                                       p->pade_host[0].taps, p->line[0]);
+            });
+        if (s == C4M_OK)
+            s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
+                return launch_solve_h_2d(p->stream, hx, hy, t0, t1, N, P, p->coef, p->cheb);
+            });
+        return s;
     }
     return fail(C4M_EINVAL, "3D stepping not supported by this build");
+}
+
+// Compulsory FP64 state bytes per launch of each kernel class (temporaries
+// excluded): each half-step reads its source field and reads and writes its
+// target field (and G_E with the carried Laplacian).
+void set_alg_bytes(c4m_problem* p)
+{
+    const double cells = p->dim == 2 ? (double)p->N * p->N : (double)p->N * p->N * p->N;
+    const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+    const double w = 8.0;
+    const int nc = p->dim == 2 ? 1 : 3;          // E components
+    const int nh = p->dim == 2 ? 2 : 3;          // H components
+    const int srcs_e = p->dim == 2 ? 2 : 3;      // H arrays read by the E half-step
+    p->alg_bytes[C4M_K_RHS_E] = w * cells * srcs_e;
+    p->alg_bytes[C4M_K_SOLVE_E] = w * cells * nc * (tracked ? 4 : 2);
+    p->alg_bytes[C4M_K_RHS_H] = w * cells * nc;
+    p->alg_bytes[C4M_K_SOLVE_H] = w * cells * nh * 2;
+    p->alg_bytes[C4M_K_STEP_E] = p->alg_bytes[C4M_K_RHS_E] + p->alg_bytes[C4M_K_SOLVE_E];
+    p->alg_bytes[C4M_K_STEP_H] = p->alg_bytes[C4M_K_RHS_H] + p->alg_bytes[C4M_K_SOLVE_H];
 }
 
 }  // namespace
@@ -460,6 +543,7 @@ c4m_status c4m_create(const c4m_config* cfg, void* d_workspace, size_t bytes, vo
     p->coef.ge_gain = 1.0 + 4.0 / (r * r);
     p->coef.ge_curl = 2.0 / r * cfg->z;
     p->cheb = chebyshev(p->coef.alpha, p->coef.beta, cfg->sweeps, 1e-16);
+    set_alg_bytes(p);
 
     for (int k = 0; k < 2; ++k) {
         const int n_in = k == 0 ? p->N + 1 : p->N;
@@ -589,6 +673,13 @@ c4m_status c4m_get_info(c4m_problem* p, c4m_info* info)
     info->sweeps = p->cheb.sweeps;
     info->nonfinite = p->nonfinite;
     info->workspace_bytes = p->used;
+    c4m_status s = flush_profile(p);
+    if (s != C4M_OK) return s;
+    for (int k = 0; k < C4M_K_COUNT; ++k) {
+        info->kernel_ms[k] = p->kernel_ms[k];
+        info->kernel_launches[k] = p->kernel_launches[k];
+        info->kernel_alg_bytes[k] = p->alg_bytes[k];
+    }
     return C4M_OK;
 }
 
@@ -596,6 +687,7 @@ c4m_status c4m_destroy(c4m_problem* p)
 {
     if (!p) return fail(C4M_EINVAL, "null problem");
     if (p->owned_by_batch) return fail(C4M_ESTATE, "problem belongs to a batch");
+    (void)flush_profile(p);
     delete p;
     return C4M_OK;
 }

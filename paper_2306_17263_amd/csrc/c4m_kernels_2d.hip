@@ -370,10 +370,9 @@ static hipError_t launch_cheb_k(int K, dim3 grid, hipStream_t st, ChebIO io0, Ch
     return hipGetLastError();
 }
 
-hipError_t launch_e_half_2d(hipStream_t st, bool tracked, const double* hx, const double* hy,
-                            double* ez, double* ge, double* t0, double* t1, int N, int P,
-                            const Coef& cf, const PadeTaps& taps, const PadeLine& line_h2n,
-                            const ChebSchedule& cs)
+hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const double* hy, double* t0,
+                           double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
+                           const PadeLine& line_h2n)
 {
     dim3 grid((N - 1 + T2X - 1) / T2X, (N - 1 + T2Y - 1) / T2Y);
     if (tracked)
@@ -382,16 +381,21 @@ hipError_t launch_e_half_2d(hipStream_t st, bool tracked, const double* hx, cons
     else
         hipLaunchKernelGGL(k_rhs_e2d<false>, grid, dim3(NT2), 0, st, hx, hy, t0, t1, N, P, cf, taps,
                            line_h2n);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_e_2d(hipStream_t st, bool tracked, double* ez, double* ge, const double* t0,
+                             const double* t1, int N, int P, const Coef& cf, const ChebSchedule& cs)
+{
+    dim3 grid((N - 1 + T2X - 1) / T2X, (N - 1 + T2Y - 1) / T2Y);
     ChebIO io{t0, ez, UGrid{{1, 1, 0}, {N, N, 1}, {0, 0, 0}}};
     if (tracked) return launch_cheb_k<0>(cs.sweeps, grid, st, io, io, ge, t1, P, cf, cs);
     return launch_cheb_k<1>(cs.sweeps, grid, st, io, io, nullptr, nullptr, P, cf, cs);
 }
 
-hipError_t launch_h_half_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy,
-                            double* t0, double* t1, int N, int P, const Coef& cf,
-                            const PadeTaps& taps, const PadeLine& line_n2h, const ChebSchedule& cs)
+hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, double* t0, double* t1,
+                           int N, int P, const Coef& cf, const PadeTaps& taps,
+                           const PadeLine& line_n2h)
 {
     dim3 grid((N + T2X - 1) / T2X, (N + T2Y - 1) / T2Y, 2);
     if (tracked)
@@ -400,8 +404,13 @@ hipError_t launch_h_half_2d(hipStream_t st, bool tracked, const double* src, dou
     else
         hipLaunchKernelGGL(k_rhs_h2d<false>, grid, dim3(NT2), 0, st, src, t0, t1, N, P, cf, taps,
                            line_n2h);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+hipError_t launch_solve_h_2d(hipStream_t st, double* hx, double* hy, const double* t0,
+                             const double* t1, int N, int P, const Coef& cf, const ChebSchedule& cs)
+{
+    dim3 grid((N + T2X - 1) / T2X, (N + T2Y - 1) / T2Y, 2);
     // Hx: Dirichlet in x (nodes 1..N-1), Neumann in y (half points 0..N-1)
     ChebIO iox{t0, hx, UGrid{{1, 0, 0}, {N, N, 1}, {0, 1, 0}}};
     // Hy: Neumann in x, Dirichlet in y

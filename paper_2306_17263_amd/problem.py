@@ -105,7 +105,11 @@ class Problem:
     def info(self) -> dict:
         inf = L.C4mInfo()
         L.check(self._lib.c4m_get_info(self._h, ctypes.byref(inf)), "c4m_get_info")
-        return {f: getattr(inf, f) for f, _ in L.C4mInfo._fields_}
+        out = {}
+        for f, _ in L.C4mInfo._fields_:
+            v = getattr(inf, f)
+            out[f] = list(v) if hasattr(v, "__len__") else v
+        return out
 
     def fields(self):
         names = ["ez", "hx", "hy"] if self.dim == 2 else ["ex", "ey", "ez", "hx", "hy", "hz"]
