@@ -74,7 +74,8 @@ enum { C4M_SOLVER_CHEBYSHEV = 0, /* reduction-free Chebyshev on the closed-form 
 #define C4M_FLAG_ALLOW_ANY_CFL 0x1u   /* skip the CFL guard of create               */
 #define C4M_FLAG_CHECK_FINITE  0x2u   /* scan the fields for NaN/Inf after each call */
 #define C4M_FLAG_PROFILE       0x4u   /* time every kernel launch with HIP events on  *
-                                       * the problem's stream (see c4m_info)           */
+                                       * the problem's stream, waiting for each launch *
+                                       * before queuing the next (see c4m_info)        */
 
 /* Kernel classes reported by the profiling counters of c4m_info. */
 enum { C4M_K_RHS_E = 0,      /* Pade curl of G(H): Step 1 right-hand side          */

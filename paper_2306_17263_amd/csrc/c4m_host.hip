@@ -16,13 +16,15 @@ namespace c4m {
 hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const double* hy, double* t0,
                            double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                            const PadeLine& line_h2n);
-hipError_t launch_solve_e_2d(hipStream_t st, bool tracked, double* ez, double* ge, const double* t0,
-                             const double* t1, int N, int P, const Coef& cf, const ChebSchedule& cs);
+hipError_t launch_solve_e_2d(hipStream_t st, bool tracked, const double* hx, double* ez, double* ge,
+                             const double* t0, const double* t1, int N, int P, const Coef& cf,
+                             const PadeTaps& taps, const PadeLine& line_h2n, const ChebSchedule& cs);
 hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, double* t0, double* t1,
                            int N, int P, const Coef& cf, const PadeTaps& taps,
                            const PadeLine& line_n2h);
-hipError_t launch_solve_h_2d(hipStream_t st, double* hx, double* hy, const double* t0,
-                             const double* t1, int N, int P, const Coef& cf, const ChebSchedule& cs);
+hipError_t launch_solve_h_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy,
+                             const double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
+                             const PadeLine& line_n2h, const ChebSchedule& cs);
 hipError_t launch_zero_walls(hipStream_t st, double* a, const Box& bx, int P, size_t plane);
 hipError_t launch_lap_convert(hipStream_t st, double* a, const double* e, double* out, const Box& bx,
                               int P, size_t plane, double alpha, int mode);
@@ -395,7 +397,10 @@ c4m_status timed(c4m_problem* p, int cls, const char* what, F&& launch)
     hipError_t e = launch();
     if (e != hipSuccess) return hip_fail(e, what);
     if (prof) {
+        // Wait for the launch to finish before the next one is queued, so
+        // the event pair brackets this kernel alone.
         if (hipEventRecord(r.b, p->stream) != hipSuccess) return fail(C4M_EDEVICE, "hipEventRecord");
+        if (hipEventSynchronize(r.b) != hipSuccess) return fail(C4M_EDEVICE, "hipEventSynchronize");
         p->pending.push_back(r);
     }
     return C4M_OK;
@@ -414,7 +419,8 @@ c4m_status step_once(c4m_problem* p)
         });
         if (s == C4M_OK)
             s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
-                return launch_solve_e_2d(p->stream, tracked, ez, ge, t0, t1, N, P, p->coef, p->cheb);
+                return launch_solve_e_2d(p->stream, tracked, hx, ez, ge, t0, t1, N, P, p->coef,
+                                         p->pade_host[1].taps, p->line[1], p->cheb);
             });
         if (s == C4M_OK)
             s = timed(p, C4M_K_RHS_H, "rhs H", [&] {
@@ -423,7 +429,8 @@ c4m_status step_once(c4m_problem* p)
             });
         if (s == C4M_OK)
             s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
-                return launch_solve_h_2d(p->stream, hx, hy, t0, t1, N, P, p->coef, p->cheb);
+                return launch_solve_h_2d(p->stream, tracked, tracked ? ge : ez, hx, hy, t1, N, P,
+                                         p->coef, p->pade_host[0].taps, p->line[0], p->cheb);
             });
         return s;
     }
@@ -435,15 +442,17 @@ c4m_status step_once(c4m_problem* p)
 // target field (and G_E with the carried Laplacian).
 void set_alg_bytes(c4m_problem* p)
 {
+    // 2D: the x-line kernel of Step 1 reads Hy, its column kernel reads Hx
+    // and updates Ez (and G_E); the x-line kernel of Step 2 reads G_E (or
+    // Ez), its column kernels update Hx and Hy.
     const double cells = p->dim == 2 ? (double)p->N * p->N : (double)p->N * p->N * p->N;
     const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
     const double w = 8.0;
-    const int nc = p->dim == 2 ? 1 : 3;          // E components
+    const int ne = p->dim == 2 ? 1 : 3;          // E components
     const int nh = p->dim == 2 ? 2 : 3;          // H components
-    const int srcs_e = p->dim == 2 ? 2 : 3;      // H arrays read by the E half-step
-    p->alg_bytes[C4M_K_RHS_E] = w * cells * srcs_e;
-    p->alg_bytes[C4M_K_SOLVE_E] = w * cells * nc * (tracked ? 4 : 2);
-    p->alg_bytes[C4M_K_RHS_H] = w * cells * nc;
+    p->alg_bytes[C4M_K_RHS_E] = w * cells * (nh - 1);
+    p->alg_bytes[C4M_K_SOLVE_E] = w * cells * (1 + ne * (tracked ? 4 : 2));
+    p->alg_bytes[C4M_K_RHS_H] = w * cells * ne;
     p->alg_bytes[C4M_K_SOLVE_H] = w * cells * nh * 2;
     p->alg_bytes[C4M_K_STEP_E] = p->alg_bytes[C4M_K_RHS_E] + p->alg_bytes[C4M_K_SOLVE_E];
     p->alg_bytes[C4M_K_STEP_H] = p->alg_bytes[C4M_K_RHS_H] + p->alg_bytes[C4M_K_SOLVE_H];

@@ -1,27 +1,30 @@
 // c4m_kernels_2d.hip -- gfx950 kernels of the 2D TM (Ez, Hx, Hy) step.
 //
-// One step is four launches:
-//   k_rhs_e2d   : b = Z curl^A G(H) at the interior Ez nodes (and, with the
-//                 carried Laplacian, c = curl^A H), Step 1 of Section 3.4;
-//   k_cheb_2d   : Phi = M^{-1} b by Chebyshev on the closed-form spectral
-//                 bounds of M, then Ez += r Phi and G_E += (1+4/r^2) r Phi - (2/r) Z c;
-//   k_rhs_h2d   : b_x = -(1/Z) delta_y G_E, b_y = (1/Z) delta_x G_E, Step 2;
-//   k_cheb_2d   : Phi = M^{-1} b per H component, H += r Phi.
-// G_E = alpha E + l/12 is stored instead of l (the carried Laplacian), so the
-// H half-step reads only G_E and H.
+// Step 1 (Section 3.4), two launches:
+//   k_xlines<E>  : rows of Hy -> T0 = Z delta_x G(Hy), T1 = delta_x Hy (carried l)
+//   k_col<E>     : per column of Hx the y-line Pade (streaming FIR in
+//                  registers) completes b = T0 - Z delta_y G(Hx); then the
+//                  Chebyshev solve of M Phi = b on the tile and its halo,
+//                  Ez += r Phi, G_E += (1 + 4/r^2) r Phi - (2/r) Z curl^A H.
+// Step 2, three launches:
+//   k_xlines<H>  : rows of G_E -> T1 = (1/Z) delta_x G_E        (Hy right-hand side)
+//   k_col<HX>    : columns of G_E -> b = -(1/Z) delta_y G_E, solve, Hx += r Phi
+//   k_col<HY>    : b = T1, solve, Hy += r Phi
+// G_E = alpha E + l/12 is stored instead of l, so Step 2 reads only G_E.
 //
-// Tiles are 64 (x) x 16 (y) outputs per 256-thread workgroup; wave w of a
-// workgroup owns rows w, w+4, w+8, w+12 of the tile and lane l column l, so
-// every global access of a wave is one contiguous 512-byte row segment.
+// Pade derivative: A^{-1} D truncated to 2 PADE_R + 2 taps on the line
+// values (exact rows near the two ends of each line from a table).
+// Source conditioning G u = alpha u + (L5 u)/12 is split by axis: the part
+// along the line is folded into the line input, the part across the line is
+// applied to the line derivatives of the neighbouring lines (the line
+// derivative is the same linear map on every line, so the two commute).
+//
+// k_col layout: one lane per column of a 256-column region, each lane holds
+// the region rows of its column in registers; only the column sums
+// S = d(y-1) + 4 d(y) + d(y+1) of the 9-point stencil cross lanes (LDS).
 #include "c4m_internal.h"
 
 namespace c4m {
-
-constexpr int T2X = 64;
-constexpr int T2Y = 16;
-constexpr int NT2 = 256;
-constexpr int RG = NT2 / T2X;            // row groups per workgroup
-constexpr int ROWS_PER_THREAD = T2Y / RG;
 
 __device__ __forceinline__ const double* pade_row(const PadeLine& L, int m)
 {
@@ -31,338 +34,415 @@ __device__ __forceinline__ const double* pade_row(const PadeLine& L, int m)
     return nullptr;
 }
 
-// Truncated A^{-1} D applied to an LDS window: s[u * st] holds the line value
-// at input index m - PADE_R + u.
-__device__ __forceinline__ double fir_taps(const PadeTaps& t, const double* s, int st)
+__device__ __forceinline__ bool pade_interior(const PadeLine& L, int m_lo, int m_hi)
 {
-    double acc = 0.0;
-#pragma unroll
-    for (int u = 0; u < PADE_TAPS; ++u) acc = fma(t.c[u], s[u * st], acc);
-    return acc;
+    // every output in [m_lo, m_hi] uses the interior taps
+    return !L.all && m_lo >= L.b && m_hi < L.n_out - L.b;
 }
 
-__device__ __forceinline__ double fir_row(const double* __restrict__ row, const double* s, int st)
-{
-    double acc = 0.0;
-#pragma unroll
-    for (int u = 0; u < PADE_TAPS; ++u) acc = fma(row[u], s[u * st], acc);
-    return acc;
-}
+// ===========================================================================
+// x-lines.  Tile: 32 rows x 64 outputs, 256 threads; thread (row = t % 32,
+// seg = t / 32) computes 8 consecutive outputs from a 33-value register
+// window.  Lanes 0..15 and 16..31 of a wave read 16 consecutive rows at the
+// same column, and the odd LDS row stride keeps those reads conflict-free.
+// ===========================================================================
+constexpr int XT_ROWS = 32;
+constexpr int XT_OUT = 64;
+constexpr int XT_SEG = 8;
+constexpr int XT_IN = XT_OUT + 2 * PADE_R + 2;     // staged inputs per row
+constexpr int XT_STRIDE = XT_IN + 1;               // odd
+constexpr int XT_WIN = XT_SEG + PADE_TAPS - 1;
 
-__device__ __forceinline__ double fir_any(const PadeLine& L, const PadeTaps& t, int m, const double* s,
-                                          int st)
-{
-    const double* row = pade_row(L, m);
-    return row ? fir_row(row, s, st) : fir_taps(t, s, st);
-}
+enum { XL_E_TRACKED = 0, XL_E_DISCRETE = 1, XL_H_TRACKED = 2, XL_H_DISCRETE = 3 };
 
-constexpr int XW = T2X + 2 * PADE_R + 2;     // staged width of an x-line window
-constexpr int YH = T2Y + 2 * PADE_R + 2;     // staged height of a y-line window
-constexpr int STAGE = (T2Y * XW > YH * T2X) ? T2Y * XW : YH * T2X;
-
-// ---------------------------------------------------------------------------
-// Step 1 right-hand side.  Output nodes i, j in [1, N-1].
-// x part: delta_x of G(Hy) along rows j (Hy at half points 0..N-1 in x,
-//         even ghosts at both ends), N-1 outputs at the interior nodes.
-// y part: delta_y of G(Hx) along columns i (Hx at half points in y).
-// G u = alpha u + (u_W + u_E + u_S + u_N - 4 u)/12 with the same ghosts along
-// the half axis and the stored wall values along the node axis.
-// ---------------------------------------------------------------------------
-template <bool TRACKED>
-__global__ __launch_bounds__(NT2) void k_rhs_e2d(const double* __restrict__ hx,
-                                                  const double* __restrict__ hy,
-                                                  double* __restrict__ b, double* __restrict__ c,
-                                                  int N, int P, Coef cf, PadeTaps taps, PadeLine L)
+template <int MODE>
+__global__ __launch_bounds__(256) void k_xlines(const double* __restrict__ src, double* __restrict__ t0,
+                                                double* __restrict__ t1, int N, int P, Coef cf,
+                                                PadeTaps taps, PadeLine L)
 {
-    __shared__ double sg[STAGE];
-    __shared__ double sh[TRACKED ? STAGE : 1];
+    constexpr bool E = MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE;
+    constexpr bool TWO = MODE == XL_E_TRACKED;     // raw derivative as well
+    __shared__ double sg[XT_ROWS * XT_STRIDE];
+    __shared__ double sr[TWO ? XT_ROWS * XT_STRIDE : 1];
     const int tid = threadIdx.x;
-    const int col = tid % T2X;
-    const int rg = tid / T2X;
-    const int i0 = 1 + blockIdx.x * T2X;
-    const int j0 = 1 + blockIdx.y * T2Y;
-    const int nout = N - 1;
-    double accb[ROWS_PER_THREAD], accc[ROWS_PER_THREAD];
-
-    // ---- x part ----
-    const int mx0 = i0 - 1;
-    for (int e = tid; e < T2Y * XW; e += NT2) {
-        const int rr = e / XW, q = e - rr * XW;
-        const int j = j0 + rr, g = mx0 - PADE_R + q;
-        double vh = 0.0, vg = 0.0;
-        if (j <= N - 1 && g >= 0 && g < N) {
-            const double* row = hy + (size_t)j * P;
-            const double h0 = row[g];
-            const double hl = row[g > 0 ? g - 1 : 0];
-            const double hr = row[g < N - 1 ? g + 1 : N - 1];
-            const double hs = hy[(size_t)(j - 1) * P + g];
-            const double hn = hy[(size_t)(j + 1) * P + g];
-            vh = h0;
-            vg = fma(cf.alpha, h0, (hl + hr + hs + hn - 4.0 * h0) * (1.0 / 12.0));
-        }
-        sg[e] = vg;
-        if (TRACKED) sh[e] = vh;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int t = 0; t < ROWS_PER_THREAD; ++t) {
-        const int rr = rg + RG * t;
-        const int m = mx0 + col;
-        double vb = 0.0, vc = 0.0;
-        if (m < nout) {
-            const double* row = pade_row(L, m);
-            if (row) {
-                vb = fir_row(row, sg + rr * XW + col, 1);
-                if (TRACKED) vc = fir_row(row, sh + rr * XW + col, 1);
+    const int m0 = blockIdx.x * XT_OUT;             // first output of the tile
+    const int j0 = 1 + blockIdx.y * XT_ROWS;        // first row (interior rows 1..N-1)
+    const int n_in = L.n_in;
+    // ---- stage the conditioned line input (and the raw one)
+    for (int e = tid; e < XT_ROWS * XT_IN; e += 256) {
+        const int rr = e / XT_IN, q = e - rr * XT_IN;
+        const int j = j0 + rr, g = m0 - PADE_R + q;
+        double vg = 0.0, vr = 0.0;
+        if (j <= N - 1 && g >= 0 && g < n_in) {
+            const double* row = src + (size_t)j * P;
+            if (E) {
+                // Hy at half points along x: even ghosts at both ends
+                const double h0 = row[g];
+                const double hl = row[g > 0 ? g - 1 : 0];
+                const double hr = row[g < n_in - 1 ? g + 1 : n_in - 1];
+                const double hs = row[g - P];
+                const double hn = row[g + P];
+                vr = h0;
+                vg = fma(cf.alpha, h0, (hl + hr + hs + hn - 4.0 * h0) * (1.0 / 12.0));
+            } else if (MODE == XL_H_TRACKED) {
+                vg = row[g];                                       // stored G_E
             } else {
-                vb = fir_taps(taps, sg + rr * XW + col, 1);
-                if (TRACKED) vc = fir_taps(taps, sh + rr * XW + col, 1);
+                // alpha E + L5 E / 12, zero on the walls (nodes 0 and N)
+                if (g > 0 && g < n_in - 1) {
+                    const double e0 = row[g];
+                    vg = fma(cf.alpha, e0, (row[g - 1] + row[g + 1] + row[g - P] + row[g + P] - 4.0 * e0) *
+                                               (1.0 / 12.0));
+                }
             }
         }
-        accb[t] = vb;
-        accc[t] = vc;
+        sg[rr * XT_STRIDE + q] = vg;
+        if (TWO) sr[rr * XT_STRIDE + q] = vr;
     }
     __syncthreads();
-
-    // ---- y part ----
-    const int my0 = j0 - 1;
-    for (int e = tid; e < YH * T2X; e += NT2) {
-        const int q = e / T2X, cc = e - q * T2X;
-        const int i = i0 + cc, g = my0 - PADE_R + q;
-        double vh = 0.0, vg = 0.0;
-        if (i <= N - 1 && g >= 0 && g < N) {
-            const double h0 = hx[(size_t)g * P + i];
-            const double hs = hx[(size_t)(g > 0 ? g - 1 : 0) * P + i];
-            const double hn = hx[(size_t)(g < N - 1 ? g + 1 : N - 1) * P + i];
-            const double hl = hx[(size_t)g * P + i - 1];
-            const double hr = hx[(size_t)g * P + i + 1];
-            vh = h0;
-            vg = fma(cf.alpha, h0, (hl + hr + hs + hn - 4.0 * h0) * (1.0 / 12.0));
-        }
-        sg[e] = vg;
-        if (TRACKED) sh[e] = vh;
-    }
-    __syncthreads();
+    const int row = tid % XT_ROWS;
+    const int seg = tid / XT_ROWS;
+    const int mb = m0 + seg * XT_SEG;
+    double outg[XT_SEG], outr[XT_SEG];
+    const double* wg = sg + row * XT_STRIDE + seg * XT_SEG;
+    const double* wr = sr + row * XT_STRIDE + seg * XT_SEG;
+    if (pade_interior(L, mb, mb + XT_SEG - 1)) {
+        double w[XT_WIN];
 #pragma unroll
-    for (int t = 0; t < ROWS_PER_THREAD; ++t) {
-        const int rr = rg + RG * t;
-        const int m = my0 + rr;
-        const int j = j0 + rr, i = i0 + col;
-        if (m < nout) {
-            const double vy = fir_any(L, taps, m, sg + rr * T2X + col, T2X);
-            const double vyh = TRACKED ? fir_any(L, taps, m, sh + rr * T2X + col, T2X) : 0.0;
-            if (j <= N - 1 && i <= N - 1) {
-                b[(size_t)j * P + i] = cf.z * (accb[t] - vy);
-                if (TRACKED) c[(size_t)j * P + i] = accc[t] - vyh;
-            }
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Step 2 right-hand sides from G_E (stored, or alpha E + L5 E / 12 in the
-// DISCRETE variant; zero on the walls either way).
-// z = 0: b_x(j, i) = -(1/Z) delta_y G_E along column i, i in [1, N-1], j in [0, N-1].
-// z = 1: b_y(j, i) = +(1/Z) delta_x G_E along row j,    j in [1, N-1], i in [0, N-1].
-// ---------------------------------------------------------------------------
-template <bool TRACKED>
-__device__ __forceinline__ double ge_value(const double* __restrict__ src, int j, int i, int N, int P,
-                                           double alpha)
-{
-    if (TRACKED) return src[(size_t)j * P + i];
-    if (i == 0 || i == N || j == 0 || j == N) return 0.0;
-    const double* p = src + (size_t)j * P + i;
-    const double e0 = p[0];
-    return fma(alpha, e0, (p[-1] + p[1] + p[-P] + p[P] - 4.0 * e0) * (1.0 / 12.0));
-}
-
-template <bool TRACKED>
-__global__ __launch_bounds__(NT2) void k_rhs_h2d(const double* __restrict__ src,
-                                                  double* __restrict__ bx, double* __restrict__ by,
-                                                  int N, int P, Coef cf, PadeTaps taps, PadeLine L)
-{
-    __shared__ double sg[STAGE];
-    const int tid = threadIdx.x;
-    const int col = tid % T2X;
-    const int rg = tid / T2X;
-    const double zinv = 1.0 / cf.z;
-    const int nout = N;                      // node -> half lines: N+1 inputs, N outputs
-    if (blockIdx.z == 0) {
-        const int i0 = 1 + blockIdx.x * T2X;
-        const int m0 = blockIdx.y * T2Y;
-        if (i0 > N - 1 || m0 > N - 1) return;
-        for (int e = tid; e < YH * T2X; e += NT2) {
-            const int q = e / T2X, cc = e - q * T2X;
-            const int i = i0 + cc, g = m0 - PADE_R + q;
-            double v = 0.0;
-            if (i <= N - 1 && g >= 0 && g <= N) v = ge_value<TRACKED>(src, g, i, N, P, cf.alpha);
-            sg[e] = v;
-        }
-        __syncthreads();
+        for (int u = 0; u < XT_WIN; ++u) w[u] = wg[u];
 #pragma unroll
-        for (int t = 0; t < ROWS_PER_THREAD; ++t) {
-            const int rr = rg + RG * t;
-            const int m = m0 + rr, i = i0 + col;
-            if (m < nout) {
-                const double v = fir_any(L, taps, m, sg + rr * T2X + col, T2X);
-                if (i <= N - 1) bx[(size_t)m * P + i] = -zinv * v;
+        for (int k = 0; k < XT_SEG; ++k) {
+            double a = 0.0;
+#pragma unroll
+            for (int u = 0; u < PADE_TAPS; ++u) a = fma(taps.c[u], w[k + u], a);
+            outg[k] = a;
+        }
+        if (TWO) {
+#pragma unroll
+            for (int u = 0; u < XT_WIN; ++u) w[u] = wr[u];
+#pragma unroll
+            for (int k = 0; k < XT_SEG; ++k) {
+                double a = 0.0;
+#pragma unroll
+                for (int u = 0; u < PADE_TAPS; ++u) a = fma(taps.c[u], w[k + u], a);
+                outr[k] = a;
             }
         }
     } else {
-        const int m0 = blockIdx.x * T2X;
-        const int j0 = 1 + blockIdx.y * T2Y;
-        if (m0 > N - 1 || j0 > N - 1) return;
-        for (int e = tid; e < T2Y * XW; e += NT2) {
-            const int rr = e / XW, q = e - rr * XW;
-            const int j = j0 + rr, g = m0 - PADE_R + q;
-            double v = 0.0;
-            if (j <= N - 1 && g >= 0 && g <= N) v = ge_value<TRACKED>(src, j, g, N, P, cf.alpha);
-            sg[e] = v;
-        }
-        __syncthreads();
 #pragma unroll
-        for (int t = 0; t < ROWS_PER_THREAD; ++t) {
-            const int rr = rg + RG * t;
-            const int m = m0 + col, j = j0 + rr;
-            if (m < nout) {
-                const double v = fir_any(L, taps, m, sg + rr * XW + col, 1);
-                if (j <= N - 1) by[(size_t)j * P + m] = zinv * v;
+        for (int k = 0; k < XT_SEG; ++k) {
+            const int m = mb + k;
+            double a = 0.0, b = 0.0;
+            if (m < L.n_out) {
+                const double* cr = pade_row(L, m);
+                for (int u = 0; u < PADE_TAPS; ++u) {
+                    const double c = cr ? cr[u] : taps.c[u];
+                    a = fma(c, wg[k + u], a);
+                    if (TWO) b = fma(c, wr[k + u], b);
+                }
             }
+            outg[k] = a;
+            outr[k] = b;
+        }
+    }
+    // ---- write through the LDS so that a wave stores contiguous row segments:
+    // E step -> node i = m + 1; H step -> half point i = m
+    __syncthreads();
+    constexpr int OS = XT_OUT + 1;
+    double* og = sg;                        // [XT_ROWS][OS], reuses the staging area
+    double* orw = TWO ? sr : sg;
+#pragma unroll
+    for (int k = 0; k < XT_SEG; ++k) {
+        og[row * OS + seg * XT_SEG + k] = outg[k];
+        if (TWO) orw[row * OS + seg * XT_SEG + k] = outr[k];
+    }
+    __syncthreads();
+    const int ioff = E ? 1 : 0;
+    const double scale = E ? cf.z : 1.0 / cf.z;
+    double* o0 = E ? t0 : t1;
+    for (int e = tid; e < XT_ROWS * XT_OUT; e += 256) {
+        const int rr = e / XT_OUT, c = e - rr * XT_OUT;
+        const int jj = j0 + rr, m = m0 + c;
+        if (jj <= N - 1 && m < L.n_out) {
+            o0[(size_t)jj * P + m + ioff] = scale * og[rr * OS + c];
+            if (TWO) t1[(size_t)jj * P + m + ioff] = orw[rr * OS + c];
         }
     }
 }
 
-// ---------------------------------------------------------------------------
-// Chebyshev solve of M Phi = b on one component grid, fused with the field
-// update.  M = alpha I - beta L9, L9 = (1/6)[1 4 1; 4 -20 4; 1 4 1].  A tile
-// of T2X x T2Y outputs is iterated in LDS together with a halo of K cells
-// (one cell of the halo becomes invalid per application of M), so the solve
-// reads b once and needs no global reduction.
-// Boundaries: Dirichlet neighbours beyond the unknown range are zero; the
-// Neumann ghost one cell beyond a half axis holds the mirrored value, which
-// the owner of the boundary cell writes next to its own value.
-// KIND 0: Ez with carried Laplacian, 1: Ez discrete, 2: Hx (z=0) / Hy (z=1).
-// ---------------------------------------------------------------------------
-struct ChebIO {
-    const double* b;
-    double* field;
-    UGrid g;
+// ===========================================================================
+// Column kernel: y-line Pade + Chebyshev solve + update.
+// A workgroup covers a region of CW = 128 columns and TR rows.  The column
+// of region row r is held by NL lanes: lane (c, q) keeps rows
+// [q HR, (q+1) HR) of column c in registers.  The rows next to a split
+// cross through a small double-buffered LDS array, the column sums
+// S = d(y-1) + 4 d(y) + d(y+1) of the 9-point stencil cross between
+// columns through the LDS (padded rows, zero sentinels at both ends).
+// ===========================================================================
+constexpr int CW = 128;      // region width (columns)
+constexpr int CWP = CW + 2;  // LDS row stride
+constexpr int NL = 4;        // lanes per column
+constexpr int NTC = CW * NL; // threads per workgroup
+
+// region rows for K sweeps: at least 16 output rows, a multiple of NL
+template <int K>
+struct ColShape {
+    static constexpr int TR = ((16 + 2 * K + NL - 1) / NL) * NL;
+    static constexpr int OH = TR - 2 * K;
+    static constexpr int HR = TR / NL;
 };
 
-template <int K, int KIND>
-__global__ __launch_bounds__(NT2) void k_cheb_2d(ChebIO io0, ChebIO io1, double* __restrict__ ge,
-                                                  const double* __restrict__ cur, int P, Coef cf,
-                                                  ChebSchedule cs)
+enum { COL_E_TRACKED = 0, COL_E_DISCRETE = 1, COL_HX_TRACKED = 2, COL_HX_DISCRETE = 3, COL_HY = 4 };
+
+struct ColArgs {
+    const double* src;      // y-line source: Hx (E step) or G_E / Ez (Hx step)
+    const double* t0;       // precomputed right-hand side part (T0 or T1), or null
+    const double* t1;       // carried Laplacian: x part of curl^A H (E step)
+    double* field;          // Ez, Hx or Hy
+    double* ge;             // G_E (E step, carried Laplacian)
+    UGrid g;                // unknowns of the solved component
+    int N, P;
+};
+
+template <int K, int MODE>
+__global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(4))) void k_col(ColArgs a, Coef cf, PadeTaps taps, PadeLine L,
+                                             ChebSchedule cs)
 {
-    constexpr int LW = T2X + 2 * K + 2;
-    constexpr int LH = T2Y + 2 * K + 2;
-    constexpr int IW = T2X + 2 * K;
-    constexpr int IH = T2Y + 2 * K;
-    constexpr int CPT = (IW * IH + NT2 - 1) / NT2;
-    __shared__ double sd[LW * LH];
-    const ChebIO& io = (KIND == 2 && blockIdx.z == 1) ? io1 : io0;
-    const UGrid& g = io.g;
-    const int x0 = g.lo[0] + blockIdx.x * T2X;
-    const int y0 = g.lo[1] + blockIdx.y * T2Y;
-    if (x0 >= g.hi[0] || y0 >= g.hi[1]) return;
+    constexpr int TR = ColShape<K>::TR;             // region rows
+    constexpr int OH = ColShape<K>::OH;             // output rows
+    constexpr int HR = ColShape<K>::HR;             // rows per lane
+    constexpr int HALO_X = K + 1;                   // column halo (one more for the cross-line term)
+    constexpr bool YPART = MODE != COL_HY;
+    constexpr bool SPLIT = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE || MODE == COL_HX_DISCRETE;
+    constexpr bool ESTEP = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE;
+    constexpr int NPOS = HR + PADE_TAPS - 1 + 2;    // streamed line positions (+1 each side for G)
+    __shared__ double lds[TR * CWP];
+    __shared__ double bnd[2][NL][2][CW];            // [parity][part][0: first row, 1: last row][column]
+
     const int tid = threadIdx.x;
-    for (int e = tid; e < LW * LH; e += NT2) sd[e] = 0.0;
-    __syncthreads();
+    const int lane = tid % CW;                      // region column
+    const int part = tid / CW;                      // rows [part HR, (part+1) HR)
+    const int rbase = part * HR;
+    const int ow = CW - 2 * HALO_X;
+    const UGrid& g = a.g;
+    const int x0 = g.lo[0] + blockIdx.x * ow;
+    const int y0 = g.lo[1] + blockIdx.y * OH;
+    const int gx = x0 - HALO_X + lane;
+    const int P = a.P, N = a.N;
+    const bool col_active = gx >= g.lo[0] && gx < g.hi[0];
+    for (int e = tid; e < TR; e += NTC) {
+        lds[e * CWP] = 0.0;
+        lds[e * CWP + CW + 1] = 0.0;
+    }
+    double* my = lds + lane + 1 + rbase * CWP;      // this lane's first row
 
-    double xv[CPT], rv[CPT], dv[CPT];
-    int pos[CPT];        // LDS index of the cell, -1 when inactive
-    int mir[CPT][3];     // LDS indices of mirror ghosts, -1 when none
-    const double a = cf.alpha, bb = cf.beta * (1.0 / 6.0);
+    double r[HR];            // right-hand side, then the Chebyshev residual
+    double cv[HR];           // carried Laplacian: curl^A H on this lane's rows
+
+    // ---------------- right-hand side ----------------
+    if (YPART) {
+        const int n_in = L.n_in;
+        const int mofs = ESTEP ? 1 : 0;                     // gy = m + mofs
+        const int mfirst = y0 - K + rbase - mofs;           // Pade output index of this lane's row 0
+        const int gfirst = mfirst - PADE_R - 1;             // first streamed position
+        const bool col_data = gx >= 0 && gx <= N;           // a stored column (walls included)
+        const bool half_line = ESTEP;
+        const bool fast = pade_interior(L, mfirst < 0 ? 0 : mfirst, mfirst + HR - 1);
+        const double* colp = a.src + gx;
+        double f[NPOS];
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        const int e = tid + q * NT2;
-        pos[q] = -1;
-        mir[q][0] = mir[q][1] = mir[q][2] = -1;
-        xv[q] = rv[q] = dv[q] = 0.0;
-        if (e < IW * IH) {
-            const int iy = e / IW, ix = e - iy * IW;
-            const int gx = x0 - K + ix, gy = y0 - K + iy;
-            if (gx >= g.lo[0] && gx < g.hi[0] && gy >= g.lo[1] && gy < g.hi[1]) {
-                const int p = (iy + 1) * LW + (ix + 1);
-                pos[q] = p;
-                const double r0 = io.b[(size_t)gy * P + gx];
-                rv[q] = r0;
-                dv[q] = r0 * cs.inv_theta;
-                int mx = 0, my = 0;
-                if (g.neumann[0]) mx = (gx == g.lo[0]) ? -1 : (gx == g.hi[0] - 1 ? 1 : 0);
-                if (g.neumann[1]) my = (gy == g.lo[1]) ? -1 : (gy == g.hi[1] - 1 ? 1 : 0);
-                if (mx) mir[q][0] = p + mx;
-                if (my) mir[q][1] = p + my * LW;
-                if (mx && my) mir[q][2] = p + mx + my * LW;
+        for (int p = 0; p < NPOS; ++p) {
+            const int gg = gfirst + p;
+            f[p] = (col_data && gg >= 0 && gg < n_in) ? colp[gg * P] : 0.0;
+        }
+        if (SPLIT) {
+            // raw line derivative P: its second difference across lines
+            // completes G; with the carried Laplacian it is also curl^A H
+#pragma unroll
+            for (int t = 0; t < HR; ++t) {
+                const int m = mfirst + t;
+                double ap = 0.0;
+                if (fast) {
+#pragma unroll
+                    for (int u = 0; u < PADE_TAPS; ++u) ap = fma(taps.c[u], f[t + 1 + u], ap);
+                } else if (m >= 0 && m < L.n_out) {
+                    const double* cr = pade_row(L, m);
+                    for (int u = 0; u < PADE_TAPS; ++u) ap = fma(cr ? cr[u] : taps.c[u], f[t + 1 + u], ap);
+                }
+                my[t * CWP] = ap;
+                cv[t] = ap;
+            }
+            // in place: f -> alpha f + (second difference along the line) / 12;
+            // half-point lines take even ghosts at their ends, node lines of
+            // E vanish on the walls
+            double prevf = 0.0;
+#pragma unroll
+            for (int p = 0; p < NPOS; ++p) {
+                const int gg = gfirst + p;
+                const double cur = f[p];
+                double lo = prevf, hi = (p < NPOS - 1) ? f[p + 1] : 0.0;
+                if (half_line) {
+                    if (gg == 0) lo = cur;
+                    if (gg == n_in - 1) hi = cur;
+                }
+                double v = fma(cf.alpha, cur, (lo + hi - 2.0 * cur) * (1.0 / 12.0));
+                if (gg < 0 || gg >= n_in || !col_data) v = 0.0;
+                if (!half_line && (gg == 0 || gg == n_in - 1)) v = 0.0;
+                f[p] = v;
+                prevf = cur;
             }
         }
-    }
+        // line derivative of the conditioned input
 #pragma unroll
-    for (int q = 0; q < CPT; ++q)
-        if (pos[q] >= 0) {
-            sd[pos[q]] = dv[q];
-            for (int t = 0; t < 3; ++t)
-                if (mir[q][t] >= 0) sd[mir[q][t]] = dv[q];
+        for (int t = 0; t < HR; ++t) {
+            const int m = mfirst + t;
+            double aq = 0.0;
+            if (fast) {
+#pragma unroll
+                for (int u = 0; u < PADE_TAPS; ++u) aq = fma(taps.c[u], f[t + 1 + u], aq);
+            } else if (m >= 0 && m < L.n_out) {
+                const double* cr = pade_row(L, m);
+                for (int u = 0; u < PADE_TAPS; ++u) aq = fma(cr ? cr[u] : taps.c[u], f[t + 1 + u], aq);
+            }
+            r[t] = aq;
         }
-    __syncthreads();
+        if (SPLIT) {
+            __syncthreads();
+            // cross-line part of G: (P(x-1) + P(x+1) - 2 P(x)) / 12
+#pragma unroll
+            for (int t = 0; t < HR; ++t) {
+                const double* q = my + t * CWP;
+                r[t] += (q[-1] + q[1] - 2.0 * q[0]) * (1.0 / 12.0);
+            }
+            __syncthreads();
+        }
+    }
 
+    // combine with the precomputed part and mask to the unknowns
+    const double ysign = ESTEP ? -cf.z : (MODE == COL_HY ? 0.0 : -1.0 / cf.z);
+#pragma unroll
+    for (int t = 0; t < HR; ++t) {
+        const int gy = y0 - K + rbase + t;
+        const bool act = col_active && gy >= g.lo[1] && gy < g.hi[1];
+        double v = 0.0;
+        if (act) {
+            const size_t o = (size_t)gy * P + gx;
+            v = YPART ? ysign * r[t] : 0.0;
+            if (a.t0) v += a.t0[o];
+        }
+        r[t] = v;
+    }
+    if (MODE == COL_E_TRACKED) {
+#pragma unroll
+        for (int t = 0; t < HR; ++t) {
+            const int row = rbase + t;
+            const int gy = y0 - K + row;
+            double v = 0.0;
+            if (row >= K && row < K + OH && col_active && gy < g.hi[1]) v = a.t1[(size_t)gy * P + gx] - cv[t];
+            cv[t] = v;
+        }
+    }
+
+    // ---------------- Chebyshev on [alpha, alpha + 16/3 beta] ----------------
+    // L9 d = (S(x-1) + S(x+1) + 4 S(x) - 36 d) / 6; A d = alpha d - beta L9 d.
+    const double b6 = cf.beta * (1.0 / 6.0);
+    const double a36 = fma(36.0, b6, cf.alpha);
+    const bool nx = g.neumann[0], ny = g.neumann[1];
+    const bool at_lo_x = gx == g.lo[0], at_hi_x = gx == g.hi[0] - 1;
+    const int rx0 = x0 - HALO_X, ry0 = y0 - K;
+    const bool inner = rx0 > g.lo[0] && rx0 + CW < g.hi[0] && ry0 > g.lo[1] && ry0 + TR < g.hi[1];
+    double d[HR], xs[HR], sown[HR];
+#pragma unroll
+    for (int t = 0; t < HR; ++t) {
+        d[t] = r[t] * cs.inv_theta;
+        xs[t] = 0.0;
+    }
+    bnd[0][part][0][lane] = d[0];
+    bnd[0][part][1][lane] = d[HR - 1];
+    __syncthreads();
+#pragma unroll
     for (int k = 0; k < K; ++k) {
-        double ad[CPT];
+        const int par = k & 1;
+        const double above = part > 0 ? bnd[par][part - 1][1][lane] : 0.0;
+        const double below = part < NL - 1 ? bnd[par][part + 1][0][lane] : 0.0;
+        const double c1 = cs.c1[k], c2 = cs.c2[k];
+        if (inner) {
 #pragma unroll
-        for (int q = 0; q < CPT; ++q) {
-            ad[q] = 0.0;
-            if (pos[q] >= 0) {
-                const double* s = sd + pos[q];
-                const double edge = s[-1] + s[1] + s[-LW] + s[LW];
-                const double corner = s[-LW - 1] + s[-LW + 1] + s[LW - 1] + s[LW + 1];
-                const double l9 = corner + 4.0 * edge - 20.0 * s[0];
-                ad[q] = fma(a, s[0], -bb * l9);
+            for (int t = 0; t < HR; ++t) {
+                const double up = t > 0 ? d[t - 1] : above;
+                const double dn = t < HR - 1 ? d[t + 1] : below;
+                sown[t] = fma(4.0, d[t], up + dn);
+                my[t * CWP] = sown[t];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < HR; ++t) {
+                const double* q = my + t * CWP;
+                const double side = q[-1] + q[1];
+                const double dc = d[t];
+                const double ad = fma(a36, dc, -b6 * fma(4.0, sown[t], side));
+                xs[t] += dc;
+                r[t] -= ad;
+                d[t] = fma(c1, dc, c2 * r[t]);
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < HR; ++t) {
+                const int gy = ry0 + rbase + t;
+                double up = t > 0 ? d[t - 1] : above;
+                double dn = t < HR - 1 ? d[t + 1] : below;
+                if (ny && gy == g.lo[1]) up = d[t];
+                if (ny && gy == g.hi[1] - 1) dn = d[t];
+                sown[t] = fma(4.0, d[t], up + dn);
+                my[t * CWP] = sown[t];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int t = 0; t < HR; ++t) {
+                const int gy = ry0 + rbase + t;
+                const double* q = my + t * CWP;
+                const double sc = sown[t];
+                double sl = q[-1], sr = q[1];
+                if (nx && at_lo_x) sl = sc;
+                if (nx && at_hi_x) sr = sc;
+                const double dc = d[t];
+                const double ad = fma(a36, dc, -b6 * fma(4.0, sc, sl + sr));
+                const bool act = col_active && gy >= g.lo[1] && gy < g.hi[1];
+                xs[t] += dc;
+                const double rn = r[t] - ad;
+                r[t] = act ? rn : 0.0;
+                d[t] = act ? fma(c1, dc, c2 * rn) : 0.0;
             }
         }
-        __syncthreads();
-        const double c1 = cs.c1[k], c2 = cs.c2[k];
-#pragma unroll
-        for (int q = 0; q < CPT; ++q)
-            if (pos[q] >= 0) {
-                xv[q] += dv[q];
-                rv[q] -= ad[q];
-                dv[q] = fma(c1, dv[q], c2 * rv[q]);
-                sd[pos[q]] = dv[q];
-                for (int t = 0; t < 3; ++t)
-                    if (mir[q][t] >= 0) sd[mir[q][t]] = dv[q];
-            }
+        bnd[par ^ 1][part][0][lane] = d[0];
+        bnd[par ^ 1][part][1][lane] = d[HR - 1];
         __syncthreads();
     }
 
-    // field update on the tile
+    // ---------------- update ----------------
+    if (lane < HALO_X || lane >= CW - HALO_X || !col_active) return;
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-        const int e = tid + q * NT2;
-        if (pos[q] < 0) continue;
-        const int iy = e / IW, ix = e - iy * IW;
-        if (ix < K || ix >= K + T2X || iy < K || iy >= K + T2Y) continue;
-        const int gx = x0 - K + ix, gy = y0 - K + iy;
+    for (int t = 0; t < HR; ++t) {
+        const int row = rbase + t;
+        if (row < K || row >= K + OH) continue;
+        const int gy = y0 - K + row;
+        if (gy >= g.hi[1]) continue;
         const size_t o = (size_t)gy * P + gx;
-        const double phi = xv[q] + dv[q];
-        const double de = cf.cfl * phi;
-        io.field[o] += de;
-        if (KIND == 0) ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cur[o]);
+        const double de = cf.cfl * (xs[t] + d[t]);
+        a.field[o] += de;
+        if (MODE == COL_E_TRACKED) a.ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cv[t]);
     }
 }
 
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
-template <int KIND>
-static hipError_t launch_cheb_k(int K, dim3 grid, hipStream_t st, ChebIO io0, ChebIO io1, double* ge,
-                                const double* cur, int P, Coef cf, ChebSchedule cs)
+template <int MODE>
+static hipError_t launch_col_k(int K, dim3 grid, hipStream_t st, const ColArgs& a, const Coef& cf,
+                               const PadeTaps& taps, const PadeLine& L, const ChebSchedule& cs)
 {
     switch (K) {
 #define C4M_CASE(KK)                                                                              \
-    case KK:                                                                                      \
-        hipLaunchKernelGGL((k_cheb_2d<KK, KIND>), grid, dim3(NT2), 0, st, io0, io1, ge, cur, P, cf, \
-                           cs);                                                                   \
-        break;
+    case KK: hipLaunchKernelGGL((k_col<KK, MODE>), grid, dim3(NTC), 0, st, a, cf, taps, L, cs); break;
         C4M_CASE(1) C4M_CASE(2) C4M_CASE(3) C4M_CASE(4) C4M_CASE(5) C4M_CASE(6) C4M_CASE(7) C4M_CASE(8)
 #undef C4M_CASE
         default: return hipErrorInvalidValue;
@@ -370,52 +450,75 @@ static hipError_t launch_cheb_k(int K, dim3 grid, hipStream_t st, ChebIO io0, Ch
     return hipGetLastError();
 }
 
+static dim3 col_grid(const UGrid& g, int K)
+{
+    int oh = 16;
+    switch (K) {
+#define C4M_CASE(KK) case KK: oh = ColShape<KK>::OH; break;
+        C4M_CASE(1) C4M_CASE(2) C4M_CASE(3) C4M_CASE(4) C4M_CASE(5) C4M_CASE(6) C4M_CASE(7) C4M_CASE(8)
+#undef C4M_CASE
+    }
+    const int ow = CW - 2 * (K + 1);
+    return dim3((g.hi[0] - g.lo[0] + ow - 1) / ow, (g.hi[1] - g.lo[1] + oh - 1) / oh);
+}
+
 hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const double* hy, double* t0,
                            double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                            const PadeLine& line_h2n)
 {
-    dim3 grid((N - 1 + T2X - 1) / T2X, (N - 1 + T2Y - 1) / T2Y);
+    // x-lines of Hy: N inputs, N-1 outputs, rows 1..N-1
+    dim3 grid((N - 1 + XT_OUT - 1) / XT_OUT, (N - 1 + XT_ROWS - 1) / XT_ROWS);
+    (void)hx;
     if (tracked)
-        hipLaunchKernelGGL(k_rhs_e2d<true>, grid, dim3(NT2), 0, st, hx, hy, t0, t1, N, P, cf, taps,
+        hipLaunchKernelGGL(k_xlines<XL_E_TRACKED>, grid, dim3(256), 0, st, hy, t0, t1, N, P, cf, taps,
                            line_h2n);
     else
-        hipLaunchKernelGGL(k_rhs_e2d<false>, grid, dim3(NT2), 0, st, hx, hy, t0, t1, N, P, cf, taps,
+        hipLaunchKernelGGL(k_xlines<XL_E_DISCRETE>, grid, dim3(256), 0, st, hy, t0, t1, N, P, cf, taps,
                            line_h2n);
     return hipGetLastError();
 }
 
-hipError_t launch_solve_e_2d(hipStream_t st, bool tracked, double* ez, double* ge, const double* t0,
-                             const double* t1, int N, int P, const Coef& cf, const ChebSchedule& cs)
+hipError_t launch_solve_e_2d(hipStream_t st, bool tracked, const double* hx, double* ez, double* ge,
+                             const double* t0, const double* t1, int N, int P, const Coef& cf,
+                             const PadeTaps& taps, const PadeLine& line_h2n, const ChebSchedule& cs)
 {
-    dim3 grid((N - 1 + T2X - 1) / T2X, (N - 1 + T2Y - 1) / T2Y);
-    ChebIO io{t0, ez, UGrid{{1, 1, 0}, {N, N, 1}, {0, 0, 0}}};
-    if (tracked) return launch_cheb_k<0>(cs.sweeps, grid, st, io, io, ge, t1, P, cf, cs);
-    return launch_cheb_k<1>(cs.sweeps, grid, st, io, io, nullptr, nullptr, P, cf, cs);
+    ColArgs a{hx, t0, t1, ez, ge, UGrid{{1, 1, 0}, {N, N, 1}, {0, 0, 0}}, N, P};
+    const dim3 grid = col_grid(a.g, cs.sweeps);
+    if (tracked) return launch_col_k<COL_E_TRACKED>(cs.sweeps, grid, st, a, cf, taps, line_h2n, cs);
+    return launch_col_k<COL_E_DISCRETE>(cs.sweeps, grid, st, a, cf, taps, line_h2n, cs);
 }
 
 hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, double* t0, double* t1,
                            int N, int P, const Coef& cf, const PadeTaps& taps,
                            const PadeLine& line_n2h)
 {
-    dim3 grid((N + T2X - 1) / T2X, (N + T2Y - 1) / T2Y, 2);
+    // x-lines of G_E: N+1 inputs, N outputs (Hy half points), rows 1..N-1
+    dim3 grid((N + XT_OUT - 1) / XT_OUT, (N - 1 + XT_ROWS - 1) / XT_ROWS);
     if (tracked)
-        hipLaunchKernelGGL(k_rhs_h2d<true>, grid, dim3(NT2), 0, st, src, t0, t1, N, P, cf, taps,
+        hipLaunchKernelGGL(k_xlines<XL_H_TRACKED>, grid, dim3(256), 0, st, src, t0, t1, N, P, cf, taps,
                            line_n2h);
     else
-        hipLaunchKernelGGL(k_rhs_h2d<false>, grid, dim3(NT2), 0, st, src, t0, t1, N, P, cf, taps,
+        hipLaunchKernelGGL(k_xlines<XL_H_DISCRETE>, grid, dim3(256), 0, st, src, t0, t1, N, P, cf, taps,
                            line_n2h);
     return hipGetLastError();
 }
 
-hipError_t launch_solve_h_2d(hipStream_t st, double* hx, double* hy, const double* t0,
-                             const double* t1, int N, int P, const Coef& cf, const ChebSchedule& cs)
+hipError_t launch_solve_h_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy,
+                             const double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
+                             const PadeLine& line_n2h, const ChebSchedule& cs)
 {
-    dim3 grid((N + T2X - 1) / T2X, (N + T2Y - 1) / T2Y, 2);
-    // Hx: Dirichlet in x (nodes 1..N-1), Neumann in y (half points 0..N-1)
-    ChebIO iox{t0, hx, UGrid{{1, 0, 0}, {N, N, 1}, {0, 1, 0}}};
-    // Hy: Neumann in x, Dirichlet in y
-    ChebIO ioy{t1, hy, UGrid{{0, 1, 0}, {N, N, 1}, {1, 0, 0}}};
-    return launch_cheb_k<2>(cs.sweeps, grid, st, iox, ioy, nullptr, nullptr, P, cf, cs);
+    // Hx: Dirichlet in x (nodes 1..N-1), Neumann in y (half points 0..N-1);
+    // right-hand side -(1/Z) delta_y G_E along columns
+    ColArgs ax{src, nullptr, nullptr, hx, nullptr, UGrid{{1, 0, 0}, {N, N, 1}, {0, 1, 0}}, N, P};
+    hipError_t e = tracked
+                       ? launch_col_k<COL_HX_TRACKED>(cs.sweeps, col_grid(ax.g, cs.sweeps), st, ax, cf,
+                                                      taps, line_n2h, cs)
+                       : launch_col_k<COL_HX_DISCRETE>(cs.sweeps, col_grid(ax.g, cs.sweeps), st, ax, cf,
+                                                       taps, line_n2h, cs);
+    if (e != hipSuccess) return e;
+    // Hy: Neumann in x, Dirichlet in y; right-hand side T1 from the x-lines
+    ColArgs ay{nullptr, t1, nullptr, hy, nullptr, UGrid{{0, 1, 0}, {N, N, 1}, {1, 0, 0}}, N, P};
+    return launch_col_k<COL_HY>(cs.sweeps, col_grid(ay.g, cs.sweeps), st, ay, cf, taps, line_n2h, cs);
 }
 
 }  // namespace c4m
