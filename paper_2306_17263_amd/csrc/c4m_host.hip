@@ -25,6 +25,10 @@ hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, doub
 hipError_t launch_solve_h_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy,
                              const double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                              const PadeLine& line_n2h, const ChebSchedule& cs);
+hipError_t launch_term3(hipStream_t st, int axis, int mode, const Term3& t, double alpha,
+                        const PadeTaps& taps, const PadeLine& L);
+hipError_t launch_solve3(hipStream_t st, const Cheb3& c, double* field, double* ge, const double* cur,
+                         const Coef& cf, const ChebSchedule& cs);
 hipError_t launch_zero_walls(hipStream_t st, double* a, const Box& bx, int P, size_t plane);
 hipError_t launch_lap_convert(hipStream_t st, double* a, const double* e, double* out, const Box& bx,
                               int P, size_t plane, double alpha, int mode);
@@ -283,7 +287,7 @@ c4m_status validate(const c4m_config* c)
     const double bound = 5.0 / (6.0 * sqrt((double)c->dim));
     if (!(c->flags & C4M_FLAG_ALLOW_ANY_CFL) && c->cfl > bound * (1.0 + 1e-12))
         return fail(C4M_EUNSTABLE, "cfl above the stability bound 5/(6 sqrt(dim))");
-    if (c->dim == 3 || c->precision != C4M_FP64 || c->solver != C4M_SOLVER_CHEBYSHEV)
+    if (c->precision != C4M_FP64 || c->solver != C4M_SOLVER_CHEBYSHEV)
         return fail(C4M_EINVAL, "configuration not supported by this build");
     return C4M_OK;
 }
@@ -406,6 +410,67 @@ c4m_status timed(c4m_problem* p, int cls, const char* what, F&& launch)
     return C4M_OK;
 }
 
+UGrid unknowns(const Box& b)
+{
+    UGrid g{};
+    for (int d = 0; d < 3; ++d) {
+        if (!b.active[d]) {
+            g.lo[d] = 0;
+            g.hi[d] = 1;
+            continue;
+        }
+        g.lo[d] = b.half[d] ? 0 : 1;
+        g.hi[d] = b.n[d] - (b.half[d] ? 0 : 1);
+        g.neumann[d] = b.half[d];
+    }
+    return g;
+}
+
+// 3D: Step 1 then Step 2 of Section 3.4, one component at a time.
+enum { T3_RAW = 0, T3_G = 1, T3_GE_STORED = 2, T3_GE_DISCRETE = 3 };
+c4m_status step3(c4m_problem* p)
+{
+    const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+    const double z = p->coef.z;
+    double *b = p->tmp[0], *x = p->tmp[1], *d0 = p->tmp[2], *d1 = p->tmp[3], *cur = p->tmp[4];
+    c4m_status s = C4M_OK;
+    auto term = [&](int axis, int src, int mode, double* out, double scale, int acc, int tgt, int line) {
+        Term3 t{p->f[src], out, p->box[src], unknowns(p->box[tgt]), p->P, p->plane, scale, acc};
+        if (mode == T3_GE_STORED) t.src = p->ge[src];
+        return launch_term3(p->stream, axis, mode, t, p->coef.alpha, p->pade_host[line].taps, p->line[line]);
+    };
+    for (int c = 0; c < 3 && s == C4M_OK; ++c) {
+        const int s1 = (c + 1) % 3, s2 = (c + 2) % 3;
+        s = timed(p, C4M_K_RHS_E, "rhs E", [&] {
+            hipError_t e = term(s1, 3 + s2, T3_G, b, z, 0, c, 1);
+            if (e == hipSuccess) e = term(s2, 3 + s1, T3_G, b, -z, 1, c, 1);
+            if (e == hipSuccess && tracked) e = term(s1, 3 + s2, T3_RAW, cur, 1.0, 0, c, 1);
+            if (e == hipSuccess && tracked) e = term(s2, 3 + s1, T3_RAW, cur, -1.0, 1, c, 1);
+            return e;
+        });
+        if (s != C4M_OK) break;
+        s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
+            Cheb3 ch{b, x, d0, d1, unknowns(p->box[c]), p->P, p->plane};
+            return launch_solve3(p->stream, ch, p->f[c], tracked ? p->ge[c] : nullptr, cur, p->coef, p->cheb);
+        });
+    }
+    const int gmode = tracked ? T3_GE_STORED : T3_GE_DISCRETE;
+    for (int c = 0; c < 3 && s == C4M_OK; ++c) {
+        const int s1 = (c + 1) % 3, s2 = (c + 2) % 3;
+        s = timed(p, C4M_K_RHS_H, "rhs H", [&] {
+            hipError_t e = term(s1, s2, gmode, b, -1.0 / z, 0, 3 + c, 0);
+            if (e == hipSuccess) e = term(s2, s1, gmode, b, 1.0 / z, 1, 3 + c, 0);
+            return e;
+        });
+        if (s != C4M_OK) break;
+        s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
+            Cheb3 ch{b, x, d0, d1, unknowns(p->box[3 + c]), p->P, p->plane};
+            return launch_solve3(p->stream, ch, p->f[3 + c], nullptr, nullptr, p->coef, p->cheb);
+        });
+    }
+    return s;
+}
+
 c4m_status step_once(c4m_problem* p)
 {
     const int N = p->N, P = p->P;
@@ -434,7 +499,7 @@ c4m_status step_once(c4m_problem* p)
             });
         return s;
     }
-    return fail(C4M_EINVAL, "3D stepping not supported by this build");
+    return step3(p);
 }
 
 // Compulsory FP64 state bytes per launch of each kernel class (temporaries
@@ -442,18 +507,26 @@ c4m_status step_once(c4m_problem* p)
 // target field (and G_E with the carried Laplacian).
 void set_alg_bytes(c4m_problem* p)
 {
-    // 2D: the x-line kernel of Step 1 reads Hy, its column kernel reads Hx
-    // and updates Ez (and G_E); the x-line kernel of Step 2 reads G_E (or
-    // Ez), its column kernels update Hx and Hy.
-    const double cells = p->dim == 2 ? (double)p->N * p->N : (double)p->N * p->N * p->N;
-    const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+    // Compulsory FP64 state traffic per launch of each class; each field is
+    // counted once per half-step (2D: the x-line kernel of Step 1 reads Hy,
+    // the column kernel reads Hx and updates Ez and G_E; 3D: the Step 1
+    // right-hand sides read the three H components once, ...).
     const double w = 8.0;
-    const int ne = p->dim == 2 ? 1 : 3;          // E components
-    const int nh = p->dim == 2 ? 2 : 3;          // H components
-    p->alg_bytes[C4M_K_RHS_E] = w * cells * (nh - 1);
-    p->alg_bytes[C4M_K_SOLVE_E] = w * cells * (1 + ne * (tracked ? 4 : 2));
-    p->alg_bytes[C4M_K_RHS_H] = w * cells * ne;
-    p->alg_bytes[C4M_K_SOLVE_H] = w * cells * nh * 2;
+    const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+    if (p->dim == 2) {
+        const double cells = (double)p->N * p->N;
+        p->alg_bytes[C4M_K_RHS_E] = w * cells;
+        p->alg_bytes[C4M_K_SOLVE_E] = w * cells * (1 + (tracked ? 4 : 2));
+        p->alg_bytes[C4M_K_RHS_H] = w * cells;
+        p->alg_bytes[C4M_K_SOLVE_H] = w * cells * 4;
+    } else {
+        // per launch = per component (three launches of each class a step)
+        const double cells = (double)p->N * p->N * p->N;
+        p->alg_bytes[C4M_K_RHS_E] = w * cells;                 // one H component's share
+        p->alg_bytes[C4M_K_SOLVE_E] = w * cells * (tracked ? 4 : 2);
+        p->alg_bytes[C4M_K_RHS_H] = w * cells;
+        p->alg_bytes[C4M_K_SOLVE_H] = w * cells * 2;
+    }
     p->alg_bytes[C4M_K_STEP_E] = p->alg_bytes[C4M_K_RHS_E] + p->alg_bytes[C4M_K_SOLVE_E];
     p->alg_bytes[C4M_K_STEP_H] = p->alg_bytes[C4M_K_RHS_H] + p->alg_bytes[C4M_K_SOLVE_H];
 }

@@ -69,4 +69,27 @@ struct Coef {
     double ge_curl;                  // (2/r) Z   : ... - ge_curl * curl^A H
 };
 
+// 3D: one Pade line-derivative term accumulated into a target right-hand side.
+struct Term3 {
+    const double* src;
+    double* out;
+    Box sb;            // source component extents and half flags
+    UGrid tg;          // target unknown ranges (outputs along the line start at tg.lo[axis])
+    int P;
+    size_t plane;
+    double scale;
+    int accumulate;
+};
+
+// 3D: arrays of one Chebyshev solve (r holds b on entry).
+struct Cheb3 {
+    double* r;
+    double* x;
+    double* d0;
+    double* d1;
+    UGrid g;
+    int P;
+    size_t plane;
+};
+
 }  // namespace c4m

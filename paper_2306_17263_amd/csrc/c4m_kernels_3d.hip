@@ -1,0 +1,279 @@
+// c4m_kernels_3d.hip -- gfx950 kernels of the full 3D step (Ex..Hz).
+//
+// Step 1 (Section 3.4), per E component s (s1 = s+1, s2 = s+2 mod 3):
+//   b   = Z (delta_{s1} G(H_{s2}) - delta_{s2} G(H_{s1}))      k_term3 twice
+//   c   = delta_{s1} H_{s2} - delta_{s2} H_{s1}                 (carried l) k_term3 twice
+//   Phi = M^{-1} b (19-point M), E_s += r Phi, G_E += ...       k_cheb3_*
+// Step 2, per H component s:
+//   b   = -(1/Z) (delta_{s1} G_{E,s2} - delta_{s2} G_{E,s1}),   H_s += r M^{-1} b.
+//
+// k_term3: one Pade line derivative along axis D, accumulated into the
+// target's right-hand side.  A tile holds A lines of the target (32 rows
+// along y for D = x, 64 columns along x otherwise) with 32 or 64 outputs
+// each; the conditioned source values of the tile's line windows are staged
+// in LDS (coalesced loads), then every thread runs the truncated Pade FIR
+// over a register window of 8 consecutive outputs.
+//
+// Chebyshev: one launch per sweep (x += d, r -= M d, d <- c1 d + c2 r) over
+// the unknowns, with the 19-point stencil read through the caches.
+#include "c4m_internal.h"
+
+namespace c4m {
+
+enum { SRC_RAW = 0, SRC_G = 1, SRC_GE_STORED = 2, SRC_GE_DISCRETE = 3 };
+
+
+__device__ __forceinline__ const double* pade_row3(const PadeLine& L, int m)
+{
+    if (L.all) return L.rows + (size_t)m * PADE_TAPS;
+    if (m < L.b) return L.rows + (size_t)m * PADE_TAPS;
+    if (m >= L.n_out - L.b) return L.rows + (size_t)(m - (L.n_out - L.b) + L.b) * PADE_TAPS;
+    return nullptr;
+}
+
+// Source value at stored index q (q[D] may run outside the line: zero).
+// SRC_G: alpha u + (sum of second differences)/12 with even ghosts along
+// half axes (node axes are interior here); SRC_GE_DISCRETE: the same on E,
+// zero on E's node walls.
+template <int MODE>
+__device__ __forceinline__ double src_value(const Term3& t, int i, int j, int k, double alpha)
+{
+    const Box& b = t.sb;
+    if (i < 0 || j < 0 || k < 0 || i >= b.n[0] || j >= b.n[1] || k >= b.n[2]) return 0.0;
+    const double* p = t.src + k * t.plane + (size_t)j * t.P + i;
+    if (MODE == SRC_RAW || MODE == SRC_GE_STORED) return p[0];
+    const int q[3] = {i, j, k};
+    const size_t st[3] = {1, (size_t)t.P, t.plane};
+    if (MODE == SRC_GE_DISCRETE) {
+#pragma unroll
+        for (int d = 0; d < 3; ++d)
+            if (!b.half[d] && (q[d] == 0 || q[d] == b.n[d] - 1)) return 0.0;
+    }
+    const double u0 = p[0];
+    double lap = 0.0;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        const double um = q[d] == 0 ? u0 : p[-(long)st[d]];          // even ghost (half axis)
+        const double up = q[d] == b.n[d] - 1 ? u0 : p[st[d]];
+        lap += um + up - 2.0 * u0;
+    }
+    return fma(alpha, u0, lap * (1.0 / 12.0));
+}
+
+constexpr int T3_SEG = 8;
+
+template <int D, int MODE>
+__global__ __launch_bounds__(256) void k_term3(Term3 t, double alpha, PadeTaps taps, PadeLine L)
+{
+    // tile geometry: A lines x NO outputs per line
+    constexpr int A = D == 0 ? 32 : 64;
+    constexpr int NO = D == 0 ? 64 : 32;
+    constexpr int BW = NO + PADE_TAPS - 1;       // staged window per line
+    constexpr int BS = (BW % 2) ? BW : BW + 1;   // odd stride
+    __shared__ double sv[A * BS];
+    // axes: D = line axis, W = across lines in the tile, Sx = slab (blockIdx.z)
+    constexpr int W = D == 0 ? 1 : 0;
+    constexpr int SX = 3 - D - W;
+    const int m0 = blockIdx.x * NO;                       // first output along D
+    const int w0 = t.tg.lo[W] + blockIdx.y * A;           // first line along W
+    const int s = t.tg.lo[SX] + blockIdx.z;               // slab index
+    const int tid = threadIdx.x;
+    const int n_in = L.n_in;
+    for (int e = tid; e < A * BW; e += 256) {
+        int a, q;
+        if (D == 0) { a = e / BW; q = e - a * BW; }       // consecutive threads along the line (x)
+        else { q = e / A; a = e - q * A; }                // consecutive threads across lines (x)
+        const int wi = w0 + a;
+        const int g = m0 - PADE_R + q;
+        double v = 0.0;
+        if (wi < t.tg.hi[W] && g >= 0 && g < n_in) {
+            int idx[3];
+            idx[D] = g;
+            idx[W] = wi;
+            idx[SX] = s;
+            v = src_value<MODE>(t, idx[0], idx[1], idx[2], alpha);
+        }
+        sv[a * BS + q] = v;
+    }
+    __syncthreads();
+    // thread -> (line a, segment): lanes of a half-wave take consecutive lines
+    const int a = tid % A;
+    const int seg = tid / A;
+    const int mb = m0 + seg * T3_SEG;
+    const double* w = sv + a * BS + seg * T3_SEG;
+    double out[T3_SEG];
+    const bool fast = !L.all && mb >= L.b && mb + T3_SEG - 1 < L.n_out - L.b;
+    if (fast) {
+        double win[T3_SEG + PADE_TAPS - 1];
+#pragma unroll
+        for (int u = 0; u < T3_SEG + PADE_TAPS - 1; ++u) win[u] = w[u];
+#pragma unroll
+        for (int k = 0; k < T3_SEG; ++k) {
+            double acc = 0.0;
+#pragma unroll
+            for (int u = 0; u < PADE_TAPS; ++u) acc = fma(taps.c[u], win[k + u], acc);
+            out[k] = acc;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < T3_SEG; ++k) {
+            const int m = mb + k;
+            double acc = 0.0;
+            if (m < L.n_out) {
+                const double* cr = pade_row3(L, m);
+                for (int u = 0; u < PADE_TAPS; ++u) acc = fma(cr ? cr[u] : taps.c[u], w[k + u], acc);
+            }
+            out[k] = acc;
+        }
+    }
+    const int wi = w0 + a;
+    if (wi >= t.tg.hi[W]) return;
+#pragma unroll
+    for (int k = 0; k < T3_SEG; ++k) {
+        const int m = mb + k;
+        if (m >= L.n_out) break;
+        int idx[3];
+        idx[D] = t.tg.lo[D] + m;
+        idx[W] = wi;
+        idx[SX] = s;
+        double* o = t.out + idx[2] * t.plane + (size_t)idx[1] * t.P + idx[0];
+        const double v = t.scale * out[k];
+        *o = t.accumulate ? *o + v : v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Chebyshev sweeps on one component grid.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ bool cell3(const UGrid& g, int& i, int& j, int& k)
+{
+    const int nx = g.hi[0] - g.lo[0], ny = g.hi[1] - g.lo[1], nz = g.hi[2] - g.lo[2];
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (long)nx * ny * nz) return false;
+    i = g.lo[0] + (int)(e % nx);
+    const long rest = e / nx;
+    j = g.lo[1] + (int)(rest % ny);
+    k = g.lo[2] + (int)(rest / ny);
+    return true;
+}
+
+__global__ void k_cheb3_init(Cheb3 c, double inv_theta)
+{
+    int i, j, k;
+    if (!cell3(c.g, i, j, k)) return;
+    const size_t o = k * c.plane + (size_t)j * c.P + i;
+    c.d0[o] = c.r[o] * inv_theta;
+    c.x[o] = 0.0;
+}
+
+// d value at a neighbour of an unknown: Dirichlet beyond the range -> 0,
+// Neumann -> mirrored back into the range.
+__device__ __forceinline__ double dval(const Cheb3& c, const double* d, int i, int j, int k)
+{
+    int q[3] = {i, j, k};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (q[a] < c.g.lo[a]) {
+            if (!c.g.neumann[a]) return 0.0;
+            q[a] = c.g.lo[a];
+        } else if (q[a] >= c.g.hi[a]) {
+            if (!c.g.neumann[a]) return 0.0;
+            q[a] = c.g.hi[a] - 1;
+        }
+    }
+    return d[q[2] * c.plane + (size_t)q[1] * c.P + q[0]];
+}
+
+// L9 (3D) = (1/6)(2 sum faces + sum edges - 24 centre); A d = alpha d - beta L9 d
+__global__ void k_cheb3_sweep(Cheb3 c, const double* __restrict__ din, double* __restrict__ dout,
+                              double alpha, double beta, double c1, double c2)
+{
+    int i, j, k;
+    if (!cell3(c.g, i, j, k)) return;
+    const size_t o = k * c.plane + (size_t)j * c.P + i;
+    const double dc = din[o];
+    double faces = 0.0, edges = 0.0;
+    faces += dval(c, din, i - 1, j, k) + dval(c, din, i + 1, j, k);
+    faces += dval(c, din, i, j - 1, k) + dval(c, din, i, j + 1, k);
+    faces += dval(c, din, i, j, k - 1) + dval(c, din, i, j, k + 1);
+    for (int a = -1; a <= 1; a += 2)
+        for (int b = -1; b <= 1; b += 2) {
+            edges += dval(c, din, i + a, j + b, k);
+            edges += dval(c, din, i, j + a, k + b);
+            edges += dval(c, din, i + a, j, k + b);
+        }
+    const double l9 = (2.0 * faces + edges - 24.0 * dc) * (1.0 / 6.0);
+    const double ad = fma(alpha, dc, -beta * l9);
+    c.x[o] += dc;
+    const double rn = c.r[o] - ad;
+    c.r[o] = rn;
+    dout[o] = fma(c1, dc, c2 * rn);
+}
+
+// field += cfl (x + d); with the carried Laplacian of E also
+// G_E += (1 + 4/r^2) dE - (2/r) Z c.
+__global__ void k_cheb3_final(Cheb3 c, const double* __restrict__ dlast, double* field, double* ge,
+                              const double* cur, Coef cf)
+{
+    int i, j, k;
+    if (!cell3(c.g, i, j, k)) return;
+    const size_t o = k * c.plane + (size_t)j * c.P + i;
+    const double de = cf.cfl * (c.x[o] + dlast[o]);
+    field[o] += de;
+    if (ge) ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cur[o]);
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+// ---------------------------------------------------------------------------
+template <int D>
+static hipError_t launch_term_d(hipStream_t st, int mode, const Term3& t, double alpha, const PadeTaps& taps,
+                                const PadeLine& L)
+{
+    constexpr int A = D == 0 ? 32 : 64;
+    constexpr int NO = D == 0 ? 64 : 32;
+    constexpr int W = D == 0 ? 1 : 0;
+    constexpr int SX = 3 - D - W;
+    dim3 grid((L.n_out + NO - 1) / NO, (t.tg.hi[W] - t.tg.lo[W] + A - 1) / A, t.tg.hi[SX] - t.tg.lo[SX]);
+    switch (mode) {
+        case SRC_RAW: hipLaunchKernelGGL((k_term3<D, SRC_RAW>), grid, dim3(256), 0, st, t, alpha, taps, L); break;
+        case SRC_G: hipLaunchKernelGGL((k_term3<D, SRC_G>), grid, dim3(256), 0, st, t, alpha, taps, L); break;
+        case SRC_GE_STORED:
+            hipLaunchKernelGGL((k_term3<D, SRC_GE_STORED>), grid, dim3(256), 0, st, t, alpha, taps, L);
+            break;
+        default:
+            hipLaunchKernelGGL((k_term3<D, SRC_GE_DISCRETE>), grid, dim3(256), 0, st, t, alpha, taps, L);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_term3(hipStream_t st, int axis, int mode, const Term3& t, double alpha, const PadeTaps& taps,
+                        const PadeLine& L)
+{
+    if (axis == 0) return launch_term_d<0>(st, mode, t, alpha, taps, L);
+    if (axis == 1) return launch_term_d<1>(st, mode, t, alpha, taps, L);
+    return launch_term_d<2>(st, mode, t, alpha, taps, L);
+}
+
+hipError_t launch_solve3(hipStream_t st, const Cheb3& c, double* field, double* ge, const double* cur,
+                         const Coef& cf, const ChebSchedule& cs)
+{
+    const long cells = (long)(c.g.hi[0] - c.g.lo[0]) * (c.g.hi[1] - c.g.lo[1]) * (c.g.hi[2] - c.g.lo[2]);
+    const dim3 grid((unsigned)((cells + 255) / 256));
+    hipLaunchKernelGGL(k_cheb3_init, grid, dim3(256), 0, st, c, cs.inv_theta);
+    double* din = c.d0;
+    double* dout = c.d1;
+    for (int k = 0; k < cs.sweeps; ++k) {
+        hipLaunchKernelGGL(k_cheb3_sweep, grid, dim3(256), 0, st, c, din, dout, cf.alpha, cf.beta, cs.c1[k],
+                           cs.c2[k]);
+        double* tmp = din;
+        din = dout;
+        dout = tmp;
+    }
+    hipLaunchKernelGGL(k_cheb3_final, grid, dim3(256), 0, st, c, din, field, ge, cur, cf);
+    return hipGetLastError();
+}
+
+}  // namespace c4m
