@@ -4,3 +4,4 @@ library libc4m.so (C ABI in include/c4m.h); this package only marshals
 arguments, with PyTorch providing device memory and streams."""
 from ._lib import C4mError, EXPORTS, load  # noqa: F401
 from .problem import Problem, make_config, workspace_bytes  # noqa: F401
+from .batch import Batch  # noqa: F401

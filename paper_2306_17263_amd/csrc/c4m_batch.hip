@@ -1,10 +1,434 @@
-// c4m_batch.hip -- batched form (many independent 2D problems per launch).
-#include "c4m_internal.h"
+// c4m_batch.hip -- batched form: many independent 2D TM cavity problems of
+// uneven N advanced together.
+//
+// A step is five phases (Step 1 x-lines, Step 1 column solve, Step 2
+// x-lines, Step 2 Hx and Hy column solves).  Each phase is ONE persistent
+// launch over the work items (problem, tile) of every problem: workgroups
+// take items from a device counter until the queue is empty, so problems of
+// very different sizes share the machine without one launch per problem.
+// The last workgroup to leave resets the counter for the next launch (no
+// memset, so the step can be captured into a HIP graph and replayed).
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "c4m_tiles_2d.h"
+
+namespace c4m {
+
+struct BatchProb {
+    XArgs xe, xh;            // x-line arguments of Step 1 and Step 2
+    ColArgs ce, chx, chy;    // column arguments of the three solves
+    int tiles_x[5];          // tiles along x per phase
+};
+
+enum { PH_XE = 0, PH_CE = 1, PH_XH = 2, PH_CHX = 3, PH_CHY = 4, NPH = 5 };
+
+struct PhaseQueue {
+    const int* prefix;       // [count + 1] first work item of each problem
+    int count;
+    int* ctr;                // [0]: next item, [1]: workgroups finished
+};
+
+__device__ __forceinline__ int find_problem(const PhaseQueue& q, int item)
+{
+    int lo = 0, hi = q.count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (q.prefix[mid] <= item) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Claim the next item for the whole workgroup; -1 when the queue is empty.
+__device__ __forceinline__ int claim(const PhaseQueue& q, int total, int* slot)
+{
+    __syncthreads();                         // every thread has read the previous item
+    if (threadIdx.x == 0) *slot = atomicAdd(q.ctr, 1);
+    __syncthreads();
+    const int it = *slot;
+    return it < total ? it : -1;
+}
+
+__device__ __forceinline__ void finish(const PhaseQueue& q)
+{
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const int done = atomicAdd(q.ctr + 1, 1);
+        if (done == (int)gridDim.x - 1) {
+            atomicExch(q.ctr, 0);
+            atomicExch(q.ctr + 1, 0);
+        }
+    }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_batch_x(const BatchProb* __restrict__ bp, PhaseQueue q, int total,
+                                                 int phase, Coef cf, PadeTaps taps)
+{
+    __shared__ int slot;
+    for (;;) {
+        const int it = claim(q, total, &slot);
+        if (it < 0) break;
+        const int p = find_problem(q, it);
+        const int local = it - q.prefix[p];
+        const int tx = bp[p].tiles_x[phase];
+        const XArgs& xa = phase == PH_XE ? bp[p].xe : bp[p].xh;
+        xlines_tile<MODE>(xa, cf, taps, local % tx, local / tx);
+    }
+    finish(q);
+}
+
+template <int K, int MODE>
+__global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_col(
+    const BatchProb* __restrict__ bp, PhaseQueue q, int total, int phase, Coef cf, PadeTaps taps,
+    ChebSchedule cs)
+{
+    __shared__ int slot;
+    for (;;) {
+        const int it = claim(q, total, &slot);
+        if (it < 0) break;
+        const int p = find_problem(q, it);
+        const int local = it - q.prefix[p];
+        const int tx = bp[p].tiles_x[phase];
+        const ColArgs& ca = phase == PH_CE ? bp[p].ce : (phase == PH_CHX ? bp[p].chx : bp[p].chy);
+        const PadeLine& L = phase == PH_CE ? bp[p].xe.L : bp[p].xh.L;
+        col_tile<K, MODE>(ca, cf, taps, L, cs, local % tx, local / tx);
+    }
+    finish(q);
+}
+
+template <int K>
+static int col_tiles(const UGrid& g, int* tx)
+{
+    *tx = col_tiles_x<K>(g);
+    return col_tiles_x<K>(g) * col_tiles_y<K>(g);
+}
+
+static int col_tiles_k(int K, const UGrid& g, int* tx)
+{
+    switch (K) {
+#define C4M_CASE(KK) case KK: return col_tiles<KK>(g, tx);
+        C4M_CASE(1) C4M_CASE(2) C4M_CASE(3) C4M_CASE(4) C4M_CASE(5) C4M_CASE(6) C4M_CASE(7) C4M_CASE(8)
+#undef C4M_CASE
+    }
+    *tx = 1;
+    return 0;
+}
+
+// workgroups of a persistent launch: what fits on the device at once
+template <class Kern>
+static int resident_blocks(Kern kern, int threads)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kern, threads, 0) != hipSuccess || per < 1) per = 1;
+    return cus * per;
+}
+
+template <int MODE>
+static int blocks_x()
+{
+    return resident_blocks(k_batch_x<MODE>, 256);
+}
+
+template <int MODE>
+static int blocks_col(int K)
+{
+    switch (K) {
+#define C4M_CASE(KK) case KK: return resident_blocks(k_batch_col<KK, MODE>, NTC);
+        C4M_CASE(1) C4M_CASE(2) C4M_CASE(3) C4M_CASE(4) C4M_CASE(5) C4M_CASE(6) C4M_CASE(7) C4M_CASE(8)
+#undef C4M_CASE
+    }
+    return 1;
+}
+
+template <int MODE>
+static hipError_t launch_bx(hipStream_t st, int blocks, const BatchProb* bp, const PhaseQueue& q, int total,
+                            int phase, const Coef& cf, const PadeTaps& taps)
+{
+    const int g = std::max(1, std::min(blocks, total));
+    hipLaunchKernelGGL(k_batch_x<MODE>, dim3(g), dim3(256), 0, st, bp, q, total, phase, cf, taps);
+    return hipGetLastError();
+}
+
+template <int MODE>
+static hipError_t launch_bc(int K, hipStream_t st, int blocks, const BatchProb* bp, const PhaseQueue& q,
+                            int total, int phase, const Coef& cf, const PadeTaps& taps, const ChebSchedule& cs)
+{
+    switch (K) {
+#define C4M_CASE(KK)                                                                                   \
+    case KK: {                                                                                         \
+        const int g = std::max(1, std::min(blocks, total));                                           \
+        hipLaunchKernelGGL((k_batch_col<KK, MODE>), dim3(g), dim3(NTC), 0, st, bp, q, total, phase, cf, \
+                           taps, cs);                                                                  \
+        break;                                                                                         \
+    }
+        C4M_CASE(1) C4M_CASE(2) C4M_CASE(3) C4M_CASE(4) C4M_CASE(5) C4M_CASE(6) C4M_CASE(7) C4M_CASE(8)
+#undef C4M_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace c4m
+
+using namespace c4m;
+
+// Internal hooks of the single-problem runtime (c4m_host.hip).
+namespace c4m {
+c4m_status problem_view(c4m_problem* p, ProblemView* v);
+c4m_status problem_prepare(c4m_problem* p);     // carried-Laplacian conversion before stepping
+c4m_status problem_create_owned(const c4m_config* cfg, void* ws, size_t bytes, hipStream_t st,
+                                c4m_problem** out);
+void problem_add_steps(c4m_problem* p, int64_t n);
+void problem_destroy_owned(c4m_problem* p);
+c4m_status set_error(c4m_status s, const char* msg);
+}  // namespace c4m
+
+struct c4m_batch {
+    int count = 0;
+    c4m_config base{};
+    hipStream_t stream = nullptr;
+    std::vector<c4m_problem*> probs;
+    BatchProb* d_probs = nullptr;
+    int* d_prefix = nullptr;       // [NPH][count + 1]
+    int* d_ctr = nullptr;          // [NPH][2] (each on its own 64-byte line)
+    int total[NPH] = {};
+    Coef coef{};
+    PadeTaps taps_xe{}, taps_xh{};
+    ChebSchedule cheb{};
+    int blocks[NPH] = {};           // workgroups of each persistent launch
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+size_t a256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+c4m_status check_uniform(const c4m_config* cfgs, int32_t count)
+{
+    if (!cfgs || count < 1) return set_error(C4M_EINVAL, "empty batch");
+    for (int i = 0; i < count; ++i) {
+        const c4m_config& c = cfgs[i];
+        if (c.dim != 2) return set_error(C4M_EINVAL, "batched form takes 2D problems");
+        if (c.cfl != cfgs[0].cfl || c.z != cfgs[0].z || c.closure != cfgs[0].closure ||
+            c.lap_mode != cfgs[0].lap_mode || c.precision != cfgs[0].precision ||
+            c.solver != cfgs[0].solver || c.sweeps != cfgs[0].sweeps)
+            return set_error(C4M_EINVAL, "batched problems must share cfl, z, closure, lap_mode, precision, solver");
+        size_t b = 0;
+        c4m_status s = c4m_workspace_bytes(&c, &b);
+        if (s != C4M_OK) return s;
+    }
+    return C4M_OK;
+}
+
+size_t tables_bytes(int count)
+{
+    return a256(sizeof(BatchProb) * count) + a256(sizeof(int) * NPH * (count + 1)) + a256(NPH * 64);
+}
+
+c4m_status launch_step(c4m_batch* b)
+{
+    const bool tracked = b->base.lap_mode == C4M_LAP_TRACKED;
+    const int K = b->cheb.sweeps;
+    hipError_t e = hipSuccess;
+    for (int ph = 0; ph < NPH && e == hipSuccess; ++ph) {
+        if (!b->total[ph]) continue;
+        PhaseQueue q{b->d_prefix + ph * (b->count + 1), b->count, b->d_ctr + ph * 16};
+        const BatchProb* bp = b->d_probs;
+        const int nb = b->blocks[ph];
+        const int tot = b->total[ph];
+        switch (ph) {
+            case PH_XE:
+                e = tracked ? launch_bx<XL_E_TRACKED>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe)
+                            : launch_bx<XL_E_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe);
+                break;
+            case PH_CE:
+                e = tracked ? launch_bc<COL_E_TRACKED>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb)
+                            : launch_bc<COL_E_DISCRETE>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb);
+                break;
+            case PH_XH:
+                e = tracked ? launch_bx<XL_H_TRACKED>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh)
+                            : launch_bx<XL_H_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh);
+                break;
+            case PH_CHX:
+                e = tracked ? launch_bc<COL_HX_TRACKED>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb)
+                            : launch_bc<COL_HX_DISCRETE>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
+                break;
+            default:
+                e = launch_bc<COL_HY>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
+                break;
+        }
+    }
+    return e == hipSuccess ? C4M_OK : set_error(C4M_EDEVICE, hipGetErrorString(e));
+}
+
+}  // namespace
 
 extern "C" {
-c4m_status c4m_batch_workspace_bytes(const c4m_config*, int32_t, size_t*) { return C4M_EINVAL; }
-c4m_status c4m_batch_create(const c4m_config*, int32_t, void*, size_t, void*, c4m_batch**) { return C4M_EINVAL; }
-c4m_status c4m_batch_problem(c4m_batch*, int32_t, c4m_problem**) { return C4M_EINVAL; }
-c4m_status c4m_batch_step(c4m_batch*, int64_t) { return C4M_EINVAL; }
-c4m_status c4m_batch_destroy(c4m_batch*) { return C4M_EINVAL; }
+
+c4m_status c4m_batch_workspace_bytes(const c4m_config* cfgs, int32_t count, size_t* bytes)
+{
+    c4m_status s = check_uniform(cfgs, count);
+    if (s != C4M_OK) return s;
+    if (!bytes) return set_error(C4M_EINVAL, "null bytes");
+    size_t tot = tables_bytes(count);
+    for (int i = 0; i < count; ++i) {
+        size_t b = 0;
+        c4m_workspace_bytes(&cfgs[i], &b);
+        tot += a256(b);
+    }
+    *bytes = tot;
+    return C4M_OK;
 }
+
+c4m_status c4m_batch_create(const c4m_config* cfgs, int32_t count, void* d_workspace, size_t bytes,
+                            void* hip_stream, c4m_batch** out)
+{
+    if (!out) return set_error(C4M_EINVAL, "null out");
+    *out = nullptr;
+    size_t need = 0;
+    c4m_status s = c4m_batch_workspace_bytes(cfgs, count, &need);
+    if (s != C4M_OK) return s;
+    if (!d_workspace || ((uintptr_t)d_workspace & 255)) return set_error(C4M_EINVAL, "workspace must be 256-byte aligned");
+    if (bytes < need) return set_error(C4M_ENOMEM, "workspace smaller than c4m_batch_workspace_bytes");
+    c4m_batch* b = new (std::nothrow) c4m_batch();
+    if (!b) return set_error(C4M_ENOMEM, "host allocation");
+    b->count = count;
+    b->base = cfgs[0];
+    b->stream = (hipStream_t)hip_stream;
+    char* cur = (char*)d_workspace;
+    b->d_probs = (BatchProb*)cur;
+    cur += a256(sizeof(BatchProb) * count);
+    b->d_prefix = (int*)cur;
+    cur += a256(sizeof(int) * NPH * (count + 1));
+    b->d_ctr = (int*)cur;
+    cur += a256(NPH * 64);
+    std::vector<BatchProb> hp(count);
+    std::vector<int> prefix((size_t)NPH * (count + 1), 0);
+    for (int i = 0; i < count && s == C4M_OK; ++i) {
+        size_t pb = 0;
+        c4m_workspace_bytes(&cfgs[i], &pb);
+        c4m_problem* p = nullptr;
+        s = problem_create_owned(&cfgs[i], cur, pb, b->stream, &p);
+        if (s != C4M_OK) break;
+        cur += a256(pb);
+        b->probs.push_back(p);
+        ProblemView v{};
+        problem_view(p, &v);
+        const int N = v.N;
+        const bool tracked = cfgs[i].lap_mode == C4M_LAP_TRACKED;
+        BatchProb& d = hp[i];
+        d.xe = XArgs{v.f[C4M_HY], v.tmp[0], v.tmp[1], N, v.P, v.line[1]};
+        d.xh = XArgs{tracked ? v.ge[2] : v.f[C4M_EZ], v.tmp[0], v.tmp[1], N, v.P, v.line[0]};
+        d.ce = ColArgs{v.f[C4M_HX], v.tmp[0], v.tmp[1], v.f[C4M_EZ], v.ge[2], ugrid_ez(N), N, v.P};
+        d.chx = ColArgs{tracked ? v.ge[2] : v.f[C4M_EZ], nullptr, nullptr, v.f[C4M_HX], nullptr, ugrid_hx(N), N, v.P};
+        d.chy = ColArgs{nullptr, v.tmp[1], nullptr, v.f[C4M_HY], nullptr, ugrid_hy(N), N, v.P};
+        const int K = v.cheb.sweeps;
+        int tiles[NPH];
+        d.tiles_x[PH_XE] = xlines_tiles_x(v.line[1].n_out);
+        tiles[PH_XE] = d.tiles_x[PH_XE] * xlines_tiles_y(N);
+        tiles[PH_CE] = col_tiles_k(K, d.ce.g, &d.tiles_x[PH_CE]);
+        d.tiles_x[PH_XH] = xlines_tiles_x(v.line[0].n_out);
+        tiles[PH_XH] = d.tiles_x[PH_XH] * xlines_tiles_y(N);
+        tiles[PH_CHX] = col_tiles_k(K, d.chx.g, &d.tiles_x[PH_CHX]);
+        tiles[PH_CHY] = col_tiles_k(K, d.chy.g, &d.tiles_x[PH_CHY]);
+        for (int ph = 0; ph < NPH; ++ph)
+            prefix[(size_t)ph * (count + 1) + i + 1] = prefix[(size_t)ph * (count + 1) + i] + tiles[ph];
+        if (i == 0) {
+            b->coef = v.coef;
+            b->taps_xe = v.taps[1];
+            b->taps_xh = v.taps[0];
+            b->cheb = v.cheb;
+        }
+    }
+    if (s != C4M_OK) {
+        for (auto* p : b->probs) problem_destroy_owned(p);
+        delete b;
+        return s;
+    }
+    for (int ph = 0; ph < NPH; ++ph) b->total[ph] = prefix[(size_t)ph * (count + 1) + count];
+    {
+        const bool tracked = b->base.lap_mode == C4M_LAP_TRACKED;
+        const int K = b->cheb.sweeps;
+        b->blocks[PH_XE] = tracked ? blocks_x<XL_E_TRACKED>() : blocks_x<XL_E_DISCRETE>();
+        b->blocks[PH_CE] = tracked ? blocks_col<COL_E_TRACKED>(K) : blocks_col<COL_E_DISCRETE>(K);
+        b->blocks[PH_XH] = tracked ? blocks_x<XL_H_TRACKED>() : blocks_x<XL_H_DISCRETE>();
+        b->blocks[PH_CHX] = tracked ? blocks_col<COL_HX_TRACKED>(K) : blocks_col<COL_HX_DISCRETE>(K);
+        b->blocks[PH_CHY] = blocks_col<COL_HY>(K);
+    }
+    hipError_t e = hipMemcpyAsync(b->d_probs, hp.data(), sizeof(BatchProb) * count, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_prefix, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_ctr, 0, NPH * 64, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        for (auto* p : b->probs) problem_destroy_owned(p);
+        delete b;
+        return set_error(C4M_EDEVICE, hipGetErrorString(e));
+    }
+    *out = b;
+    return C4M_OK;
+}
+
+c4m_status c4m_batch_problem(c4m_batch* b, int32_t i, c4m_problem** out)
+{
+    if (!b || !out || i < 0 || i >= b->count) return set_error(C4M_EINVAL, "bad batch index");
+    *out = b->probs[i];
+    return C4M_OK;
+}
+
+c4m_status c4m_batch_step(c4m_batch* b, int64_t nsteps)
+{
+    if (!b || nsteps < 0) return set_error(C4M_EINVAL, "bad step count");
+    for (auto* p : b->probs) {
+        c4m_status s = problem_prepare(p);
+        if (s != C4M_OK) return s;
+    }
+    if (nsteps == 0) return C4M_OK;
+    // one step captured once as a graph, then replayed
+    if (!b->exec) {
+        hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return set_error(C4M_EDEVICE, "hipStreamBeginCapture");
+        c4m_status s = launch_step(b);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->stream, &g);
+        if (s != C4M_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return set_error(C4M_EDEVICE, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            b->exec = nullptr;
+            return set_error(C4M_EDEVICE, "hipGraphInstantiate");
+        }
+        b->graph = g;
+    }
+    for (int64_t t = 0; t < nsteps; ++t) {
+        hipError_t e = hipGraphLaunch(b->exec, b->stream);
+        if (e != hipSuccess) return set_error(C4M_EDEVICE, "hipGraphLaunch");
+    }
+    for (auto* p : b->probs) problem_add_steps(p, nsteps);
+    return C4M_OK;
+}
+
+c4m_status c4m_batch_destroy(c4m_batch* b)
+{
+    if (!b) return set_error(C4M_EINVAL, "null batch");
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (auto* p : b->probs) problem_destroy_owned(p);
+    delete b;
+    return C4M_OK;
+}
+
+}  // extern "C"

@@ -774,5 +774,46 @@ c4m_status c4m_destroy(c4m_problem* p)
     return C4M_OK;
 }
 
-// batched form: filled in by c4m_batch.hip
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Hooks used by the batched form (c4m_batch.hip).
+// ---------------------------------------------------------------------------
+namespace c4m {
+
+c4m_status set_error(c4m_status s, const char* msg) { return fail(s, msg); }
+
+c4m_status problem_view(c4m_problem* p, ProblemView* v)
+{
+    for (int i = 0; i < 6; ++i) v->f[i] = p->f[i];
+    for (int i = 0; i < 3; ++i) v->ge[i] = p->ge[i];
+    for (int i = 0; i < 5; ++i) v->tmp[i] = p->tmp[i];
+    v->N = p->N;
+    v->P = p->P;
+    for (int k = 0; k < 2; ++k) {
+        v->line[k] = p->line[k];
+        v->taps[k] = p->pade_host[k].taps;
+    }
+    v->coef = p->coef;
+    v->cheb = p->cheb;
+    return C4M_OK;
+}
+
+c4m_status problem_prepare(c4m_problem* p) { return ensure_ge(p); }
+
+c4m_status problem_create_owned(const c4m_config* cfg, void* ws, size_t bytes, hipStream_t st,
+                                c4m_problem** out)
+{
+    c4m_status s = c4m_create(cfg, ws, bytes, (void*)st, out);
+    if (s == C4M_OK) (*out)->owned_by_batch = true;
+    return s;
+}
+
+void problem_add_steps(c4m_problem* p, int64_t n) { p->steps += n; }
+
+void problem_destroy_owned(c4m_problem* p)
+{
+    (void)flush_profile(p);
+    delete p;
+}
+}  // namespace c4m

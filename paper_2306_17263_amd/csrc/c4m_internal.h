@@ -92,4 +92,16 @@ struct Cheb3 {
     size_t plane;
 };
 
+// Internal view of a problem for the batched form (c4m_host.hip fills it).
+struct ProblemView {
+    double* f[6];
+    double* ge[3];
+    double* tmp[5];
+    int N, P;
+    PadeLine line[2];
+    PadeTaps taps[2];
+    Coef coef;
+    ChebSchedule cheb;
+};
+
 }  // namespace c4m

@@ -1,436 +1,21 @@
-// c4m_kernels_2d.hip -- gfx950 kernels of the 2D TM (Ez, Hx, Hy) step.
-//
-// Step 1 (Section 3.4), two launches:
-//   k_xlines<E>  : rows of Hy -> T0 = Z delta_x G(Hy), T1 = delta_x Hy (carried l)
-//   k_col<E>     : per column of Hx the y-line Pade (streaming FIR in
-//                  registers) completes b = T0 - Z delta_y G(Hx); then the
-//                  Chebyshev solve of M Phi = b on the tile and its halo,
-//                  Ez += r Phi, G_E += (1 + 4/r^2) r Phi - (2/r) Z curl^A H.
-// Step 2, three launches:
-//   k_xlines<H>  : rows of G_E -> T1 = (1/Z) delta_x G_E        (Hy right-hand side)
-//   k_col<HX>    : columns of G_E -> b = -(1/Z) delta_y G_E, solve, Hx += r Phi
-//   k_col<HY>    : b = T1, solve, Hy += r Phi
-// G_E = alpha E + l/12 is stored instead of l, so Step 2 reads only G_E.
-//
-// Pade derivative: A^{-1} D truncated to 2 PADE_R + 2 taps on the line
-// values (exact rows near the two ends of each line from a table).
-// Source conditioning G u = alpha u + (L5 u)/12 is split by axis: the part
-// along the line is folded into the line input, the part across the line is
-// applied to the line derivatives of the neighbouring lines (the line
-// derivative is the same linear map on every line, so the two commute).
-//
-// k_col layout: one lane per column of a 256-column region, each lane holds
-// the region rows of its column in registers; only the column sums
-// S = d(y-1) + 4 d(y) + d(y+1) of the 9-point stencil cross lanes (LDS).
-#include "c4m_internal.h"
+// c4m_kernels_2d.hip -- single-problem launches of the 2D TM kernels (the
+// tile code lives in c4m_tiles_2d.h and is shared with the batched form).
+#include "c4m_tiles_2d.h"
 
 namespace c4m {
 
-__device__ __forceinline__ const double* pade_row(const PadeLine& L, int m)
-{
-    if (L.all) return L.rows + (size_t)m * PADE_TAPS;
-    if (m < L.b) return L.rows + (size_t)m * PADE_TAPS;
-    if (m >= L.n_out - L.b) return L.rows + (size_t)(m - (L.n_out - L.b) + L.b) * PADE_TAPS;
-    return nullptr;
-}
-
-__device__ __forceinline__ bool pade_interior(const PadeLine& L, int m_lo, int m_hi)
-{
-    // every output in [m_lo, m_hi] uses the interior taps
-    return !L.all && m_lo >= L.b && m_hi < L.n_out - L.b;
-}
-
-// ===========================================================================
-// x-lines.  Tile: 32 rows x 64 outputs, 256 threads; thread (row = t % 32,
-// seg = t / 32) computes 8 consecutive outputs from a 33-value register
-// window.  Lanes 0..15 and 16..31 of a wave read 16 consecutive rows at the
-// same column, and the odd LDS row stride keeps those reads conflict-free.
-// ===========================================================================
-constexpr int XT_ROWS = 32;
-constexpr int XT_OUT = 64;
-constexpr int XT_SEG = 8;
-constexpr int XT_IN = XT_OUT + 2 * PADE_R + 2;     // staged inputs per row
-constexpr int XT_STRIDE = XT_IN + 1;               // odd
-constexpr int XT_WIN = XT_SEG + PADE_TAPS - 1;
-
-enum { XL_E_TRACKED = 0, XL_E_DISCRETE = 1, XL_H_TRACKED = 2, XL_H_DISCRETE = 3 };
-
 template <int MODE>
-__global__ __launch_bounds__(256) void k_xlines(const double* __restrict__ src, double* __restrict__ t0,
-                                                double* __restrict__ t1, int N, int P, Coef cf,
-                                                PadeTaps taps, PadeLine L)
+__global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps)
 {
-    constexpr bool E = MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE;
-    constexpr bool TWO = MODE == XL_E_TRACKED;     // raw derivative as well
-    __shared__ double sg[XT_ROWS * XT_STRIDE];
-    __shared__ double sr[TWO ? XT_ROWS * XT_STRIDE : 1];
-    const int tid = threadIdx.x;
-    const int m0 = blockIdx.x * XT_OUT;             // first output of the tile
-    const int j0 = 1 + blockIdx.y * XT_ROWS;        // first row (interior rows 1..N-1)
-    const int n_in = L.n_in;
-    // ---- stage the conditioned line input (and the raw one)
-    for (int e = tid; e < XT_ROWS * XT_IN; e += 256) {
-        const int rr = e / XT_IN, q = e - rr * XT_IN;
-        const int j = j0 + rr, g = m0 - PADE_R + q;
-        double vg = 0.0, vr = 0.0;
-        if (j <= N - 1 && g >= 0 && g < n_in) {
-            const double* row = src + (size_t)j * P;
-            if (E) {
-                // Hy at half points along x: even ghosts at both ends
-                const double h0 = row[g];
-                const double hl = row[g > 0 ? g - 1 : 0];
-                const double hr = row[g < n_in - 1 ? g + 1 : n_in - 1];
-                const double hs = row[g - P];
-                const double hn = row[g + P];
-                vr = h0;
-                vg = fma(cf.alpha, h0, (hl + hr + hs + hn - 4.0 * h0) * (1.0 / 12.0));
-            } else if (MODE == XL_H_TRACKED) {
-                vg = row[g];                                       // stored G_E
-            } else {
-                // alpha E + L5 E / 12, zero on the walls (nodes 0 and N)
-                if (g > 0 && g < n_in - 1) {
-                    const double e0 = row[g];
-                    vg = fma(cf.alpha, e0, (row[g - 1] + row[g + 1] + row[g - P] + row[g + P] - 4.0 * e0) *
-                                               (1.0 / 12.0));
-                }
-            }
-        }
-        sg[rr * XT_STRIDE + q] = vg;
-        if (TWO) sr[rr * XT_STRIDE + q] = vr;
-    }
-    __syncthreads();
-    const int row = tid % XT_ROWS;
-    const int seg = tid / XT_ROWS;
-    const int mb = m0 + seg * XT_SEG;
-    double outg[XT_SEG], outr[XT_SEG];
-    const double* wg = sg + row * XT_STRIDE + seg * XT_SEG;
-    const double* wr = sr + row * XT_STRIDE + seg * XT_SEG;
-    if (pade_interior(L, mb, mb + XT_SEG - 1)) {
-        double w[XT_WIN];
-#pragma unroll
-        for (int u = 0; u < XT_WIN; ++u) w[u] = wg[u];
-#pragma unroll
-        for (int k = 0; k < XT_SEG; ++k) {
-            double a = 0.0;
-#pragma unroll
-            for (int u = 0; u < PADE_TAPS; ++u) a = fma(taps.c[u], w[k + u], a);
-            outg[k] = a;
-        }
-        if (TWO) {
-#pragma unroll
-            for (int u = 0; u < XT_WIN; ++u) w[u] = wr[u];
-#pragma unroll
-            for (int k = 0; k < XT_SEG; ++k) {
-                double a = 0.0;
-#pragma unroll
-                for (int u = 0; u < PADE_TAPS; ++u) a = fma(taps.c[u], w[k + u], a);
-                outr[k] = a;
-            }
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < XT_SEG; ++k) {
-            const int m = mb + k;
-            double a = 0.0, b = 0.0;
-            if (m < L.n_out) {
-                const double* cr = pade_row(L, m);
-                for (int u = 0; u < PADE_TAPS; ++u) {
-                    const double c = cr ? cr[u] : taps.c[u];
-                    a = fma(c, wg[k + u], a);
-                    if (TWO) b = fma(c, wr[k + u], b);
-                }
-            }
-            outg[k] = a;
-            outr[k] = b;
-        }
-    }
-    // ---- write through the LDS so that a wave stores contiguous row segments:
-    // E step -> node i = m + 1; H step -> half point i = m
-    __syncthreads();
-    constexpr int OS = XT_OUT + 1;
-    double* og = sg;                        // [XT_ROWS][OS], reuses the staging area
-    double* orw = TWO ? sr : sg;
-#pragma unroll
-    for (int k = 0; k < XT_SEG; ++k) {
-        og[row * OS + seg * XT_SEG + k] = outg[k];
-        if (TWO) orw[row * OS + seg * XT_SEG + k] = outr[k];
-    }
-    __syncthreads();
-    const int ioff = E ? 1 : 0;
-    const double scale = E ? cf.z : 1.0 / cf.z;
-    double* o0 = E ? t0 : t1;
-    for (int e = tid; e < XT_ROWS * XT_OUT; e += 256) {
-        const int rr = e / XT_OUT, c = e - rr * XT_OUT;
-        const int jj = j0 + rr, m = m0 + c;
-        if (jj <= N - 1 && m < L.n_out) {
-            o0[(size_t)jj * P + m + ioff] = scale * og[rr * OS + c];
-            if (TWO) t1[(size_t)jj * P + m + ioff] = orw[rr * OS + c];
-        }
-    }
+    xlines_tile<MODE>(xa, cf, taps, blockIdx.x, blockIdx.y);
 }
-
-// ===========================================================================
-// Column kernel: y-line Pade + Chebyshev solve + update.
-// A workgroup covers a region of CW = 128 columns and TR rows.  The column
-// of region row r is held by NL lanes: lane (c, q) keeps rows
-// [q HR, (q+1) HR) of column c in registers.  The rows next to a split
-// cross through a small double-buffered LDS array, the column sums
-// S = d(y-1) + 4 d(y) + d(y+1) of the 9-point stencil cross between
-// columns through the LDS (padded rows, zero sentinels at both ends).
-// ===========================================================================
-constexpr int CW = 128;      // region width (columns)
-constexpr int CWP = CW + 2;  // LDS row stride
-constexpr int NL = 4;        // lanes per column
-constexpr int NTC = CW * NL; // threads per workgroup
-
-// region rows for K sweeps: at least 16 output rows, a multiple of NL
-template <int K>
-struct ColShape {
-    static constexpr int TR = ((16 + 2 * K + NL - 1) / NL) * NL;
-    static constexpr int OH = TR - 2 * K;
-    static constexpr int HR = TR / NL;
-};
-
-enum { COL_E_TRACKED = 0, COL_E_DISCRETE = 1, COL_HX_TRACKED = 2, COL_HX_DISCRETE = 3, COL_HY = 4 };
-
-struct ColArgs {
-    const double* src;      // y-line source: Hx (E step) or G_E / Ez (Hx step)
-    const double* t0;       // precomputed right-hand side part (T0 or T1), or null
-    const double* t1;       // carried Laplacian: x part of curl^A H (E step)
-    double* field;          // Ez, Hx or Hy
-    double* ge;             // G_E (E step, carried Laplacian)
-    UGrid g;                // unknowns of the solved component
-    int N, P;
-};
 
 template <int K, int MODE>
-__global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(4))) void k_col(ColArgs a, Coef cf, PadeTaps taps, PadeLine L,
-                                             ChebSchedule cs)
+__global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(4))) void k_col(ColArgs a, Coef cf,
+                                                                                  PadeTaps taps, PadeLine L,
+                                                                                  ChebSchedule cs)
 {
-    constexpr int TR = ColShape<K>::TR;             // region rows
-    constexpr int OH = ColShape<K>::OH;             // output rows
-    constexpr int HR = ColShape<K>::HR;             // rows per lane
-    constexpr int HALO_X = K + 1;                   // column halo (one more for the cross-line term)
-    constexpr bool YPART = MODE != COL_HY;
-    constexpr bool SPLIT = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE || MODE == COL_HX_DISCRETE;
-    constexpr bool ESTEP = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE;
-    constexpr int NPOS = HR + PADE_TAPS - 1 + 2;    // streamed line positions (+1 each side for G)
-    __shared__ double lds[TR * CWP];
-    __shared__ double bnd[2][NL][2][CW];            // [parity][part][0: first row, 1: last row][column]
-
-    const int tid = threadIdx.x;
-    const int lane = tid % CW;                      // region column
-    const int part = tid / CW;                      // rows [part HR, (part+1) HR)
-    const int rbase = part * HR;
-    const int ow = CW - 2 * HALO_X;
-    const UGrid& g = a.g;
-    const int x0 = g.lo[0] + blockIdx.x * ow;
-    const int y0 = g.lo[1] + blockIdx.y * OH;
-    const int gx = x0 - HALO_X + lane;
-    const int P = a.P, N = a.N;
-    const bool col_active = gx >= g.lo[0] && gx < g.hi[0];
-    for (int e = tid; e < TR; e += NTC) {
-        lds[e * CWP] = 0.0;
-        lds[e * CWP + CW + 1] = 0.0;
-    }
-    double* my = lds + lane + 1 + rbase * CWP;      // this lane's first row
-
-    double r[HR];            // right-hand side, then the Chebyshev residual
-    double cv[HR];           // carried Laplacian: curl^A H on this lane's rows
-
-    // ---------------- right-hand side ----------------
-    if (YPART) {
-        const int n_in = L.n_in;
-        const int mofs = ESTEP ? 1 : 0;                     // gy = m + mofs
-        const int mfirst = y0 - K + rbase - mofs;           // Pade output index of this lane's row 0
-        const int gfirst = mfirst - PADE_R - 1;             // first streamed position
-        const bool col_data = gx >= 0 && gx <= N;           // a stored column (walls included)
-        const bool half_line = ESTEP;
-        const bool fast = pade_interior(L, mfirst < 0 ? 0 : mfirst, mfirst + HR - 1);
-        const double* colp = a.src + gx;
-        double f[NPOS];
-#pragma unroll
-        for (int p = 0; p < NPOS; ++p) {
-            const int gg = gfirst + p;
-            f[p] = (col_data && gg >= 0 && gg < n_in) ? colp[gg * P] : 0.0;
-        }
-        if (SPLIT) {
-            // raw line derivative P: its second difference across lines
-            // completes G; with the carried Laplacian it is also curl^A H
-#pragma unroll
-            for (int t = 0; t < HR; ++t) {
-                const int m = mfirst + t;
-                double ap = 0.0;
-                if (fast) {
-#pragma unroll
-                    for (int u = 0; u < PADE_TAPS; ++u) ap = fma(taps.c[u], f[t + 1 + u], ap);
-                } else if (m >= 0 && m < L.n_out) {
-                    const double* cr = pade_row(L, m);
-                    for (int u = 0; u < PADE_TAPS; ++u) ap = fma(cr ? cr[u] : taps.c[u], f[t + 1 + u], ap);
-                }
-                my[t * CWP] = ap;
-                cv[t] = ap;
-            }
-            // in place: f -> alpha f + (second difference along the line) / 12;
-            // half-point lines take even ghosts at their ends, node lines of
-            // E vanish on the walls
-            double prevf = 0.0;
-#pragma unroll
-            for (int p = 0; p < NPOS; ++p) {
-                const int gg = gfirst + p;
-                const double cur = f[p];
-                double lo = prevf, hi = (p < NPOS - 1) ? f[p + 1] : 0.0;
-                if (half_line) {
-                    if (gg == 0) lo = cur;
-                    if (gg == n_in - 1) hi = cur;
-                }
-                double v = fma(cf.alpha, cur, (lo + hi - 2.0 * cur) * (1.0 / 12.0));
-                if (gg < 0 || gg >= n_in || !col_data) v = 0.0;
-                if (!half_line && (gg == 0 || gg == n_in - 1)) v = 0.0;
-                f[p] = v;
-                prevf = cur;
-            }
-        }
-        // line derivative of the conditioned input
-#pragma unroll
-        for (int t = 0; t < HR; ++t) {
-            const int m = mfirst + t;
-            double aq = 0.0;
-            if (fast) {
-#pragma unroll
-                for (int u = 0; u < PADE_TAPS; ++u) aq = fma(taps.c[u], f[t + 1 + u], aq);
-            } else if (m >= 0 && m < L.n_out) {
-                const double* cr = pade_row(L, m);
-                for (int u = 0; u < PADE_TAPS; ++u) aq = fma(cr ? cr[u] : taps.c[u], f[t + 1 + u], aq);
-            }
-            r[t] = aq;
-        }
-        if (SPLIT) {
-            __syncthreads();
-            // cross-line part of G: (P(x-1) + P(x+1) - 2 P(x)) / 12
-#pragma unroll
-            for (int t = 0; t < HR; ++t) {
-                const double* q = my + t * CWP;
-                r[t] += (q[-1] + q[1] - 2.0 * q[0]) * (1.0 / 12.0);
-            }
-            __syncthreads();
-        }
-    }
-
-    // combine with the precomputed part and mask to the unknowns
-    const double ysign = ESTEP ? -cf.z : (MODE == COL_HY ? 0.0 : -1.0 / cf.z);
-#pragma unroll
-    for (int t = 0; t < HR; ++t) {
-        const int gy = y0 - K + rbase + t;
-        const bool act = col_active && gy >= g.lo[1] && gy < g.hi[1];
-        double v = 0.0;
-        if (act) {
-            const size_t o = (size_t)gy * P + gx;
-            v = YPART ? ysign * r[t] : 0.0;
-            if (a.t0) v += a.t0[o];
-        }
-        r[t] = v;
-    }
-    if (MODE == COL_E_TRACKED) {
-#pragma unroll
-        for (int t = 0; t < HR; ++t) {
-            const int row = rbase + t;
-            const int gy = y0 - K + row;
-            double v = 0.0;
-            if (row >= K && row < K + OH && col_active && gy < g.hi[1]) v = a.t1[(size_t)gy * P + gx] - cv[t];
-            cv[t] = v;
-        }
-    }
-
-    // ---------------- Chebyshev on [alpha, alpha + 16/3 beta] ----------------
-    // L9 d = (S(x-1) + S(x+1) + 4 S(x) - 36 d) / 6; A d = alpha d - beta L9 d.
-    const double b6 = cf.beta * (1.0 / 6.0);
-    const double a36 = fma(36.0, b6, cf.alpha);
-    const bool nx = g.neumann[0], ny = g.neumann[1];
-    const bool at_lo_x = gx == g.lo[0], at_hi_x = gx == g.hi[0] - 1;
-    const int rx0 = x0 - HALO_X, ry0 = y0 - K;
-    const bool inner = rx0 > g.lo[0] && rx0 + CW < g.hi[0] && ry0 > g.lo[1] && ry0 + TR < g.hi[1];
-    double d[HR], xs[HR], sown[HR];
-#pragma unroll
-    for (int t = 0; t < HR; ++t) {
-        d[t] = r[t] * cs.inv_theta;
-        xs[t] = 0.0;
-    }
-    bnd[0][part][0][lane] = d[0];
-    bnd[0][part][1][lane] = d[HR - 1];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int par = k & 1;
-        const double above = part > 0 ? bnd[par][part - 1][1][lane] : 0.0;
-        const double below = part < NL - 1 ? bnd[par][part + 1][0][lane] : 0.0;
-        const double c1 = cs.c1[k], c2 = cs.c2[k];
-        if (inner) {
-#pragma unroll
-            for (int t = 0; t < HR; ++t) {
-                const double up = t > 0 ? d[t - 1] : above;
-                const double dn = t < HR - 1 ? d[t + 1] : below;
-                sown[t] = fma(4.0, d[t], up + dn);
-                my[t * CWP] = sown[t];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int t = 0; t < HR; ++t) {
-                const double* q = my + t * CWP;
-                const double side = q[-1] + q[1];
-                const double dc = d[t];
-                const double ad = fma(a36, dc, -b6 * fma(4.0, sown[t], side));
-                xs[t] += dc;
-                r[t] -= ad;
-                d[t] = fma(c1, dc, c2 * r[t]);
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < HR; ++t) {
-                const int gy = ry0 + rbase + t;
-                double up = t > 0 ? d[t - 1] : above;
-                double dn = t < HR - 1 ? d[t + 1] : below;
-                if (ny && gy == g.lo[1]) up = d[t];
-                if (ny && gy == g.hi[1] - 1) dn = d[t];
-                sown[t] = fma(4.0, d[t], up + dn);
-                my[t * CWP] = sown[t];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int t = 0; t < HR; ++t) {
-                const int gy = ry0 + rbase + t;
-                const double* q = my + t * CWP;
-                const double sc = sown[t];
-                double sl = q[-1], sr = q[1];
-                if (nx && at_lo_x) sl = sc;
-                if (nx && at_hi_x) sr = sc;
-                const double dc = d[t];
-                const double ad = fma(a36, dc, -b6 * fma(4.0, sc, sl + sr));
-                const bool act = col_active && gy >= g.lo[1] && gy < g.hi[1];
-                xs[t] += dc;
-                const double rn = r[t] - ad;
-                r[t] = act ? rn : 0.0;
-                d[t] = act ? fma(c1, dc, c2 * rn) : 0.0;
-            }
-        }
-        bnd[par ^ 1][part][0][lane] = d[0];
-        bnd[par ^ 1][part][1][lane] = d[HR - 1];
-        __syncthreads();
-    }
-
-    // ---------------- update ----------------
-    if (lane < HALO_X || lane >= CW - HALO_X || !col_active) return;
-#pragma unroll
-    for (int t = 0; t < HR; ++t) {
-        const int row = rbase + t;
-        if (row < K || row >= K + OH) continue;
-        const int gy = y0 - K + row;
-        if (gy >= g.hi[1]) continue;
-        const size_t o = (size_t)gy * P + gx;
-        const double de = cf.cfl * (xs[t] + d[t]);
-        a.field[o] += de;
-        if (MODE == COL_E_TRACKED) a.ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cv[t]);
-    }
+    col_tile<K, MODE>(a, cf, taps, L, cs, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
@@ -467,14 +52,13 @@ hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const
                            const PadeLine& line_h2n)
 {
     // x-lines of Hy: N inputs, N-1 outputs, rows 1..N-1
-    dim3 grid((N - 1 + XT_OUT - 1) / XT_OUT, (N - 1 + XT_ROWS - 1) / XT_ROWS);
+    dim3 grid(xlines_tiles_x(line_h2n.n_out), xlines_tiles_y(N));
     (void)hx;
+    const XArgs xa{hy, t0, t1, N, P, line_h2n};
     if (tracked)
-        hipLaunchKernelGGL(k_xlines<XL_E_TRACKED>, grid, dim3(256), 0, st, hy, t0, t1, N, P, cf, taps,
-                           line_h2n);
+        hipLaunchKernelGGL(k_xlines<XL_E_TRACKED>, grid, dim3(256), 0, st, xa, cf, taps);
     else
-        hipLaunchKernelGGL(k_xlines<XL_E_DISCRETE>, grid, dim3(256), 0, st, hy, t0, t1, N, P, cf, taps,
-                           line_h2n);
+        hipLaunchKernelGGL(k_xlines<XL_E_DISCRETE>, grid, dim3(256), 0, st, xa, cf, taps);
     return hipGetLastError();
 }
 
@@ -493,13 +77,12 @@ hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, doub
                            const PadeLine& line_n2h)
 {
     // x-lines of G_E: N+1 inputs, N outputs (Hy half points), rows 1..N-1
-    dim3 grid((N + XT_OUT - 1) / XT_OUT, (N - 1 + XT_ROWS - 1) / XT_ROWS);
+    dim3 grid(xlines_tiles_x(line_n2h.n_out), xlines_tiles_y(N));
+    const XArgs xa{src, t0, t1, N, P, line_n2h};
     if (tracked)
-        hipLaunchKernelGGL(k_xlines<XL_H_TRACKED>, grid, dim3(256), 0, st, src, t0, t1, N, P, cf, taps,
-                           line_n2h);
+        hipLaunchKernelGGL(k_xlines<XL_H_TRACKED>, grid, dim3(256), 0, st, xa, cf, taps);
     else
-        hipLaunchKernelGGL(k_xlines<XL_H_DISCRETE>, grid, dim3(256), 0, st, src, t0, t1, N, P, cf, taps,
-                           line_n2h);
+        hipLaunchKernelGGL(k_xlines<XL_H_DISCRETE>, grid, dim3(256), 0, st, xa, cf, taps);
     return hipGetLastError();
 }
 

@@ -42,9 +42,16 @@ class Problem:
     """One PEC cavity problem resident on the device."""
 
     def __init__(self, dim: int = 2, n: int = 64, cfl: float = 0.5, *, device="cuda",
-                 stream=None, **kw):
+                 stream=None, _borrowed=None, **kw):
         self._lib = L.load()
         self.cfg = make_config(dim, n, cfl, **kw)
+        self._owned = _borrowed is None
+        if _borrowed is not None:             # a member of a Batch: handle owned by the batch
+            self.device = torch.device(device)
+            self.stream = stream
+            self._h = _borrowed
+            self.dim, self.n, self.cfl = dim, n, cfl
+            return
         self.device = torch.device(device)
         self.nbytes = workspace_bytes(self.cfg)
         self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
@@ -60,9 +67,9 @@ class Problem:
         return self._h
 
     def close(self):
-        if self._h:
+        if self._h and self._owned:
             L.check(self._lib.c4m_destroy(self._h), "c4m_destroy")
-            self._h = ctypes.c_void_p()
+        self._h = ctypes.c_void_p()
 
     def __del__(self):
         try:
