@@ -78,7 +78,16 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="2d", choices=["2d", "batch", "3d"],
+                    help="2d: the N=2048 refinement-sweep cavity (default); batch: 512 seeded 2D "
+                         "cavities of uneven N; 3d: the cube cavity")
+    ap.add_argument("--count", type=int, default=512)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
     args = ap.parse_args()
+    if args.workload == "batch":
+        return bench_batch(args)
+    if args.workload == "3d":
+        return bench_3d(args)
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -209,6 +218,170 @@ def main():
         "parity_sample": parity,
         "roofline": roofline,
         "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def _cpu_cores():
+    return len(os.sched_getaffinity(0))
+
+
+def bench_batch(args):
+    """Batched form: seeded mix of independent 2D TM cavities, N uniform in
+    64..768, modes (k, l) in 1..8, amplitude U(0.5, 2), CFL 0.5, 200 steps
+    each, one persistent launch per phase and a HIP graph per step, launch
+    shape from the autotuner."""
+    import torch
+    from paper_2306_17263_amd import Batch, Problem, autotune
+    from workloads import batch_mix, mode_fields
+    specs = batch_mix(count=args.count)
+    steps = args.steps if args.steps is not None else 200
+    st = torch.cuda.Stream()
+    settings = dict(closure=args.closure, lap_mode=args.lap, precision=args.precision)
+    tuned = autotune.tune_batch([{"n": s["n"]} for s in specs], steps=2, **settings)
+    b = Batch(specs, stream=st, tile_x=tuned["tile_x"], tile_y=tuned["tile_y"], **settings)
+    inits = []
+    for p, s in zip(b.problems, specs):
+        h = 1.0 / s["n"]
+        init = mode_fields(2, s["n"], s["k"], 0.0, s["r"] * h / 2, amp=s["amp"])
+        inits.append(init)
+        for name in p.fields():
+            p.set(name, init[name])
+    b.step(args.warmup)
+    for p, init in zip(b.problems, inits):
+        for name in p.fields():
+            p.set(name, init[name])
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(st)
+    b.step(steps)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    elapsed = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3)
+    cells = sum(s["n"] ** 2 for s in specs)
+    value = cells * steps / elapsed / 1e6
+    # accuracy of every problem against its exact mode at the final time
+    names = ["ez", "hx", "hy"]
+    errs = []
+    for p, s in zip(b.problems, specs):
+        h = 1.0 / s["n"]
+        ht = s["r"] * h
+        ex = mode_fields(2, s["n"], s["k"], steps * ht, (steps + 0.5) * ht, amp=s["amp"], with_laplacian=False)
+        errs.append(rel_l2({a: p.get(a) for a in names}, ex, names))
+    # the same problems one after another through the single-problem path
+    t1 = time.perf_counter()
+    for s, init in zip(specs, inits):
+        q = Problem(2, s["n"], s["r"], stream=st, **settings)
+        for name in q.fields():
+            q.set(name, init[name])
+        q.step(steps)
+    torch.cuda.synchronize()
+    seq = time.perf_counter() - t1
+    cpu = parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        sub = sorted(range(len(specs)), key=lambda i: specs[i]["n"])[:3]
+        parity = []
+        for i in sub:
+            s = specs[i]
+            o = oracle.OracleProblem(2, s["n"], s["r"], 1.0)
+            for name in o.fields():
+                o.set(name, inits[i][name])
+            o.step(steps)
+            parity.append({"n": s["n"], "rel_l2_vs_oracle":
+                           rel_l2({a: b.problems[i].get(a) for a in names}, {a: o.get(a) for a in names}, names)})
+        rng = np.random.default_rng(2306)
+        sample = sorted(rng.choice(len(specs), 32, replace=False).tolist())
+        t2 = time.perf_counter()
+        done = 0
+        for i in sample:
+            s = specs[i]
+            o = oracle.OracleProblem(2, s["n"], s["r"], 1.0)
+            for name in o.fields():
+                o.set(name, inits[i][name])
+            o.step(2)
+            done += s["n"] ** 2 * 2
+            if time.perf_counter() - t2 > args.cpu_seconds:
+                break
+        spent = time.perf_counter() - t2
+        cpu = {"value": round(done / spent / 1e6, 3), "unit": "Mcell-steps/s", "cores": _cpu_cores(), "kind": "oracle",
+               "sample": f"2 steps of each of up to 32 seeded problems of the mix ({spent:.1f} s)"}
+    b.close()
+    line = {
+        "metric": "Mcell-steps/s at fixed L2 error vs FP64 oracle + % HBM roofline",
+        "value": round(value, 2), "unit": "Mcell-steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic (seeded exact PEC cavity modes)",
+        "config": {"workload": f"batched: {len(specs)} 2D TM cavities, N uniform 64..768 (seed 2306), "
+                               f"modes 1..8, CFL 0.5, {steps} steps each, {args.precision}",
+                   "problems": len(specs), "cells_per_step": cells, "tile_x": tuned["tile_x"],
+                   "tile_y": tuned["tile_y"], "autotune_timings_s": tuned["timings"]},
+        "l2_vs_exact": {"max": max(errs), "median": float(np.median(errs))},
+        "sequential_single_problem_s": round(seq, 4), "speedup_vs_sequential": round(seq / elapsed, 3),
+        "parity_sample": parity,
+        "step_frac": round(88.0 * value * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_3d(args):
+    """3D PEC cube cavity, mode (2,3,4), CFL 0.4, T = 0.5."""
+    import torch
+    from paper_2306_17263_amd import Problem
+    from paper_2306_17263_amd import _lib as L
+    from workloads import mode_fields
+    n = args.n if args.n != 2048 else 256
+    r = 0.4
+    h = 1.0 / n
+    ht = r * h
+    steps = args.steps if args.steps is not None else int(round(0.5 / ht))
+    st = torch.cuda.Stream()
+    settings = dict(closure=args.closure, lap_mode=args.lap, precision=args.precision)
+    init = mode_fields(3, n, (2, 3, 4), 0.0, ht / 2)
+    p = Problem(3, n, r, stream=st, **settings)
+    for name in p.fields():
+        p.set(name, init[name])
+    p.step(min(args.warmup, 4))
+    for name in p.fields():
+        p.set(name, init[name])
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(st)
+    p.step(steps)
+    ev1.record(st)
+    torch.cuda.synchronize()
+    elapsed = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3)
+    cells = n ** 3
+    value = cells * steps / elapsed / 1e6
+    names = ["ex", "ey", "ez", "hx", "hy", "hz"]
+    ex = mode_fields(3, n, (2, 3, 4), steps * ht, (steps + 0.5) * ht, with_laplacian=False)
+    l2 = rel_l2({a: p.get(a) for a in names}, ex, names)
+    p.close()
+    pp = Problem(3, n, r, stream=st, flags=L.FLAG_PROFILE, **settings)
+    for name in pp.fields():
+        pp.set(name, init[name])
+    pp.step(2)
+    inf = pp.info()
+    pp.close()
+    per = {c: 1e3 * inf["kernel_ms"][i] / inf["kernel_launches"][i] for i, c in enumerate(L.KERNEL_CLASSES)
+           if inf["kernel_launches"][i]}
+    line = {
+        "metric": "Mcell-steps/s at fixed L2 error vs FP64 oracle + % HBM roofline",
+        "value": round(value, 2), "unit": "Mcell-steps/s", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 4),
+        "ms_per_step": round(elapsed * 1e3 / steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic (exact PEC cube-cavity mode)",
+        "config": {"workload": f"3D PEC cube cavity N={n}, mode (2,3,4), CFL 0.4, T=0.5 ({steps} steps), "
+                               f"{args.closure} closure, {args.lap} Laplacian, {args.precision}", "n": n},
+        "l2_vs_exact": l2,
+        "per_class_avg_us": {c: round(v, 1) for c, v in per.items()},
+        "step_frac": round(192.0 * value * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
     }
     print(json.dumps(line), flush=True)
 

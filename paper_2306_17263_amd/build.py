@@ -19,7 +19,7 @@ def sources():
 def build(verbose: bool = True, jobs: int = 8) -> str:
     objdir = os.path.join(ROOT, "_build")
     os.makedirs(objdir, exist_ok=True)
-    flags = ["-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC",
+    flags = ["-O3", "-std=c++20", f"--offload-arch={ARCH}", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-munsafe-fp-atomics", "-Wall",
              "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]

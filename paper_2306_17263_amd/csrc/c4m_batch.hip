@@ -83,8 +83,8 @@ __global__ __launch_bounds__(256) void k_batch_x(const BatchProb* __restrict__ b
     finish(q);
 }
 
-template <int K, int MODE>
-__global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_col(
+template <int K, int MODE, class S>
+__global__ __launch_bounds__(S::NTC) __attribute__((amdgpu_waves_per_eu(S::NL == 4 ? 4 : 2))) void k_batch_col(
     const BatchProb* __restrict__ bp, PhaseQueue q, int total, int phase, Coef cf, PadeTaps taps,
     ChebSchedule cs)
 {
@@ -97,27 +97,17 @@ __global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(4))) void k
         const int tx = bp[p].tiles_x[phase];
         const ColArgs& ca = phase == PH_CE ? bp[p].ce : (phase == PH_CHX ? bp[p].chx : bp[p].chy);
         const PadeLine& L = phase == PH_CE ? bp[p].xe.L : bp[p].xh.L;
-        col_tile<K, MODE>(ca, cf, taps, L, cs, local % tx, local / tx);
+        col_tile<K, MODE, S>(ca, cf, taps, L, cs, local % tx, local / tx);
     }
     finish(q);
 }
 
-template <int K>
-static int col_tiles(const UGrid& g, int* tx)
+static int col_tiles_k(int K, int shape, const UGrid& g, int* tx)
 {
-    *tx = col_tiles_x<K>(g);
-    return col_tiles_x<K>(g) * col_tiles_y<K>(g);
-}
-
-static int col_tiles_k(int K, const UGrid& g, int* tx)
-{
-    switch (K) {
-#define C4M_CASE(KK) case KK: return col_tiles<KK>(g, tx);
-        C4M_CASE(1) C4M_CASE(2) C4M_CASE(3) C4M_CASE(4) C4M_CASE(5) C4M_CASE(6) C4M_CASE(7) C4M_CASE(8)
-#undef C4M_CASE
-    }
-    *tx = 1;
-    return 0;
+    return with_k_shape(K, shape, [&]<int KK, class S>() {
+        *tx = col_tiles_x<KK, S>(g);
+        return col_tiles_x<KK, S>(g) * col_tiles_y<KK, S>(g);
+    });
 }
 
 // workgroups of a persistent launch: what fits on the device at once
@@ -138,14 +128,9 @@ static int blocks_x()
 }
 
 template <int MODE>
-static int blocks_col(int K)
+static int blocks_col(int K, int shape)
 {
-    switch (K) {
-#define C4M_CASE(KK) case KK: return resident_blocks(k_batch_col<KK, MODE>, NTC);
-        C4M_CASE(1) C4M_CASE(2) C4M_CASE(3) C4M_CASE(4) C4M_CASE(5) C4M_CASE(6) C4M_CASE(7) C4M_CASE(8)
-#undef C4M_CASE
-    }
-    return 1;
+    return with_k_shape(K, shape, [&]<int KK, class S>() { return resident_blocks(k_batch_col<KK, MODE, S>, S::NTC); });
 }
 
 template <int MODE>
@@ -158,22 +143,14 @@ static hipError_t launch_bx(hipStream_t st, int blocks, const BatchProb* bp, con
 }
 
 template <int MODE>
-static hipError_t launch_bc(int K, hipStream_t st, int blocks, const BatchProb* bp, const PhaseQueue& q,
+static hipError_t launch_bc(int K, int shape, hipStream_t st, int blocks, const BatchProb* bp, const PhaseQueue& q,
                             int total, int phase, const Coef& cf, const PadeTaps& taps, const ChebSchedule& cs)
 {
-    switch (K) {
-#define C4M_CASE(KK)                                                                                   \
-    case KK: {                                                                                         \
-        const int g = std::max(1, std::min(blocks, total));                                           \
-        hipLaunchKernelGGL((k_batch_col<KK, MODE>), dim3(g), dim3(NTC), 0, st, bp, q, total, phase, cf, \
-                           taps, cs);                                                                  \
-        break;                                                                                         \
-    }
-        C4M_CASE(1) C4M_CASE(2) C4M_CASE(3) C4M_CASE(4) C4M_CASE(5) C4M_CASE(6) C4M_CASE(7) C4M_CASE(8)
-#undef C4M_CASE
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    return with_k_shape(K, shape, [&]<int KK, class S>() {
+        const int g = std::max(1, std::min(blocks, total));
+        hipLaunchKernelGGL((k_batch_col<KK, MODE, S>), dim3(g), dim3(S::NTC), 0, st, bp, q, total, phase, cf, taps, cs);
+        return hipGetLastError();
+    });
 }
 
 }  // namespace c4m
@@ -220,7 +197,8 @@ c4m_status check_uniform(const c4m_config* cfgs, int32_t count)
         if (c.dim != 2) return set_error(C4M_EINVAL, "batched form takes 2D problems");
         if (c.cfl != cfgs[0].cfl || c.z != cfgs[0].z || c.closure != cfgs[0].closure ||
             c.lap_mode != cfgs[0].lap_mode || c.precision != cfgs[0].precision ||
-            c.solver != cfgs[0].solver || c.sweeps != cfgs[0].sweeps)
+            c.solver != cfgs[0].solver || c.sweeps != cfgs[0].sweeps || c.tile_x != cfgs[0].tile_x ||
+            c.tile_y != cfgs[0].tile_y)
             return set_error(C4M_EINVAL, "batched problems must share cfl, z, closure, lap_mode, precision, solver");
         size_t b = 0;
         c4m_status s = c4m_workspace_bytes(&c, &b);
@@ -251,19 +229,19 @@ c4m_status launch_step(c4m_batch* b)
                             : launch_bx<XL_E_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe);
                 break;
             case PH_CE:
-                e = tracked ? launch_bc<COL_E_TRACKED>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb)
-                            : launch_bc<COL_E_DISCRETE>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb);
+                e = tracked ? launch_bc<COL_E_TRACKED>(K, b->base.tile_x, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb)
+                            : launch_bc<COL_E_DISCRETE>(K, b->base.tile_x, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb);
                 break;
             case PH_XH:
                 e = tracked ? launch_bx<XL_H_TRACKED>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh)
                             : launch_bx<XL_H_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh);
                 break;
             case PH_CHX:
-                e = tracked ? launch_bc<COL_HX_TRACKED>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb)
-                            : launch_bc<COL_HX_DISCRETE>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
+                e = tracked ? launch_bc<COL_HX_TRACKED>(K, b->base.tile_x, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb)
+                            : launch_bc<COL_HX_DISCRETE>(K, b->base.tile_x, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
                 break;
             default:
-                e = launch_bc<COL_HY>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
+                e = launch_bc<COL_HY>(K, b->base.tile_x, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
                 break;
         }
     }
@@ -335,11 +313,11 @@ c4m_status c4m_batch_create(const c4m_config* cfgs, int32_t count, void* d_works
         int tiles[NPH];
         d.tiles_x[PH_XE] = xlines_tiles_x(v.line[1].n_out);
         tiles[PH_XE] = d.tiles_x[PH_XE] * xlines_tiles_y(N);
-        tiles[PH_CE] = col_tiles_k(K, d.ce.g, &d.tiles_x[PH_CE]);
+        tiles[PH_CE] = col_tiles_k(K, cfgs[0].tile_x, d.ce.g, &d.tiles_x[PH_CE]);
         d.tiles_x[PH_XH] = xlines_tiles_x(v.line[0].n_out);
         tiles[PH_XH] = d.tiles_x[PH_XH] * xlines_tiles_y(N);
-        tiles[PH_CHX] = col_tiles_k(K, d.chx.g, &d.tiles_x[PH_CHX]);
-        tiles[PH_CHY] = col_tiles_k(K, d.chy.g, &d.tiles_x[PH_CHY]);
+        tiles[PH_CHX] = col_tiles_k(K, cfgs[0].tile_x, d.chx.g, &d.tiles_x[PH_CHX]);
+        tiles[PH_CHY] = col_tiles_k(K, cfgs[0].tile_x, d.chy.g, &d.tiles_x[PH_CHY]);
         for (int ph = 0; ph < NPH; ++ph)
             prefix[(size_t)ph * (count + 1) + i + 1] = prefix[(size_t)ph * (count + 1) + i] + tiles[ph];
         if (i == 0) {
@@ -359,10 +337,12 @@ c4m_status c4m_batch_create(const c4m_config* cfgs, int32_t count, void* d_works
         const bool tracked = b->base.lap_mode == C4M_LAP_TRACKED;
         const int K = b->cheb.sweeps;
         b->blocks[PH_XE] = tracked ? blocks_x<XL_E_TRACKED>() : blocks_x<XL_E_DISCRETE>();
-        b->blocks[PH_CE] = tracked ? blocks_col<COL_E_TRACKED>(K) : blocks_col<COL_E_DISCRETE>(K);
+        b->blocks[PH_CE] = tracked ? blocks_col<COL_E_TRACKED>(K, b->base.tile_x) : blocks_col<COL_E_DISCRETE>(K, b->base.tile_x);
         b->blocks[PH_XH] = tracked ? blocks_x<XL_H_TRACKED>() : blocks_x<XL_H_DISCRETE>();
-        b->blocks[PH_CHX] = tracked ? blocks_col<COL_HX_TRACKED>(K) : blocks_col<COL_HX_DISCRETE>(K);
-        b->blocks[PH_CHY] = blocks_col<COL_HY>(K);
+        b->blocks[PH_CHX] = tracked ? blocks_col<COL_HX_TRACKED>(K, b->base.tile_x) : blocks_col<COL_HX_DISCRETE>(K, b->base.tile_x);
+        b->blocks[PH_CHY] = blocks_col<COL_HY>(K, b->base.tile_x);
+        const int mult = b->base.tile_y > 0 ? b->base.tile_y : 1;   // persistent grid multiplier
+        for (int ph = 0; ph < NPH; ++ph) b->blocks[ph] *= mult;
     }
     hipError_t e = hipMemcpyAsync(b->d_probs, hp.data(), sizeof(BatchProb) * count, hipMemcpyHostToDevice, b->stream);
     if (e == hipSuccess)

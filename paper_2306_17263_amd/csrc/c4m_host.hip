@@ -16,13 +16,13 @@ namespace c4m {
 hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const double* hy, double* t0,
                            double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                            const PadeLine& line_h2n);
-hipError_t launch_solve_e_2d(hipStream_t st, bool tracked, const double* hx, double* ez, double* ge,
+hipError_t launch_solve_e_2d(hipStream_t st, int shape, bool tracked, const double* hx, double* ez, double* ge,
                              const double* t0, const double* t1, int N, int P, const Coef& cf,
                              const PadeTaps& taps, const PadeLine& line_h2n, const ChebSchedule& cs);
 hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, double* t0, double* t1,
                            int N, int P, const Coef& cf, const PadeTaps& taps,
                            const PadeLine& line_n2h);
-hipError_t launch_solve_h_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy,
+hipError_t launch_solve_h_2d(hipStream_t st, int shape, bool tracked, const double* src, double* hx, double* hy,
                              const double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                              const PadeLine& line_n2h, const ChebSchedule& cs);
 hipError_t launch_term3(hipStream_t st, int axis, int mode, const Term3& t, double alpha,
@@ -283,6 +283,8 @@ c4m_status validate(const c4m_config* c)
     if (c->solver != C4M_SOLVER_CHEBYSHEV && c->solver != C4M_SOLVER_PCG)
         return fail(C4M_EINVAL, "bad solver");
     if (c->sweeps < 0 || c->sweeps > MAX_SWEEPS) return fail(C4M_EINVAL, "sweeps out of range");
+    if (c->tile_x < 0 || c->tile_x > 2) return fail(C4M_EINVAL, "tile_x (column tile shape) must be 0, 1 or 2");
+    if (c->tile_y < 0 || c->tile_y > 8) return fail(C4M_EINVAL, "tile_y (persistent grid multiplier) out of range");
     // Section 4: r <= 1/(sqrt(d) ||A^{-1}||) with ||A^{-1}|| ~ 6/5
     const double bound = 5.0 / (6.0 * sqrt((double)c->dim));
     if (!(c->flags & C4M_FLAG_ALLOW_ANY_CFL) && c->cfl > bound * (1.0 + 1e-12))
@@ -484,7 +486,7 @@ c4m_status step_once(c4m_problem* p)
         });
         if (s == C4M_OK)
             s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
-                return launch_solve_e_2d(p->stream, tracked, hx, ez, ge, t0, t1, N, P, p->coef,
+                return launch_solve_e_2d(p->stream, p->cfg.tile_x, tracked, hx, ez, ge, t0, t1, N, P, p->coef,
                                          p->pade_host[1].taps, p->line[1], p->cheb);
             });
         if (s == C4M_OK)
@@ -494,7 +496,7 @@ c4m_status step_once(c4m_problem* p)
             });
         if (s == C4M_OK)
             s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
-                return launch_solve_h_2d(p->stream, tracked, tracked ? ge : ez, hx, hy, t1, N, P,
+                return launch_solve_h_2d(p->stream, p->cfg.tile_x, tracked, tracked ? ge : ez, hx, hy, t1, N, P,
                                          p->coef, p->pade_host[0].taps, p->line[0], p->cheb);
             });
         return s;

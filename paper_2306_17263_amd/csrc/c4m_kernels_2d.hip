@@ -10,41 +10,25 @@ __global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps
     xlines_tile<MODE>(xa, cf, taps, blockIdx.x, blockIdx.y);
 }
 
-template <int K, int MODE>
-__global__ __launch_bounds__(NTC) __attribute__((amdgpu_waves_per_eu(4))) void k_col(ColArgs a, Coef cf,
-                                                                                  PadeTaps taps, PadeLine L,
-                                                                                  ChebSchedule cs)
+template <int K, int MODE, class S>
+__global__ __launch_bounds__(S::NTC) __attribute__((amdgpu_waves_per_eu(S::NL == 4 ? 4 : 2))) void k_col(
+    ColArgs a, Coef cf, PadeTaps taps, PadeLine L, ChebSchedule cs)
 {
-    col_tile<K, MODE>(a, cf, taps, L, cs, blockIdx.x, blockIdx.y);
+    col_tile<K, MODE, S>(a, cf, taps, L, cs, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
 template <int MODE>
-static hipError_t launch_col_k(int K, dim3 grid, hipStream_t st, const ColArgs& a, const Coef& cf,
-                               const PadeTaps& taps, const PadeLine& L, const ChebSchedule& cs)
+static hipError_t launch_col(int shape, hipStream_t st, const ColArgs& a, const Coef& cf, const PadeTaps& taps,
+                             const PadeLine& L, const ChebSchedule& cs)
 {
-    switch (K) {
-#define C4M_CASE(KK)                                                                              \
-    case KK: hipLaunchKernelGGL((k_col<KK, MODE>), grid, dim3(NTC), 0, st, a, cf, taps, L, cs); break;
-        C4M_CASE(1) C4M_CASE(2) C4M_CASE(3) C4M_CASE(4) C4M_CASE(5) C4M_CASE(6) C4M_CASE(7) C4M_CASE(8)
-#undef C4M_CASE
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-static dim3 col_grid(const UGrid& g, int K)
-{
-    int oh = 16;
-    switch (K) {
-#define C4M_CASE(KK) case KK: oh = ColShape<KK>::OH; break;
-        C4M_CASE(1) C4M_CASE(2) C4M_CASE(3) C4M_CASE(4) C4M_CASE(5) C4M_CASE(6) C4M_CASE(7) C4M_CASE(8)
-#undef C4M_CASE
-    }
-    const int ow = CW - 2 * (K + 1);
-    return dim3((g.hi[0] - g.lo[0] + ow - 1) / ow, (g.hi[1] - g.lo[1] + oh - 1) / oh);
+    return with_k_shape(cs.sweeps, shape, [&]<int K, class S>() {
+        const dim3 grid(col_tiles_x<K, S>(a.g), col_tiles_y<K, S>(a.g));
+        hipLaunchKernelGGL((k_col<K, MODE, S>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);
+        return hipGetLastError();
+    });
 }
 
 hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const double* hy, double* t0,
@@ -62,14 +46,13 @@ hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const
     return hipGetLastError();
 }
 
-hipError_t launch_solve_e_2d(hipStream_t st, bool tracked, const double* hx, double* ez, double* ge,
+hipError_t launch_solve_e_2d(hipStream_t st, int shape, bool tracked, const double* hx, double* ez, double* ge,
                              const double* t0, const double* t1, int N, int P, const Coef& cf,
                              const PadeTaps& taps, const PadeLine& line_h2n, const ChebSchedule& cs)
 {
-    ColArgs a{hx, t0, t1, ez, ge, UGrid{{1, 1, 0}, {N, N, 1}, {0, 0, 0}}, N, P};
-    const dim3 grid = col_grid(a.g, cs.sweeps);
-    if (tracked) return launch_col_k<COL_E_TRACKED>(cs.sweeps, grid, st, a, cf, taps, line_h2n, cs);
-    return launch_col_k<COL_E_DISCRETE>(cs.sweeps, grid, st, a, cf, taps, line_h2n, cs);
+    ColArgs a{hx, t0, t1, ez, ge, ugrid_ez(N), N, P};
+    if (tracked) return launch_col<COL_E_TRACKED>(shape, st, a, cf, taps, line_h2n, cs);
+    return launch_col<COL_E_DISCRETE>(shape, st, a, cf, taps, line_h2n, cs);
 }
 
 hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, double* t0, double* t1,
@@ -86,22 +69,19 @@ hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, doub
     return hipGetLastError();
 }
 
-hipError_t launch_solve_h_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy,
+hipError_t launch_solve_h_2d(hipStream_t st, int shape, bool tracked, const double* src, double* hx, double* hy,
                              const double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                              const PadeLine& line_n2h, const ChebSchedule& cs)
 {
     // Hx: Dirichlet in x (nodes 1..N-1), Neumann in y (half points 0..N-1);
     // right-hand side -(1/Z) delta_y G_E along columns
-    ColArgs ax{src, nullptr, nullptr, hx, nullptr, UGrid{{1, 0, 0}, {N, N, 1}, {0, 1, 0}}, N, P};
-    hipError_t e = tracked
-                       ? launch_col_k<COL_HX_TRACKED>(cs.sweeps, col_grid(ax.g, cs.sweeps), st, ax, cf,
-                                                      taps, line_n2h, cs)
-                       : launch_col_k<COL_HX_DISCRETE>(cs.sweeps, col_grid(ax.g, cs.sweeps), st, ax, cf,
-                                                       taps, line_n2h, cs);
+    ColArgs ax{src, nullptr, nullptr, hx, nullptr, ugrid_hx(N), N, P};
+    hipError_t e = tracked ? launch_col<COL_HX_TRACKED>(shape, st, ax, cf, taps, line_n2h, cs)
+                           : launch_col<COL_HX_DISCRETE>(shape, st, ax, cf, taps, line_n2h, cs);
     if (e != hipSuccess) return e;
     // Hy: Neumann in x, Dirichlet in y; right-hand side T1 from the x-lines
-    ColArgs ay{nullptr, t1, nullptr, hy, nullptr, UGrid{{0, 1, 0}, {N, N, 1}, {1, 0, 0}}, N, P};
-    return launch_col_k<COL_HY>(cs.sweeps, col_grid(ay.g, cs.sweeps), st, ay, cf, taps, line_n2h, cs);
+    ColArgs ay{nullptr, t1, nullptr, hy, nullptr, ugrid_hy(N), N, P};
+    return launch_col<COL_HY>(shape, st, ay, cf, taps, line_n2h, cs);
 }
 
 }  // namespace c4m

@@ -191,17 +191,25 @@ __device__ __forceinline__ void xlines_tile(const XArgs& xa, const Coef& cf, con
 // S = d(y-1) + 4 d(y) + d(y+1) of the 9-point stencil cross between
 // columns through the LDS (padded rows, zero sentinels at both ends).
 // ===========================================================================
-constexpr int CW = 128;      // region width (columns)
-constexpr int CWP = CW + 2;  // LDS row stride
-constexpr int NL = 4;        // lanes per column
-constexpr int NTC = CW * NL; // threads per workgroup
+// Column-kernel tile shapes: CW region columns, NL lanes per column.
+template <int CW_, int NL_>
+struct TileShape {
+    static constexpr int CW = CW_;
+    static constexpr int CWP = CW_ + 2;      // LDS row stride (zero sentinels at both ends)
+    static constexpr int NL = NL_;
+    static constexpr int NTC = CW_ * NL_;    // threads per workgroup
+};
+using Shape0 = TileShape<128, 4>;            // default
+using Shape1 = TileShape<64, 4>;
+using Shape2 = TileShape<128, 2>;
+constexpr int NSHAPES = 3;
 
 // region rows for K sweeps: at least 16 output rows, a multiple of NL
-template <int K>
+template <int K, class S>
 struct ColShape {
-    static constexpr int TR = ((16 + 2 * K + NL - 1) / NL) * NL;
+    static constexpr int TR = ((16 + 2 * K + S::NL - 1) / S::NL) * S::NL;
     static constexpr int OH = TR - 2 * K;
-    static constexpr int HR = TR / NL;
+    static constexpr int HR = TR / S::NL;
 };
 
 enum { COL_E_TRACKED = 0, COL_E_DISCRETE = 1, COL_HX_TRACKED = 2, COL_HX_DISCRETE = 3, COL_HY = 4 };
@@ -216,13 +224,14 @@ struct ColArgs {
     int N, P;
 };
 
-template <int K, int MODE>
+template <int K, int MODE, class S>
 __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const PadeTaps& taps,
                                          const PadeLine& L, const ChebSchedule& cs, int bxi, int byi)
 {
-    constexpr int TR = ColShape<K>::TR;             // region rows
-    constexpr int OH = ColShape<K>::OH;             // output rows
-    constexpr int HR = ColShape<K>::HR;             // rows per lane
+    constexpr int CW = S::CW, CWP = S::CWP, NL = S::NL, NTC = S::NTC;
+    constexpr int TR = ColShape<K, S>::TR;          // region rows
+    constexpr int OH = ColShape<K, S>::OH;          // output rows
+    constexpr int HR = ColShape<K, S>::HR;          // rows per lane
     constexpr int HALO_X = K + 1;                   // column halo (one more for the cross-line term)
     constexpr bool YPART = MODE != COL_HY;
     constexpr bool SPLIT = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE || MODE == COL_HX_DISCRETE;
@@ -449,12 +458,42 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const
 // Tile counts of the two 2D kernels.
 __host__ __device__ inline int xlines_tiles_x(int n_out) { return (n_out + XT_OUT - 1) / XT_OUT; }
 __host__ __device__ inline int xlines_tiles_y(int N) { return (N - 1 + XT_ROWS - 1) / XT_ROWS; }
-template <int K>
-__host__ __device__ inline int col_tiles_x(const UGrid& g) { return (g.hi[0] - g.lo[0] + CW - 2 * (K + 1) - 1) / (CW - 2 * (K + 1)); }
-template <int K>
+template <int K, class S>
+__host__ __device__ inline int col_tiles_x(const UGrid& g)
+{
+    return (g.hi[0] - g.lo[0] + S::CW - 2 * (K + 1) - 1) / (S::CW - 2 * (K + 1));
+}
+template <int K, class S>
 __host__ __device__ inline int col_tiles_y(const UGrid& g)
 {
-    return (g.hi[1] - g.lo[1] + ColShape<K>::OH - 1) / ColShape<K>::OH;
+    return (g.hi[1] - g.lo[1] + ColShape<K, S>::OH - 1) / ColShape<K, S>::OH;
+}
+
+// Dispatch a callable templated on (K, shape) from run-time values; shapes
+// 1 and 2 exist for K in 4..6 only (shape 0 otherwise).
+template <class F>
+inline auto with_k_shape(int K, int shape, F&& f)
+{
+    if (shape == 1 && K >= 4 && K <= 6) {
+        if (K == 4) return f.template operator()<4, Shape1>();
+        if (K == 5) return f.template operator()<5, Shape1>();
+        return f.template operator()<6, Shape1>();
+    }
+    if (shape == 2 && K >= 4 && K <= 6) {
+        if (K == 4) return f.template operator()<4, Shape2>();
+        if (K == 5) return f.template operator()<5, Shape2>();
+        return f.template operator()<6, Shape2>();
+    }
+    switch (K) {
+        case 1: return f.template operator()<1, Shape0>();
+        case 2: return f.template operator()<2, Shape0>();
+        case 3: return f.template operator()<3, Shape0>();
+        case 4: return f.template operator()<4, Shape0>();
+        case 5: return f.template operator()<5, Shape0>();
+        case 6: return f.template operator()<6, Shape0>();
+        case 7: return f.template operator()<7, Shape0>();
+        default: return f.template operator()<8, Shape0>();
+    }
 }
 
 // unknowns of the 2D components

@@ -59,3 +59,37 @@ def test_batch_rejects_mixed_settings():
     from paper_2306_17263_amd import Batch, C4mError
     with pytest.raises(C4mError):
         Batch([{"n": 16, "cfl": 0.5}, {"n": 20, "cfl": 0.4}])
+
+
+@pytest.mark.parametrize("shape,mult", [(1, 1), (2, 2), (0, 3)])
+def test_batch_shapes_and_grid(shape, mult):
+    import torch
+    from paper_2306_17263_amd import Batch
+    specs = _specs(11)[:5]
+    st = torch.cuda.Stream()
+    b = Batch(specs, stream=st, tile_x=shape, tile_y=mult)
+    inits = []
+    for p, s in zip(b.problems, specs):
+        init = initial_fields(2, s["n"], 0.5, k=s["k"], amp=s["amp"])
+        inits.append(init)
+        for name in p.fields():
+            p.set(name, init[name])
+    b.step(6)
+    for p, s, init in zip(b.problems, specs, inits):
+        o = oracle.OracleProblem(2, s["n"], 0.5, 1.0)
+        for name in p.fields():
+            o.set(name, init[name])
+        o.step(6)
+        names = ["ez", "hx", "hy"]
+        assert rel_l2_all({a: p.get(a) for a in names}, {a: o.get(a) for a in names}, names) <= 1e-12
+    b.close()
+
+
+def test_autotune_batch_and_single(tmp_path, monkeypatch):
+    monkeypatch.setenv("C4M_TUNE_CACHE", str(tmp_path / "tune.json"))
+    from paper_2306_17263_amd import autotune
+    r = autotune.tune_batch(_specs(3)[:4], steps=2)
+    assert r["tile_x"] in (0, 1, 2) and r["tile_y"] in (1, 2)
+    assert autotune.tune_batch(_specs(3)[:4], steps=2) == r          # served from the cache
+    s = autotune.tune_single(96, steps=2)
+    assert s["tile_x"] in (0, 1, 2)

@@ -57,3 +57,11 @@ def test_explicit_sweep_counts(sweeps):
     gf, of = run_pair(2, 64, 0.5, 8, k=(4, 3), sweeps=sweeps)
     tol = 1e-12 if sweeps >= 5 else 1e-7
     assert rel_l2_all(gf, of, EH) <= tol
+
+
+@pytest.mark.parametrize("shape", [1, 2])
+@pytest.mark.parametrize("lap", ["tracked", "discrete"])
+def test_tile_shapes_parity(shape, lap):
+    # the alternative column-tile shapes of the autotuner give the same scheme
+    gf, of = run_pair(2, 150, 0.5, 10, closure="paper", lap=lap, seed=5, tile_x=shape)
+    _check(gf, of)
