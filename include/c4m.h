@@ -177,6 +177,17 @@ c4m_status c4m_batch_problem(c4m_batch* b, int32_t i, c4m_problem** out);
 c4m_status c4m_batch_step(c4m_batch* b, int64_t nsteps);
 c4m_status c4m_batch_destroy(c4m_batch* b);
 
+/* Batched form over 2D problems the caller already created (each on its own
+ * workspace, sharing cfl, z, closure, lap_mode, precision, solver, sweeps and
+ * tiles).  `d_tables` (>= c4m_batch_tables_bytes(count), 256-byte aligned)
+ * holds only the work-queue tables; the problems stay the caller's, must
+ * outlive the batch, and keep their own stream-ordered state (they are
+ * stepped on the batch's stream).  Lets a serving loop re-form batches as
+ * requests come and go without moving resident fields. */
+c4m_status c4m_batch_tables_bytes(int32_t count, size_t* bytes);
+c4m_status c4m_batch_create_from(c4m_problem* const* probs, int32_t count, void* d_tables,
+                                 size_t bytes, void* hip_stream, c4m_batch** out);
+
 const char* c4m_status_string(c4m_status s);
 const char* c4m_last_error(void);
 

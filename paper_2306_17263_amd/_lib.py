@@ -23,7 +23,8 @@ EXPORTS = [
     "c4m_config_default", "c4m_workspace_bytes", "c4m_create", "c4m_field_shape",
     "c4m_set_field", "c4m_get_field", "c4m_step", "c4m_get_info", "c4m_destroy",
     "c4m_batch_workspace_bytes", "c4m_batch_create", "c4m_batch_problem", "c4m_batch_step",
-    "c4m_batch_destroy", "c4m_status_string", "c4m_last_error",
+    "c4m_batch_destroy", "c4m_batch_tables_bytes", "c4m_batch_create_from",
+    "c4m_status_string", "c4m_last_error",
 ]
 
 
@@ -81,6 +82,8 @@ def load():
     lib.c4m_batch_problem.argtypes = [vp, i32, ctypes.POINTER(vp)]
     lib.c4m_batch_step.argtypes = [vp, i64]
     lib.c4m_batch_destroy.argtypes = [vp]
+    lib.c4m_batch_tables_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+    lib.c4m_batch_create_from.argtypes = [ctypes.POINTER(vp), i32, vp, sz, vp, ctypes.POINTER(vp)]
     for name in EXPORTS:
         if name in ("c4m_status_string", "c4m_last_error"):
             continue

@@ -38,6 +38,28 @@ class Batch:
             self.problems.append(Problem(2, s["n"], s.get("cfl", 0.5), device=device, stream=self.stream,
                                          _borrowed=ph, **common))
 
+    @classmethod
+    def from_problems(cls, problems, *, stream=None):
+        """A batch over existing 2D problems (their fields stay where they
+        are); only the work-queue tables are allocated."""
+        self = cls.__new__(cls)
+        self._lib = L.load()
+        self.problems = list(problems)
+        self.device = problems[0].device
+        self.stream = stream if stream is not None else problems[0].stream
+        self.specs = [{"n": p.n, "cfl": p.cfl} for p in problems]
+        nb = ctypes.c_size_t()
+        L.check(self._lib.c4m_batch_tables_bytes(len(problems), ctypes.byref(nb)), "c4m_batch_tables_bytes")
+        self.nbytes = nb.value
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        arr = (ctypes.c_void_p * len(problems))(*[p.handle.value for p in problems])
+        self._h = ctypes.c_void_p()
+        L.check(self._lib.c4m_batch_create_from(arr, len(problems), ctypes.c_void_p(self.workspace.data_ptr()),
+                                                self.nbytes, ctypes.c_void_p(int(self.stream.cuda_stream)),
+                                                ctypes.byref(self._h)), "c4m_batch_create_from")
+        self._borrowed_problems = True
+        return self
+
     def __len__(self):
         return len(self.problems)
 
@@ -49,8 +71,9 @@ class Batch:
 
     def close(self):
         if self._h:
-            for p in self.problems:
-                p.close()
+            if not getattr(self, "_borrowed_problems", False):
+                for p in self.problems:
+                    p.close()
             L.check(self._lib.c4m_batch_destroy(self._h), "c4m_batch_destroy")
             self._h = ctypes.c_void_p()
 

@@ -165,6 +165,7 @@ c4m_status problem_create_owned(const c4m_config* cfg, void* ws, size_t bytes, h
                                 c4m_problem** out);
 void problem_add_steps(c4m_problem* p, int64_t n);
 void problem_destroy_owned(c4m_problem* p);
+const c4m_config* problem_config(const c4m_problem* p);
 c4m_status set_error(c4m_status s, const char* msg);
 }  // namespace c4m
 
@@ -181,6 +182,7 @@ struct c4m_batch {
     PadeTaps taps_xe{}, taps_xh{};
     ChebSchedule cheb{};
     int blocks[NPH] = {};           // workgroups of each persistent launch
+    bool owns = true;               // problems created by (and destroyed with) the batch
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -267,6 +269,75 @@ c4m_status c4m_batch_workspace_bytes(const c4m_config* cfgs, int32_t count, size
     return C4M_OK;
 }
 
+}  // extern "C"
+
+namespace {
+
+// Work-queue tables of a batch over b->probs, carved at `cur`.
+c4m_status build_tables(c4m_batch* b, char* cur)
+{
+    const int count = b->count;
+    b->d_probs = (BatchProb*)cur;
+    cur += a256(sizeof(BatchProb) * count);
+    b->d_prefix = (int*)cur;
+    cur += a256(sizeof(int) * NPH * (count + 1));
+    b->d_ctr = (int*)cur;
+    std::vector<BatchProb> hp(count);
+    std::vector<int> prefix((size_t)NPH * (count + 1), 0);
+    const int shape = b->base.tile_x;
+    for (int i = 0; i < count; ++i) {
+        ProblemView v{};
+        problem_view(b->probs[i], &v);
+        const int N = v.N;
+        const bool tracked = b->base.lap_mode == C4M_LAP_TRACKED;
+        BatchProb& d = hp[i];
+        d.xe = XArgs{v.f[C4M_HY], v.tmp[0], v.tmp[1], N, v.P, v.line[1]};
+        d.xh = XArgs{tracked ? v.ge[2] : v.f[C4M_EZ], v.tmp[0], v.tmp[1], N, v.P, v.line[0]};
+        d.ce = ColArgs{v.f[C4M_HX], v.tmp[0], v.tmp[1], v.f[C4M_EZ], v.ge[2], ugrid_ez(N), N, v.P};
+        d.chx = ColArgs{tracked ? v.ge[2] : v.f[C4M_EZ], nullptr, nullptr, v.f[C4M_HX], nullptr, ugrid_hx(N), N, v.P};
+        d.chy = ColArgs{nullptr, v.tmp[1], nullptr, v.f[C4M_HY], nullptr, ugrid_hy(N), N, v.P};
+        const int K = v.cheb.sweeps;
+        int tiles[NPH];
+        d.tiles_x[PH_XE] = xlines_tiles_x(v.line[1].n_out);
+        tiles[PH_XE] = d.tiles_x[PH_XE] * xlines_tiles_y(N);
+        tiles[PH_CE] = col_tiles_k(K, shape, d.ce.g, &d.tiles_x[PH_CE]);
+        d.tiles_x[PH_XH] = xlines_tiles_x(v.line[0].n_out);
+        tiles[PH_XH] = d.tiles_x[PH_XH] * xlines_tiles_y(N);
+        tiles[PH_CHX] = col_tiles_k(K, shape, d.chx.g, &d.tiles_x[PH_CHX]);
+        tiles[PH_CHY] = col_tiles_k(K, shape, d.chy.g, &d.tiles_x[PH_CHY]);
+        for (int ph = 0; ph < NPH; ++ph)
+            prefix[(size_t)ph * (count + 1) + i + 1] = prefix[(size_t)ph * (count + 1) + i] + tiles[ph];
+        if (i == 0) {
+            b->coef = v.coef;
+            b->taps_xe = v.taps[1];
+            b->taps_xh = v.taps[0];
+            b->cheb = v.cheb;
+        }
+    }
+    for (int ph = 0; ph < NPH; ++ph) b->total[ph] = prefix[(size_t)ph * (count + 1) + count];
+    {
+        const bool tracked = b->base.lap_mode == C4M_LAP_TRACKED;
+        const int K = b->cheb.sweeps;
+        b->blocks[PH_XE] = tracked ? blocks_x<XL_E_TRACKED>() : blocks_x<XL_E_DISCRETE>();
+        b->blocks[PH_CE] = tracked ? blocks_col<COL_E_TRACKED>(K, shape) : blocks_col<COL_E_DISCRETE>(K, shape);
+        b->blocks[PH_XH] = tracked ? blocks_x<XL_H_TRACKED>() : blocks_x<XL_H_DISCRETE>();
+        b->blocks[PH_CHX] = tracked ? blocks_col<COL_HX_TRACKED>(K, shape) : blocks_col<COL_HX_DISCRETE>(K, shape);
+        b->blocks[PH_CHY] = blocks_col<COL_HY>(K, shape);
+        const int mult = b->base.tile_y > 0 ? b->base.tile_y : 1;   // persistent grid multiplier
+        for (int ph = 0; ph < NPH; ++ph) b->blocks[ph] *= mult;
+    }
+    hipError_t e = hipMemcpyAsync(b->d_probs, hp.data(), sizeof(BatchProb) * count, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(b->d_prefix, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_ctr, 0, NPH * 64, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    return e == hipSuccess ? C4M_OK : set_error(C4M_EDEVICE, hipGetErrorString(e));
+}
+
+}  // namespace
+
+extern "C" {
+
 c4m_status c4m_batch_create(const c4m_config* cfgs, int32_t count, void* d_workspace, size_t bytes,
                             void* hip_stream, c4m_batch** out)
 {
@@ -282,15 +353,8 @@ c4m_status c4m_batch_create(const c4m_config* cfgs, int32_t count, void* d_works
     b->count = count;
     b->base = cfgs[0];
     b->stream = (hipStream_t)hip_stream;
-    char* cur = (char*)d_workspace;
-    b->d_probs = (BatchProb*)cur;
-    cur += a256(sizeof(BatchProb) * count);
-    b->d_prefix = (int*)cur;
-    cur += a256(sizeof(int) * NPH * (count + 1));
-    b->d_ctr = (int*)cur;
-    cur += a256(NPH * 64);
-    std::vector<BatchProb> hp(count);
-    std::vector<int> prefix((size_t)NPH * (count + 1), 0);
+    char* tables = (char*)d_workspace;
+    char* cur = tables + tables_bytes(count);
     for (int i = 0; i < count && s == C4M_OK; ++i) {
         size_t pb = 0;
         c4m_workspace_bytes(&cfgs[i], &pb);
@@ -299,60 +363,49 @@ c4m_status c4m_batch_create(const c4m_config* cfgs, int32_t count, void* d_works
         if (s != C4M_OK) break;
         cur += a256(pb);
         b->probs.push_back(p);
-        ProblemView v{};
-        problem_view(p, &v);
-        const int N = v.N;
-        const bool tracked = cfgs[i].lap_mode == C4M_LAP_TRACKED;
-        BatchProb& d = hp[i];
-        d.xe = XArgs{v.f[C4M_HY], v.tmp[0], v.tmp[1], N, v.P, v.line[1]};
-        d.xh = XArgs{tracked ? v.ge[2] : v.f[C4M_EZ], v.tmp[0], v.tmp[1], N, v.P, v.line[0]};
-        d.ce = ColArgs{v.f[C4M_HX], v.tmp[0], v.tmp[1], v.f[C4M_EZ], v.ge[2], ugrid_ez(N), N, v.P};
-        d.chx = ColArgs{tracked ? v.ge[2] : v.f[C4M_EZ], nullptr, nullptr, v.f[C4M_HX], nullptr, ugrid_hx(N), N, v.P};
-        d.chy = ColArgs{nullptr, v.tmp[1], nullptr, v.f[C4M_HY], nullptr, ugrid_hy(N), N, v.P};
-        const int K = v.cheb.sweeps;
-        int tiles[NPH];
-        d.tiles_x[PH_XE] = xlines_tiles_x(v.line[1].n_out);
-        tiles[PH_XE] = d.tiles_x[PH_XE] * xlines_tiles_y(N);
-        tiles[PH_CE] = col_tiles_k(K, cfgs[0].tile_x, d.ce.g, &d.tiles_x[PH_CE]);
-        d.tiles_x[PH_XH] = xlines_tiles_x(v.line[0].n_out);
-        tiles[PH_XH] = d.tiles_x[PH_XH] * xlines_tiles_y(N);
-        tiles[PH_CHX] = col_tiles_k(K, cfgs[0].tile_x, d.chx.g, &d.tiles_x[PH_CHX]);
-        tiles[PH_CHY] = col_tiles_k(K, cfgs[0].tile_x, d.chy.g, &d.tiles_x[PH_CHY]);
-        for (int ph = 0; ph < NPH; ++ph)
-            prefix[(size_t)ph * (count + 1) + i + 1] = prefix[(size_t)ph * (count + 1) + i] + tiles[ph];
-        if (i == 0) {
-            b->coef = v.coef;
-            b->taps_xe = v.taps[1];
-            b->taps_xh = v.taps[0];
-            b->cheb = v.cheb;
-        }
     }
+    if (s == C4M_OK) s = build_tables(b, tables);
     if (s != C4M_OK) {
         for (auto* p : b->probs) problem_destroy_owned(p);
         delete b;
         return s;
     }
-    for (int ph = 0; ph < NPH; ++ph) b->total[ph] = prefix[(size_t)ph * (count + 1) + count];
-    {
-        const bool tracked = b->base.lap_mode == C4M_LAP_TRACKED;
-        const int K = b->cheb.sweeps;
-        b->blocks[PH_XE] = tracked ? blocks_x<XL_E_TRACKED>() : blocks_x<XL_E_DISCRETE>();
-        b->blocks[PH_CE] = tracked ? blocks_col<COL_E_TRACKED>(K, b->base.tile_x) : blocks_col<COL_E_DISCRETE>(K, b->base.tile_x);
-        b->blocks[PH_XH] = tracked ? blocks_x<XL_H_TRACKED>() : blocks_x<XL_H_DISCRETE>();
-        b->blocks[PH_CHX] = tracked ? blocks_col<COL_HX_TRACKED>(K, b->base.tile_x) : blocks_col<COL_HX_DISCRETE>(K, b->base.tile_x);
-        b->blocks[PH_CHY] = blocks_col<COL_HY>(K, b->base.tile_x);
-        const int mult = b->base.tile_y > 0 ? b->base.tile_y : 1;   // persistent grid multiplier
-        for (int ph = 0; ph < NPH; ++ph) b->blocks[ph] *= mult;
+    *out = b;
+    return C4M_OK;
+}
+
+c4m_status c4m_batch_tables_bytes(int32_t count, size_t* bytes)
+{
+    if (count < 1 || !bytes) return set_error(C4M_EINVAL, "bad count");
+    *bytes = tables_bytes(count);
+    return C4M_OK;
+}
+
+c4m_status c4m_batch_create_from(c4m_problem* const* probs, int32_t count, void* d_tables, size_t bytes,
+                                 void* hip_stream, c4m_batch** out)
+{
+    if (!out || !probs || count < 1) return set_error(C4M_EINVAL, "bad arguments");
+    *out = nullptr;
+    if (!d_tables || ((uintptr_t)d_tables & 255)) return set_error(C4M_EINVAL, "tables must be 256-byte aligned");
+    if (bytes < tables_bytes(count)) return set_error(C4M_ENOMEM, "table space smaller than c4m_batch_tables_bytes");
+    std::vector<c4m_config> cfgs(count);
+    for (int i = 0; i < count; ++i) {
+        if (!probs[i]) return set_error(C4M_EINVAL, "null problem");
+        cfgs[i] = *problem_config(probs[i]);
     }
-    hipError_t e = hipMemcpyAsync(b->d_probs, hp.data(), sizeof(BatchProb) * count, hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(b->d_prefix, prefix.data(), sizeof(int) * prefix.size(), hipMemcpyHostToDevice, b->stream);
-    if (e == hipSuccess) e = hipMemsetAsync(b->d_ctr, 0, NPH * 64, b->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) {
-        for (auto* p : b->probs) problem_destroy_owned(p);
+    c4m_status s = check_uniform(cfgs.data(), count);
+    if (s != C4M_OK) return s;
+    c4m_batch* b = new (std::nothrow) c4m_batch();
+    if (!b) return set_error(C4M_ENOMEM, "host allocation");
+    b->count = count;
+    b->base = cfgs[0];
+    b->stream = (hipStream_t)hip_stream;
+    b->owns = false;
+    b->probs.assign(probs, probs + count);
+    s = build_tables(b, (char*)d_tables);
+    if (s != C4M_OK) {
         delete b;
-        return set_error(C4M_EDEVICE, hipGetErrorString(e));
+        return s;
     }
     *out = b;
     return C4M_OK;
@@ -406,7 +459,8 @@ c4m_status c4m_batch_destroy(c4m_batch* b)
     if (!b) return set_error(C4M_EINVAL, "null batch");
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (auto* p : b->probs) problem_destroy_owned(p);
+    if (b->owns)
+        for (auto* p : b->probs) problem_destroy_owned(p);
     delete b;
     return C4M_OK;
 }

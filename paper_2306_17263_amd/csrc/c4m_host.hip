@@ -813,6 +813,8 @@ c4m_status problem_create_owned(const c4m_config* cfg, void* ws, size_t bytes, h
 
 void problem_add_steps(c4m_problem* p, int64_t n) { p->steps += n; }
 
+const c4m_config* problem_config(const c4m_problem* p) { return &p->cfg; }
+
 void problem_destroy_owned(c4m_problem* p)
 {
     (void)flush_profile(p);

@@ -1,0 +1,120 @@
+"""Scheduling logic of the serving loop on the CPU: a fake backend (the
+oracle for the fields, a virtual clock for time) behind the same interface
+as the device backend."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_17263_amd.serve import Request, Server, requests_from_mix
+from workloads import mode_fields, serving_arrivals
+
+
+class VirtualClock:
+    def __init__(self):
+        self.t = 0.0
+
+    def __call__(self):
+        return self.t
+
+    def advance(self, dt):
+        self.t += dt
+
+
+class FakeBackend:
+    """Oracle problems; every step advances the virtual clock by its cost."""
+
+    def __init__(self, clock, cost_per_cell_step=1e-9, bytes_per_cell=64):
+        self.clock = clock
+        self.cost = cost_per_cell_step
+        self.bpc = bytes_per_cell
+        self.steps_done = {}
+        self.live = set()
+        self.max_live = 0
+
+    def footprint(self, req):
+        return req.cells * self.bpc
+
+    def create(self, req):
+        p = oracle.OracleProblem(req.dim, req.n, req.r)
+        h = 1.0 / req.n
+        for name, v in mode_fields(req.dim, req.n, req.k, 0.0, req.r * h / 2, amp=req.amp).items():
+            p.set(name, v)
+        self.steps_done[req.id] = 0
+        self.live.add(req.id)
+        self.max_live = max(self.max_live, len(self.live))
+        return p
+
+    def step(self, a2, a3, k):
+        assert k >= 1
+        for r in a2 + a3:
+            assert self.steps_done[r.id] + k <= r.steps          # never overshoots
+            r.handle.step(k)
+            self.steps_done[r.id] += k
+        self.clock.advance(self.cost * k * sum(r.cells for r in a2 + a3))
+
+    def sync(self):
+        pass
+
+    def finish(self, req):
+        names = ["ez", "hx", "hy"] if req.dim == 2 else ["ex", "ey", "ez", "hx", "hy", "hz"]
+        req.result = {a: req.handle.get(a) for a in names}
+        self.live.discard(req.id)
+        req.handle = None
+
+
+def _mix(count=12, seed=3):
+    mix = serving_arrivals(count=count, seed=seed, rate=50.0, n2=(8, 24), n3=(8, 10), steps=(3, 12))
+    return requests_from_mix(mix)
+
+
+def test_all_requests_complete_with_exact_step_counts():
+    clock = VirtualClock()
+    be = FakeBackend(clock)
+    reqs = _mix()
+    out = Server(be, hbm_budget=10 ** 9, chunk=4, clock=clock).run(reqs)
+    assert out["completed"] == len(reqs)
+    for r in out["done"]:
+        assert be.steps_done[r.id] == r.steps
+        assert r.t_done >= r.t_admit >= r.t_arrive - 1e-12
+
+
+def test_admission_respects_the_budget():
+    clock = VirtualClock()
+    be = FakeBackend(clock)
+    reqs = _mix(16)
+    budget = max(be.footprint(r) for r in reqs) * 2
+    srv = Server(be, hbm_budget=budget, chunk=3, clock=clock)
+    out = srv.run(reqs)
+    assert out["completed"] == len(reqs)
+    assert srv.peak_in_use <= budget
+    assert be.max_live >= 1
+
+
+def test_request_larger_than_budget_is_refused():
+    clock = VirtualClock()
+    be = FakeBackend(clock)
+    reqs = _mix(3)
+    with pytest.raises(ValueError):
+        Server(be, hbm_budget=10, clock=clock).run(reqs)
+
+
+def test_result_in_the_mix_equals_result_alone():
+    clock = VirtualClock()
+    be = FakeBackend(clock)
+    reqs = _mix(8, seed=5)
+    out = Server(be, hbm_budget=10 ** 9, chunk=5, clock=clock).run(reqs)
+    for r in out["done"]:
+        alone = oracle.OracleProblem(r.dim, r.n, r.r)
+        h = 1.0 / r.n
+        for name, v in mode_fields(r.dim, r.n, r.k, 0.0, r.r * h / 2, amp=r.amp).items():
+            alone.set(name, v)
+        alone.step(r.steps)
+        for a, v in r.result.items():
+            assert np.array_equal(v, alone.get(a)), (r.id, a)
+
+
+def test_latency_percentiles_reported():
+    clock = VirtualClock()
+    out = Server(FakeBackend(clock), hbm_budget=10 ** 9, chunk=4, clock=clock).run(_mix(10))
+    assert 0 <= out["p50_latency_s"] <= out["p99_latency_s"]
+    assert out["cell_steps_per_s"] > 0
