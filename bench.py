@@ -54,6 +54,98 @@ def measured_traffic(kernel: str, workload: str):
     return ent.get("bytes_per_launch")
 
 
+COPY_PROBE_BYTES = 256 << 20
+# kernel-class -> kernel-name pattern of the 2D path (rocprofv3 names)
+CLASS_PATTERNS = {
+    "rhs_e": r"k_xlines<[01]>",
+    "solve_e": r"k_col<\d+, [01],",
+    "rhs_h": r"k_xlines<[23]>",
+    "solve_h": r"k_col<\d+, [234],",
+}
+
+
+def traffic_key(n, args):
+    return f"2d_n{n}_{args.closure}_{args.lap}_{args.precision}_{args.solver}"
+
+
+def pmc_probe(args):
+    """A plain elementwise copy of COPY_PROBE_BYTES (reads and writes that
+    many bytes), then a few steps of the 2D workload, each on a dedicated
+    stream; run under rocprofv3 --pmc FETCH_SIZE (then WRITE_SIZE)."""
+    import torch
+    from paper_2306_17263_amd import Problem
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+    st.synchronize()
+    n = args.n
+    k = tuple(int(v) for v in args.mode.split(","))
+    ht = args.cfl / n
+    init = exact_fields(n, k, 0.0, ht / 2)
+    prob = Problem(2, n, args.cfl, closure=args.closure, lap_mode=args.lap, precision=args.precision, stream=st)
+    for name in prob.fields():
+        prob.set(name, init[name])
+    prob.step(args.steps or 4)
+    st.synchronize()
+    prob.close()
+    print(json.dumps({"pmc_probe": traffic_key(n, args), "copy_bytes": COPY_PROBE_BYTES}), flush=True)
+
+
+def _counter_means(folder):
+    """Mean counter value per kernel name from a rocprofv3 --pmc CSV."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {folder}")
+    acc = {}
+    with open(files[0]) as f:
+        for row in csv.DictReader(f):
+            key = row.get("Kernel_Name", "")
+            acc.setdefault(key, []).append(float(row["Counter_Value"]))
+    return {k: sum(v) / len(v) for k, v in acc.items()}
+
+
+def traffic_from(args):
+    """HBM bytes per launch of each kernel class: FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch) divided by what the same counters read for the copy
+    kernel of known size (bytes counted / bytes moved)."""
+    import re
+    fetch = _counter_means(args.traffic_from[0])
+    write = _counter_means(args.traffic_from[1])
+
+    def copy_value(table):
+        vals = [v for name, v in table.items() if "MulFunctor" in name]
+        if not vals:
+            raise SystemExit("copy kernel not found in the counter run")
+        return max(vals) * 1024.0
+
+    scale_f = copy_value(fetch) / COPY_PROBE_BYTES
+    scale_w = copy_value(write) / COPY_PROBE_BYTES
+    out = {}
+    for cls, pat in CLASS_PATTERNS.items():
+        rx = re.compile(pat)
+        fb = sum(v for name, v in fetch.items() if rx.search(name)) * 1024.0 / scale_f
+        wb = sum(v for name, v in write.items() if rx.search(name)) * 1024.0 / scale_w
+        if fb or wb:
+            out[cls] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                        "copy_scale": {"fetch": scale_f, "write": scale_w},
+                        "source_hash": kernel_source_hash()}
+    key = traffic_key(args.n, args)
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    data = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            data = json.load(f)
+    data[key] = out
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1, sort_keys=True)
+    print(json.dumps({key: out}, indent=1))
+
+
 def exact_fields(n, k, tau_e, tau_h):
     from workloads import mode_fields
     return mode_fields(2, n, k, tau_e, tau_h)
@@ -83,17 +175,28 @@ def main():
                          "cavities of uneven N; 3d: the cube cavity")
     ap.add_argument("--count", type=int, default=512)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
+    ap.add_argument("--solver", default="chebyshev", choices=["chebyshev", "pcg"],
+                    help="2d/3d workloads: fused fixed-sweep Chebyshev (default) or PCG with device reductions")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="for a rocprofv3 --pmc run: one plain copy kernel of known size, then a few "
+                         "steps of the 2D workload")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="read the FETCH_SIZE and WRITE_SIZE counter runs of --pmc-probe and write "
+                         "profiles/traffic.json")
     args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+    if args.traffic_from:
+        return traffic_from(args)
+    if args.pmc_probe:
+        return pmc_probe(args)
     if args.workload == "batch":
         return bench_batch(args)
     if args.workload == "3d":
         return bench_3d(args)
     if args.workload == "serve":
         return bench_serve(args)
-
-    if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
-        sys.exit(2)
 
     import torch
     if not torch.cuda.is_available():
@@ -111,7 +214,8 @@ def main():
     names = ["ez", "hx", "hy"]
     init = exact_fields(n, k, 0.0, ht / 2)
     stream = torch.cuda.Stream()              # a dedicated stream (default priority)
-    kw = dict(closure=args.closure, lap_mode=args.lap, stream=stream)
+    kw = dict(closure=args.closure, lap_mode=args.lap, precision=args.precision, solver=args.solver, stream=stream)
+    prec_name = "FP64" if args.precision == "fp64" else "FP32 Chebyshev rounds + FP64 residual"
 
     prob = Problem(2, n, cfl, **kw)
 
@@ -156,7 +260,7 @@ def main():
                           "alg_bytes": inf["kernel_alg_bytes"][ci]}
     dom = max(per, key=lambda c: per[c]["avg_us"] * per[c]["launches"])
     dom_ach = per[dom]["alg_bytes"] / (per[dom]["avg_us"] * 1e-6) / 1e9
-    workload_key = f"2d_n{n}_{args.closure}_{args.lap}"
+    workload_key = traffic_key(n, args)
     traffic = measured_traffic(dom, workload_key)
     roofline = {"bound": "hbm", "achieved": round(dom_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom_ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
@@ -210,12 +314,14 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic (exact PEC cavity mode sampled on the Yee grids)",
         "config": {"workload": f"2D TM PEC cavity N={n}, mode {k}, CFL {cfl}, T={steps * ht:g} "
-                               f"({steps} steps), {args.closure} closure, {args.lap} Laplacian, FP64",
+                               f"({steps} steps), {args.closure} closure, {args.lap} Laplacian, {prec_name}",
+                   "precision": args.precision,
                    "n": n, "mode": list(k), "cfl": cfl, "closure": args.closure,
-                   "lap_mode": args.lap, "solver": f"chebyshev x{sweeps}"},
+                   "lap_mode": args.lap,
+                   "solver": f"chebyshev x{sweeps}" if args.solver == "chebyshev" else "pcg"},
         "l2_vs_exact": l2_exact,
         "parity_sample": parity,
         "roofline": roofline,
@@ -342,7 +448,7 @@ def bench_3d(args):
     ht = r * h
     steps = args.steps if args.steps is not None else int(round(0.5 / ht))
     st = torch.cuda.Stream()
-    settings = dict(closure=args.closure, lap_mode=args.lap, precision=args.precision)
+    settings = dict(closure=args.closure, lap_mode=args.lap, precision=args.precision, solver=args.solver)
     init = mode_fields(3, n, (2, 3, 4), 0.0, ht / 2)
     p = Problem(3, n, r, stream=st, **settings)
     for name in p.fields():

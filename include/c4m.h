@@ -98,7 +98,7 @@ typedef struct {
     int32_t precision;  /* C4M_FP64 or C4M_FP32_REFINED                                */
     int32_t solver;     /* C4M_SOLVER_*                                                */
     int32_t sweeps;     /* Chebyshev M-applications per solve (0 = enough for 1e-16)   */
-    int32_t max_iter;   /* PCG iteration cap (0 = 50)                                  */
+    int32_t max_iter;   /* PCG iteration cap per solve (0 = 16)                         */
     double rtol;        /* PCG relative residual target (0 = 1e-14)                    */
     int32_t tile_x;     /* kernel tile override (0 = built-in / autotuned)             */
     int32_t tile_y;

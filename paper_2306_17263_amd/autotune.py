@@ -95,7 +95,8 @@ def tune_single(n: int, dim: int = 2, cfl: float = 0.5, steps: int = 8, use_cach
             return hit
     st = torch.cuda.Stream()
     timings = {}
-    shapes = SHAPES if dim == 2 else (0,)
+    # the 3D path and the FP32-refined form have one column-tile shape
+    shapes = SHAPES if dim == 2 and settings.get("precision", "fp64") == "fp64" else (0,)
     for shape in shapes:
         p = Problem(dim, n, cfl, stream=st, tile_x=shape, **settings)
         p.step(1)
@@ -121,7 +122,8 @@ def tune_batch(specs, steps: int = 4, use_cache: bool = True, **settings) -> dic
             return hit
     st = torch.cuda.Stream()
     timings = {}
-    for shape in SHAPES:
+    shapes = SHAPES if settings.get("precision", "fp64") == "fp64" else (0,)
+    for shape in shapes:
         for mult in GRID_MULT:
             b = Batch(specs, stream=st, tile_x=shape, tile_y=mult, **settings)
             b.step(1)

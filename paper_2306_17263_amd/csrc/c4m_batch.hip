@@ -78,12 +78,12 @@ __global__ __launch_bounds__(256) void k_batch_x(const BatchProb* __restrict__ b
         const int local = it - q.prefix[p];
         const int tx = bp[p].tiles_x[phase];
         const XArgs& xa = phase == PH_XE ? bp[p].xe : bp[p].xh;
-        xlines_tile<MODE>(xa, cf, taps, local % tx, local / tx);
+        xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, local % tx, local / tx);
     }
     finish(q);
 }
 
-template <int K, int MODE, class S>
+template <int K, int MODE, class S, int FORM>
 __global__ __launch_bounds__(S::NTC) __attribute__((amdgpu_waves_per_eu(S::NL == 4 ? 4 : 2))) void k_batch_col(
     const BatchProb* __restrict__ bp, PhaseQueue q, int total, int phase, Coef cf, PadeTaps taps,
     ChebSchedule cs)
@@ -97,13 +97,18 @@ __global__ __launch_bounds__(S::NTC) __attribute__((amdgpu_waves_per_eu(S::NL ==
         const int tx = bp[p].tiles_x[phase];
         const ColArgs& ca = phase == PH_CE ? bp[p].ce : (phase == PH_CHX ? bp[p].chx : bp[p].chy);
         const PadeLine& L = phase == PH_CE ? bp[p].xe.L : bp[p].xh.L;
-        col_tile<K, MODE, S>(ca, cf, taps, L, cs, local % tx, local / tx);
+        col_tile<K, MODE, S, FORM>(ca, cf, taps, L, cs, local % tx, local / tx);
     }
     finish(q);
 }
 
-static int col_tiles_k(int K, int shape, const UGrid& g, int* tx)
+static int col_tiles_k(int K, int shape, bool mixed, const UGrid& g, int* tx)
 {
+    if (mixed)
+        return with_k_mixed(K, [&]<int KK, class S>() {
+            *tx = col_tiles_x<KK, S>(g);
+            return col_tiles_x<KK, S>(g) * col_tiles_y<KK, S>(g);
+        });
     return with_k_shape(K, shape, [&]<int KK, class S>() {
         *tx = col_tiles_x<KK, S>(g);
         return col_tiles_x<KK, S>(g) * col_tiles_y<KK, S>(g);
@@ -128,9 +133,11 @@ static int blocks_x()
 }
 
 template <int MODE>
-static int blocks_col(int K, int shape)
+static int blocks_col(int K, int shape, bool mixed)
 {
-    return with_k_shape(K, shape, [&]<int KK, class S>() { return resident_blocks(k_batch_col<KK, MODE, S>, S::NTC); });
+    if (mixed)
+        return with_k_mixed(K, [&]<int KK, class S>() { return resident_blocks(k_batch_col<KK, MODE, S, FORM_MIXED>, S::NTC); });
+    return with_k_shape(K, shape, [&]<int KK, class S>() { return resident_blocks(k_batch_col<KK, MODE, S, FORM_FP64>, S::NTC); });
 }
 
 template <int MODE>
@@ -143,12 +150,20 @@ static hipError_t launch_bx(hipStream_t st, int blocks, const BatchProb* bp, con
 }
 
 template <int MODE>
-static hipError_t launch_bc(int K, int shape, hipStream_t st, int blocks, const BatchProb* bp, const PhaseQueue& q,
-                            int total, int phase, const Coef& cf, const PadeTaps& taps, const ChebSchedule& cs)
+static hipError_t launch_bc(int K, int shape, bool mixed, hipStream_t st, int blocks, const BatchProb* bp,
+                            const PhaseQueue& q, int total, int phase, const Coef& cf, const PadeTaps& taps,
+                            const ChebSchedule& cs)
 {
+    const int g = std::max(1, std::min(blocks, total));
+    if (mixed)
+        return with_k_mixed(K, [&]<int KK, class S>() {
+            hipLaunchKernelGGL((k_batch_col<KK, MODE, S, FORM_MIXED>), dim3(g), dim3(S::NTC), 0, st, bp, q, total, phase,
+                               cf, taps, cs);
+            return hipGetLastError();
+        });
     return with_k_shape(K, shape, [&]<int KK, class S>() {
-        const int g = std::max(1, std::min(blocks, total));
-        hipLaunchKernelGGL((k_batch_col<KK, MODE, S>), dim3(g), dim3(S::NTC), 0, st, bp, q, total, phase, cf, taps, cs);
+        hipLaunchKernelGGL((k_batch_col<KK, MODE, S, FORM_FP64>), dim3(g), dim3(S::NTC), 0, st, bp, q, total, phase, cf,
+                           taps, cs);
         return hipGetLastError();
     });
 }
@@ -197,6 +212,8 @@ c4m_status check_uniform(const c4m_config* cfgs, int32_t count)
     for (int i = 0; i < count; ++i) {
         const c4m_config& c = cfgs[i];
         if (c.dim != 2) return set_error(C4M_EINVAL, "batched form takes 2D problems");
+        if (c.solver != C4M_SOLVER_CHEBYSHEV)
+            return set_error(C4M_EINVAL, "batched form runs the fused Chebyshev solve only");
         if (c.cfl != cfgs[0].cfl || c.z != cfgs[0].z || c.closure != cfgs[0].closure ||
             c.lap_mode != cfgs[0].lap_mode || c.precision != cfgs[0].precision ||
             c.solver != cfgs[0].solver || c.sweeps != cfgs[0].sweeps || c.tile_x != cfgs[0].tile_x ||
@@ -217,6 +234,7 @@ size_t tables_bytes(int count)
 c4m_status launch_step(c4m_batch* b)
 {
     const bool tracked = b->base.lap_mode == C4M_LAP_TRACKED;
+    const bool mixed = b->base.precision == C4M_FP32_REFINED;
     const int K = b->cheb.sweeps;
     hipError_t e = hipSuccess;
     for (int ph = 0; ph < NPH && e == hipSuccess; ++ph) {
@@ -231,19 +249,19 @@ c4m_status launch_step(c4m_batch* b)
                             : launch_bx<XL_E_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe);
                 break;
             case PH_CE:
-                e = tracked ? launch_bc<COL_E_TRACKED>(K, b->base.tile_x, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb)
-                            : launch_bc<COL_E_DISCRETE>(K, b->base.tile_x, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb);
+                e = tracked ? launch_bc<COL_E_TRACKED>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb)
+                            : launch_bc<COL_E_DISCRETE>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb);
                 break;
             case PH_XH:
                 e = tracked ? launch_bx<XL_H_TRACKED>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh)
                             : launch_bx<XL_H_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh);
                 break;
             case PH_CHX:
-                e = tracked ? launch_bc<COL_HX_TRACKED>(K, b->base.tile_x, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb)
-                            : launch_bc<COL_HX_DISCRETE>(K, b->base.tile_x, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
+                e = tracked ? launch_bc<COL_HX_TRACKED>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb)
+                            : launch_bc<COL_HX_DISCRETE>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
                 break;
             default:
-                e = launch_bc<COL_HY>(K, b->base.tile_x, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
+                e = launch_bc<COL_HY>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
                 break;
         }
     }
@@ -285,6 +303,7 @@ c4m_status build_tables(c4m_batch* b, char* cur)
     std::vector<BatchProb> hp(count);
     std::vector<int> prefix((size_t)NPH * (count + 1), 0);
     const int shape = b->base.tile_x;
+    const bool mixed = b->base.precision == C4M_FP32_REFINED;
     for (int i = 0; i < count; ++i) {
         ProblemView v{};
         problem_view(b->probs[i], &v);
@@ -300,11 +319,11 @@ c4m_status build_tables(c4m_batch* b, char* cur)
         int tiles[NPH];
         d.tiles_x[PH_XE] = xlines_tiles_x(v.line[1].n_out);
         tiles[PH_XE] = d.tiles_x[PH_XE] * xlines_tiles_y(N);
-        tiles[PH_CE] = col_tiles_k(K, shape, d.ce.g, &d.tiles_x[PH_CE]);
+        tiles[PH_CE] = col_tiles_k(K, shape, mixed, d.ce.g, &d.tiles_x[PH_CE]);
         d.tiles_x[PH_XH] = xlines_tiles_x(v.line[0].n_out);
         tiles[PH_XH] = d.tiles_x[PH_XH] * xlines_tiles_y(N);
-        tiles[PH_CHX] = col_tiles_k(K, shape, d.chx.g, &d.tiles_x[PH_CHX]);
-        tiles[PH_CHY] = col_tiles_k(K, shape, d.chy.g, &d.tiles_x[PH_CHY]);
+        tiles[PH_CHX] = col_tiles_k(K, shape, mixed, d.chx.g, &d.tiles_x[PH_CHX]);
+        tiles[PH_CHY] = col_tiles_k(K, shape, mixed, d.chy.g, &d.tiles_x[PH_CHY]);
         for (int ph = 0; ph < NPH; ++ph)
             prefix[(size_t)ph * (count + 1) + i + 1] = prefix[(size_t)ph * (count + 1) + i] + tiles[ph];
         if (i == 0) {
@@ -319,10 +338,10 @@ c4m_status build_tables(c4m_batch* b, char* cur)
         const bool tracked = b->base.lap_mode == C4M_LAP_TRACKED;
         const int K = b->cheb.sweeps;
         b->blocks[PH_XE] = tracked ? blocks_x<XL_E_TRACKED>() : blocks_x<XL_E_DISCRETE>();
-        b->blocks[PH_CE] = tracked ? blocks_col<COL_E_TRACKED>(K, shape) : blocks_col<COL_E_DISCRETE>(K, shape);
+        b->blocks[PH_CE] = tracked ? blocks_col<COL_E_TRACKED>(K, shape, mixed) : blocks_col<COL_E_DISCRETE>(K, shape, mixed);
         b->blocks[PH_XH] = tracked ? blocks_x<XL_H_TRACKED>() : blocks_x<XL_H_DISCRETE>();
-        b->blocks[PH_CHX] = tracked ? blocks_col<COL_HX_TRACKED>(K, shape) : blocks_col<COL_HX_DISCRETE>(K, shape);
-        b->blocks[PH_CHY] = blocks_col<COL_HY>(K, shape);
+        b->blocks[PH_CHX] = tracked ? blocks_col<COL_HX_TRACKED>(K, shape, mixed) : blocks_col<COL_HX_DISCRETE>(K, shape, mixed);
+        b->blocks[PH_CHY] = blocks_col<COL_HY>(K, shape, mixed);
         const int mult = b->base.tile_y > 0 ? b->base.tile_y : 1;   // persistent grid multiplier
         for (int ph = 0; ph < NPH; ++ph) b->blocks[ph] *= mult;
     }

@@ -16,19 +16,29 @@ namespace c4m {
 hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const double* hy, double* t0,
                            double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                            const PadeLine& line_h2n);
-hipError_t launch_solve_e_2d(hipStream_t st, int shape, bool tracked, const double* hx, double* ez, double* ge,
+hipError_t launch_solve_e_2d(hipStream_t st, int shape, bool mixed, bool tracked, const double* hx, double* ez, double* ge,
                              const double* t0, const double* t1, int N, int P, const Coef& cf,
                              const PadeTaps& taps, const PadeLine& line_h2n, const ChebSchedule& cs);
 hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, double* t0, double* t1,
                            int N, int P, const Coef& cf, const PadeTaps& taps,
                            const PadeLine& line_n2h);
-hipError_t launch_solve_h_2d(hipStream_t st, int shape, bool tracked, const double* src, double* hx, double* hy,
+hipError_t launch_solve_h_2d(hipStream_t st, int shape, bool mixed, bool tracked, const double* src, double* hx, double* hy,
                              const double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                              const PadeLine& line_n2h, const ChebSchedule& cs);
+hipError_t launch_pcg_e_2d(hipStream_t st, bool tracked, const double* hx, double* ez, double* ge,
+                           const double* t0, double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
+                           const PadeLine& line_h2n, const ChebSchedule& cs, double* const* pt, double* part,
+                           PcgState* pst, double rtol, int max_iter);
+hipError_t launch_pcg_h_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy, double* t1,
+                           int N, int P, const Coef& cf, const PadeTaps& taps, const PadeLine& line_n2h,
+                           const ChebSchedule& cs, double* const* pt, double* part, PcgState* pst, double rtol,
+                           int max_iter);
 hipError_t launch_term3(hipStream_t st, int axis, int mode, const Term3& t, double alpha,
                         const PadeTaps& taps, const PadeLine& L);
 hipError_t launch_solve3(hipStream_t st, const Cheb3& c, double* field, double* ge, const double* cur,
                          const Coef& cf, const ChebSchedule& cs);
+hipError_t launch_solve3_mixed(hipStream_t st, const Cheb3& c, size_t arr, double* field, double* ge,
+                               const double* cur, const Coef& cf, const ChebSchedule& cs);
 hipError_t launch_zero_walls(hipStream_t st, double* a, const Box& bx, int P, size_t plane);
 hipError_t launch_lap_convert(hipStream_t st, double* a, const double* e, double* out, const Box& bx,
                               int P, size_t plane, double alpha, int mode);
@@ -164,6 +174,7 @@ PadeHost build_pade(int n_in, int closure, bool node_to_half)
     }
     auto Wi = [&](int k) { return (k < -PADE_R || k > PADE_R) ? 0.0 : wrow[k + PADE_R]; };
     for (int u = -PADE_R; u <= PADE_R + 1; ++u) ph.taps.c[u + PADE_R] = Wi(u - 1) - Wi(u);
+    if (!ph.all) ph.rows.insert(ph.rows.end(), ph.taps.c, ph.taps.c + PADE_TAPS);   // row 2 b
     return ph;
 }
 
@@ -216,7 +227,9 @@ struct c4m_problem {
     size_t ws_bytes = 0, used = 0;
     double* f[6] = {};                  // Ex Ey Ez Hx Hy Hz
     double* ge[3] = {};                 // G_E per E component (carried Laplacian)
-    double* tmp[5] = {};
+    double* tmp[8] = {};
+    double* pcg_part = nullptr;         // PCG per-workgroup partial sums
+    PcgState* pcg_state = nullptr;      // PCG scalars and statistics
     double* pade_dev[2] = {};           // [0] node->half (n_in N+1), [1] half->node (n_in N)
     int* counter = nullptr;
     PadeHost pade_host[2];
@@ -289,14 +302,18 @@ c4m_status validate(const c4m_config* c)
     const double bound = 5.0 / (6.0 * sqrt((double)c->dim));
     if (!(c->flags & C4M_FLAG_ALLOW_ANY_CFL) && c->cfl > bound * (1.0 + 1e-12))
         return fail(C4M_EUNSTABLE, "cfl above the stability bound 5/(6 sqrt(dim))");
-    if (c->precision != C4M_FP64 || c->solver != C4M_SOLVER_CHEBYSHEV)
-        return fail(C4M_EINVAL, "configuration not supported by this build");
+    if (c->solver == C4M_SOLVER_PCG && c->precision != C4M_FP64)
+        return fail(C4M_EINVAL, "the PCG solver runs in FP64 only");
+    if (c->max_iter < 0 || c->max_iter > 1000) return fail(C4M_EINVAL, "max_iter out of range");
+    if (!(c->rtol >= 0.0) || c->rtol >= 1.0) return fail(C4M_EINVAL, "rtol must be in [0, 1)");
+    if (c->precision == C4M_FP32_REFINED && (c->sweeps > 3 || (c->dim == 2 && c->tile_x != 0)))
+        return fail(C4M_EINVAL, "FP32 refinement: at most 3 sweeps per round and the default tile shape");
     return C4M_OK;
 }
 
 struct Layout {
     int P;
-    size_t plane, arr, arr_bytes, table_bytes[2], total;
+    size_t plane, arr, arr_bytes, table_bytes[2], pcg_bytes, total;
     int n_fields, n_ge, n_tmp;
 };
 
@@ -310,13 +327,17 @@ Layout layout(const c4m_config* c)
     L.arr_bytes = align256(L.arr * sizeof(double));
     L.n_fields = c->dim == 2 ? 3 : 6;
     L.n_ge = c->lap_mode == C4M_LAP_TRACKED ? (c->dim == 2 ? 1 : 3) : 0;
-    L.n_tmp = c->dim == 2 ? 2 : 5;
+    const bool pcg = c->solver == C4M_SOLVER_PCG;
+    // 2D: T0, T1 (+ x, r, two directions, M p, 1/diag for PCG);
+    // 3D: b, x, d0, d1, curl (+ M p, 1/diag for PCG)
+    L.n_tmp = c->dim == 2 ? (pcg ? 8 : 2) : (pcg ? 7 : 5);
+    L.pcg_bytes = pcg ? align256(3 * ((L.arr + 255) / 256) * sizeof(double)) + 256 : 0;
     for (int k = 0; k < 2; ++k) {
         const int n_out = (k == 0 ? N + 1 : N) - 1;
-        const int rows = n_out <= 2 * PADE_B ? n_out : 2 * PADE_B;
+        const int rows = n_out <= 2 * PADE_B ? n_out : 2 * PADE_B + 1;
         L.table_bytes[k] = align256((size_t)rows * PADE_TAPS * sizeof(double));
     }
-    L.total = (size_t)(L.n_fields + L.n_ge + L.n_tmp) * L.arr_bytes + L.table_bytes[0] +
+    L.total = (size_t)(L.n_fields + L.n_ge + L.n_tmp) * L.arr_bytes + L.pcg_bytes + L.table_bytes[0] +
               L.table_bytes[1] + 256;
     return L;
 }
@@ -412,6 +433,9 @@ c4m_status timed(c4m_problem* p, int cls, const char* what, F&& launch)
     return C4M_OK;
 }
 
+double pcg_rtol(const c4m_problem* p) { return p->cfg.rtol > 0.0 ? p->cfg.rtol : 1e-14; }
+int pcg_max_iter(const c4m_problem* p) { return p->cfg.max_iter > 0 ? p->cfg.max_iter : 16; }
+
 UGrid unknowns(const Box& b)
 {
     UGrid g{};
@@ -435,6 +459,25 @@ c4m_status step3(c4m_problem* p)
     const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
     const double z = p->coef.z;
     double *b = p->tmp[0], *x = p->tmp[1], *d0 = p->tmp[2], *d1 = p->tmp[3], *cur = p->tmp[4];
+    const bool pcg = p->cfg.solver == C4M_SOLVER_PCG;
+    auto pcg_args = [&](int comp) {
+        PcgArgs a{};
+        a.x = x;
+        a.r = b;
+        a.p[0] = d0;
+        a.p[1] = d1;
+        a.q = p->tmp[5];
+        a.dinv = p->tmp[6];
+        a.part = p->pcg_part;
+        a.st = p->pcg_state;
+        a.g = unknowns(p->box[comp]);
+        a.P = p->P;
+        a.plane = p->plane;
+        a.alpha = p->coef.alpha;
+        a.beta = p->coef.beta;
+        a.rtol2 = pcg_rtol(p) * pcg_rtol(p);
+        return a;
+    };
     c4m_status s = C4M_OK;
     auto term = [&](int axis, int src, int mode, double* out, double scale, int acc, int tgt, int line) {
         Term3 t{p->f[src], out, p->box[src], unknowns(p->box[tgt]), p->P, p->plane, scale, acc};
@@ -452,7 +495,13 @@ c4m_status step3(c4m_problem* p)
         });
         if (s != C4M_OK) break;
         s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
+            if (pcg)
+                return launch_pcg(p->stream, 3, pcg_args(c), pcg_max_iter(p), p->f[c], tracked ? p->ge[c] : nullptr,
+                                  cur, p->coef);
             Cheb3 ch{b, x, d0, d1, unknowns(p->box[c]), p->P, p->plane};
+            if (p->cfg.precision == C4M_FP32_REFINED)
+                return launch_solve3_mixed(p->stream, ch, p->arr, p->f[c], tracked ? p->ge[c] : nullptr, cur,
+                                           p->coef, p->cheb);
             return launch_solve3(p->stream, ch, p->f[c], tracked ? p->ge[c] : nullptr, cur, p->coef, p->cheb);
         });
     }
@@ -466,7 +515,12 @@ c4m_status step3(c4m_problem* p)
         });
         if (s != C4M_OK) break;
         s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
+            if (pcg)
+                return launch_pcg(p->stream, 3, pcg_args(3 + c), pcg_max_iter(p), p->f[3 + c], nullptr, nullptr,
+                                  p->coef);
             Cheb3 ch{b, x, d0, d1, unknowns(p->box[3 + c]), p->P, p->plane};
+            if (p->cfg.precision == C4M_FP32_REFINED)
+                return launch_solve3_mixed(p->stream, ch, p->arr, p->f[3 + c], nullptr, nullptr, p->coef, p->cheb);
             return launch_solve3(p->stream, ch, p->f[3 + c], nullptr, nullptr, p->coef, p->cheb);
         });
     }
@@ -484,9 +538,16 @@ c4m_status step_once(c4m_problem* p)
             return launch_rhs_e_2d(p->stream, tracked, hx, hy, t0, t1, N, P, p->coef,
                                    p->pade_host[1].taps, p->line[1]);
         });
-        if (s == C4M_OK)
+        const bool pcg = p->cfg.solver == C4M_SOLVER_PCG;
+        if (s == C4M_OK && pcg)
             s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
-                return launch_solve_e_2d(p->stream, p->cfg.tile_x, tracked, hx, ez, ge, t0, t1, N, P, p->coef,
+                return launch_pcg_e_2d(p->stream, tracked, hx, ez, ge, t0, t1, N, P, p->coef, p->pade_host[1].taps,
+                                       p->line[1], p->cheb, p->tmp + 2, p->pcg_part, p->pcg_state, pcg_rtol(p),
+                                       pcg_max_iter(p));
+            });
+        else if (s == C4M_OK)
+            s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
+                return launch_solve_e_2d(p->stream, p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, tracked, hx, ez, ge, t0, t1, N, P, p->coef,
                                          p->pade_host[1].taps, p->line[1], p->cheb);
             });
         if (s == C4M_OK)
@@ -494,9 +555,15 @@ c4m_status step_once(c4m_problem* p)
                 return launch_rhs_h_2d(p->stream, tracked, tracked ? ge : ez, t0, t1, N, P, p->coef,
                                        p->pade_host[0].taps, p->line[0]);
             });
-        if (s == C4M_OK)
+        if (s == C4M_OK && pcg)
             s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
-                return launch_solve_h_2d(p->stream, p->cfg.tile_x, tracked, tracked ? ge : ez, hx, hy, t1, N, P,
+                return launch_pcg_h_2d(p->stream, tracked, tracked ? ge : ez, hx, hy, t1, N, P, p->coef,
+                                       p->pade_host[0].taps, p->line[0], p->cheb, p->tmp + 2, p->pcg_part,
+                                       p->pcg_state, pcg_rtol(p), pcg_max_iter(p));
+            });
+        else if (s == C4M_OK)
+            s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
+                return launch_solve_h_2d(p->stream, p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, tracked, tracked ? ge : ez, hx, hy, t1, N, P,
                                          p->coef, p->pade_host[0].taps, p->line[0], p->cheb);
             });
         return s;
@@ -614,6 +681,10 @@ c4m_status c4m_create(const c4m_config* cfg, void* d_workspace, size_t bytes, vo
         for (int c = 0; c < 3; ++c)
             if (p->f[c]) p->ge[c] = (double*)take(L.arr_bytes);
     for (int t = 0; t < L.n_tmp; ++t) p->tmp[t] = (double*)take(L.arr_bytes);
+    if (L.pcg_bytes) {
+        p->pcg_state = (PcgState*)take(256);
+        p->pcg_part = (double*)take(L.pcg_bytes - 256);
+    }
     p->pade_dev[0] = (double*)take(L.table_bytes[0]);
     p->pade_dev[1] = (double*)take(L.table_bytes[1]);
     p->counter = (int*)take(256);
@@ -626,7 +697,15 @@ c4m_status c4m_create(const c4m_config* cfg, void* d_workspace, size_t bytes, vo
     p->coef.z = cfg->z;
     p->coef.ge_gain = 1.0 + 4.0 / (r * r);
     p->coef.ge_curl = 2.0 / r * cfg->z;
-    p->cheb = chebyshev(p->coef.alpha, p->coef.beta, cfg->sweeps, 1e-16);
+    if (cfg->precision == C4M_FP32_REFINED) {
+        // two FP32 rounds of s applications around one FP64 residual; the
+        // tile halo (and ChebSchedule::sweeps) is 2 s + 1
+        const int s_round = cfg->sweeps > 0 ? cfg->sweeps : 2;
+        p->cheb = chebyshev(p->coef.alpha, p->coef.beta, 2 * s_round + 1, 1e-16);
+        p->cheb.sweeps = 2 * s_round + 1;
+    } else {
+        p->cheb = chebyshev(p->coef.alpha, p->coef.beta, cfg->sweeps, 1e-16);
+    }
     set_alg_bytes(p);
 
     for (int k = 0; k < 2; ++k) {
@@ -759,6 +838,17 @@ c4m_status c4m_get_info(c4m_problem* p, c4m_info* info)
     info->workspace_bytes = p->used;
     c4m_status s = flush_profile(p);
     if (s != C4M_OK) return s;
+    if (p->pcg_state) {
+        PcgState h{};
+        hipError_t e = hipMemcpyAsync(&h, p->pcg_state, sizeof(h), hipMemcpyDeviceToHost, p->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+        if (e != hipSuccess) return hip_fail(e, "PCG statistics");
+        info->last_iters = h.last_iters;
+        info->max_iters = h.max_iters;
+        info->last_rel_residual = h.last_rel;
+        info->noconv = h.noconv;
+        info->sweeps = 0;
+    }
     for (int k = 0; k < C4M_K_COUNT; ++k) {
         info->kernel_ms[k] = p->kernel_ms[k];
         info->kernel_launches[k] = p->kernel_launches[k];

@@ -92,6 +92,42 @@ struct Cheb3 {
     size_t plane;
 };
 
+// PCG solve state on the device (one per problem).
+struct PcgState {
+    int arrived;          // workgroups that published their partials (reset by the last)
+    int done;             // residual target met: later kernels of the solve return at once
+    int iters;            // iterations of the current solve
+    int last_iters, max_iters, noconv;
+    double rz, bb, rr;    // <r, z>, <b, b>, <r, r>
+    double alpha, beta;   // step lengths of the current iteration
+    double last_rel;      // sqrt(rr / bb) at the end of the last solve
+};
+
+// Arrays of one PCG solve on one component grid (b in r on entry).
+struct PcgArgs {
+    double* x;
+    double* r;
+    double* p[2];         // search directions (alternate per iteration)
+    double* q;            // M p
+    double* dinv;         // 1 / diag(M)
+    double* part;         // [3][nparts] per-workgroup partial sums
+    PcgState* st;
+    UGrid g;
+    int P;
+    size_t plane;
+    int nparts;
+    double alpha, beta;   // M = alpha I - beta L9
+    double rtol2;         // squared relative residual target
+};
+
+// One PCG solve (c4m_pcg.hip): M x = b with b in a.r (overwritten), at most
+// max_iter iterations, then field += cfl x (and the G_E update when ge is
+// given, with cur the raw curl).  dim 2 uses the 9-point L9, dim 3 the
+// 19-point one.
+hipError_t launch_pcg(hipStream_t st, int dim, PcgArgs a, int max_iter, double* field, double* ge,
+                      const double* cur, const Coef& cf);
+size_t pcg_partials(const UGrid& g);
+
 // Internal view of a problem for the batched form (c4m_host.hip fills it).
 struct ProblemView {
     double* f[6];

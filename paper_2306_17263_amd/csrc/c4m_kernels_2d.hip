@@ -7,28 +7,45 @@ namespace c4m {
 template <int MODE>
 __global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps)
 {
-    xlines_tile<MODE>(xa, cf, taps, blockIdx.x, blockIdx.y);
+    xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, blockIdx.x, blockIdx.y);
 }
 
-template <int K, int MODE, class S>
+template <int K, int MODE, class S, int FORM>
 __global__ __launch_bounds__(S::NTC) __attribute__((amdgpu_waves_per_eu(S::NL == 4 ? 4 : 2))) void k_col(
     ColArgs a, Coef cf, PadeTaps taps, PadeLine L, ChebSchedule cs)
 {
-    col_tile<K, MODE, S>(a, cf, taps, L, cs, blockIdx.x, blockIdx.y);
+    col_tile<K, MODE, S, FORM>(a, cf, taps, L, cs, blockIdx.x, blockIdx.y);
 }
 
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
 template <int MODE>
-static hipError_t launch_col(int shape, hipStream_t st, const ColArgs& a, const Coef& cf, const PadeTaps& taps,
-                             const PadeLine& L, const ChebSchedule& cs)
+static hipError_t launch_col(int shape, bool mixed, hipStream_t st, const ColArgs& a, const Coef& cf,
+                             const PadeTaps& taps, const PadeLine& L, const ChebSchedule& cs)
 {
+    if (mixed)
+        return with_k_mixed(cs.sweeps, [&]<int K, class S>() {
+            const dim3 grid(col_tiles_x<K, S>(a.g), col_tiles_y<K, S>(a.g));
+            hipLaunchKernelGGL((k_col<K, MODE, S, FORM_MIXED>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);
+            return hipGetLastError();
+        });
     return with_k_shape(cs.sweeps, shape, [&]<int K, class S>() {
         const dim3 grid(col_tiles_x<K, S>(a.g), col_tiles_y<K, S>(a.g));
-        hipLaunchKernelGGL((k_col<K, MODE, S>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);
+        hipLaunchKernelGGL((k_col<K, MODE, S, FORM_FP64>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);
         return hipGetLastError();
     });
+}
+
+// Right-hand side only (no solve halo): b on the unknowns, and the raw curl
+// for the G_E update with the carried Laplacian.
+template <int MODE>
+static hipError_t launch_col_rhs(hipStream_t st, const ColArgs& a, const Coef& cf, const PadeTaps& taps,
+                                 const PadeLine& L, const ChebSchedule& cs)
+{
+    const dim3 grid(col_tiles_x<0, Shape0>(a.g), col_tiles_y<0, Shape0>(a.g));
+    hipLaunchKernelGGL((k_col<0, MODE, Shape0, FORM_RHS>), grid, dim3(Shape0::NTC), 0, st, a, cf, taps, L, cs);
+    return hipGetLastError();
 }
 
 hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const double* hy, double* t0,
@@ -46,13 +63,13 @@ hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const
     return hipGetLastError();
 }
 
-hipError_t launch_solve_e_2d(hipStream_t st, int shape, bool tracked, const double* hx, double* ez, double* ge,
+hipError_t launch_solve_e_2d(hipStream_t st, int shape, bool mixed, bool tracked, const double* hx, double* ez, double* ge,
                              const double* t0, const double* t1, int N, int P, const Coef& cf,
                              const PadeTaps& taps, const PadeLine& line_h2n, const ChebSchedule& cs)
 {
     ColArgs a{hx, t0, t1, ez, ge, ugrid_ez(N), N, P};
-    if (tracked) return launch_col<COL_E_TRACKED>(shape, st, a, cf, taps, line_h2n, cs);
-    return launch_col<COL_E_DISCRETE>(shape, st, a, cf, taps, line_h2n, cs);
+    if (tracked) return launch_col<COL_E_TRACKED>(shape, mixed, st, a, cf, taps, line_h2n, cs);
+    return launch_col<COL_E_DISCRETE>(shape, mixed, st, a, cf, taps, line_h2n, cs);
 }
 
 hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, double* t0, double* t1,
@@ -69,19 +86,72 @@ hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, doub
     return hipGetLastError();
 }
 
-hipError_t launch_solve_h_2d(hipStream_t st, int shape, bool tracked, const double* src, double* hx, double* hy,
+hipError_t launch_solve_h_2d(hipStream_t st, int shape, bool mixed, bool tracked, const double* src, double* hx, double* hy,
                              const double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                              const PadeLine& line_n2h, const ChebSchedule& cs)
 {
     // Hx: Dirichlet in x (nodes 1..N-1), Neumann in y (half points 0..N-1);
     // right-hand side -(1/Z) delta_y G_E along columns
     ColArgs ax{src, nullptr, nullptr, hx, nullptr, ugrid_hx(N), N, P};
-    hipError_t e = tracked ? launch_col<COL_HX_TRACKED>(shape, st, ax, cf, taps, line_n2h, cs)
-                           : launch_col<COL_HX_DISCRETE>(shape, st, ax, cf, taps, line_n2h, cs);
+    hipError_t e = tracked ? launch_col<COL_HX_TRACKED>(shape, mixed, st, ax, cf, taps, line_n2h, cs)
+                           : launch_col<COL_HX_DISCRETE>(shape, mixed, st, ax, cf, taps, line_n2h, cs);
     if (e != hipSuccess) return e;
     // Hy: Neumann in x, Dirichlet in y; right-hand side T1 from the x-lines
     ColArgs ay{nullptr, t1, nullptr, hy, nullptr, ugrid_hy(N), N, P};
-    return launch_col<COL_HY>(shape, st, ay, cf, taps, line_n2h, cs);
+    return launch_col<COL_HY>(shape, mixed, st, ay, cf, taps, line_n2h, cs);
+}
+
+// PCG forms of the two solves.  Temporaries: pt[0] x, pt[1] r (= b),
+// pt[2], pt[3] search directions, pt[4] M p, pt[5] 1/diag(M).
+static PcgArgs pcg_args(double* const* pt, const UGrid& g, int P, const Coef& cf, double* part, PcgState* pst,
+                        double rtol)
+{
+    PcgArgs a{};
+    a.x = pt[0];
+    a.r = pt[1];
+    a.p[0] = pt[2];
+    a.p[1] = pt[3];
+    a.q = pt[4];
+    a.dinv = pt[5];
+    a.part = part;
+    a.st = pst;
+    a.g = g;
+    a.P = P;
+    a.plane = 0;
+    a.alpha = cf.alpha;
+    a.beta = cf.beta;
+    a.rtol2 = rtol * rtol;
+    return a;
+}
+
+hipError_t launch_pcg_e_2d(hipStream_t st, bool tracked, const double* hx, double* ez, double* ge,
+                           const double* t0, double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
+                           const PadeLine& line_h2n, const ChebSchedule& cs, double* const* pt, double* part,
+                           PcgState* pst, double rtol, int max_iter)
+{
+    ColArgs a{hx, t0, t1, ez, ge, ugrid_ez(N), N, P, pt[1], t1};
+    hipError_t e = tracked ? launch_col_rhs<COL_E_TRACKED>(st, a, cf, taps, line_h2n, cs)
+                           : launch_col_rhs<COL_E_DISCRETE>(st, a, cf, taps, line_h2n, cs);
+    if (e != hipSuccess) return e;
+    return launch_pcg(st, 2, pcg_args(pt, ugrid_ez(N), P, cf, part, pst, rtol), max_iter, ez,
+                      tracked ? ge : nullptr, t1, cf);
+}
+
+hipError_t launch_pcg_h_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy, double* t1,
+                           int N, int P, const Coef& cf, const PadeTaps& taps, const PadeLine& line_n2h,
+                           const ChebSchedule& cs, double* const* pt, double* part, PcgState* pst, double rtol,
+                           int max_iter)
+{
+    ColArgs ax{src, nullptr, nullptr, hx, nullptr, ugrid_hx(N), N, P, pt[1], nullptr};
+    hipError_t e = tracked ? launch_col_rhs<COL_HX_TRACKED>(st, ax, cf, taps, line_n2h, cs)
+                           : launch_col_rhs<COL_HX_DISCRETE>(st, ax, cf, taps, line_n2h, cs);
+    if (e != hipSuccess) return e;
+    e = launch_pcg(st, 2, pcg_args(pt, ugrid_hx(N), P, cf, part, pst, rtol), max_iter, hx, nullptr, nullptr, cf);
+    if (e != hipSuccess) return e;
+    // Hy: the x-line right-hand side T1 is b
+    double* pty[6] = {pt[0], t1, pt[2], pt[3], pt[4], pt[5]};
+    return launch_pcg(st, 2, pcg_args(pty, ugrid_hy(N), P, cf, part, pst, rtol), max_iter, hy, nullptr, nullptr,
+                      cf);
 }
 
 }  // namespace c4m

@@ -28,7 +28,7 @@ __device__ __forceinline__ const double* pade_row3(const PadeLine& L, int m)
     if (L.all) return L.rows + (size_t)m * PADE_TAPS;
     if (m < L.b) return L.rows + (size_t)m * PADE_TAPS;
     if (m >= L.n_out - L.b) return L.rows + (size_t)(m - (L.n_out - L.b) + L.b) * PADE_TAPS;
-    return nullptr;
+    return L.rows + (size_t)(2 * L.b) * PADE_TAPS;   // the interior taps, stored after the boundary rows
 }
 
 // Source value at stored index q (q[D] may run outside the line: zero).
@@ -121,7 +121,7 @@ __global__ __launch_bounds__(256) void k_term3(Term3 t, double alpha, PadeTaps t
             double acc = 0.0;
             if (m < L.n_out) {
                 const double* cr = pade_row3(L, m);
-                for (int u = 0; u < PADE_TAPS; ++u) acc = fma(cr ? cr[u] : taps.c[u], w[k + u], acc);
+                for (int u = 0; u < PADE_TAPS; ++u) acc = fma(cr[u], w[k + u], acc);
             }
             out[k] = acc;
         }
@@ -222,6 +222,167 @@ __global__ void k_cheb3_final(Cheb3 c, const double* __restrict__ dlast, double*
     const double de = cf.cfl * (c.x[o] + dlast[o]);
     field[o] += de;
     if (ge) ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cur[o]);
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: two FP32 rounds x1 = C(b), x2 = C(b - M x1) around one
+// FP64 residual; the round arrays are FP32 views of the FP64 temporaries.
+// ---------------------------------------------------------------------------
+struct Cheb3f {
+    float* r;
+    float* x;
+    float* d0;
+    float* d1;
+    UGrid g;
+    int P;
+    size_t plane;
+};
+
+__device__ __forceinline__ float dvalf(const Cheb3f& c, const float* d, int i, int j, int k)
+{
+    int q[3] = {i, j, k};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (q[a] < c.g.lo[a]) {
+            if (!c.g.neumann[a]) return 0.f;
+            q[a] = c.g.lo[a];
+        } else if (q[a] >= c.g.hi[a]) {
+            if (!c.g.neumann[a]) return 0.f;
+            q[a] = c.g.hi[a] - 1;
+        }
+    }
+    return d[q[2] * c.plane + (size_t)q[1] * c.P + q[0]];
+}
+
+template <class T, class V>
+__device__ __forceinline__ T l9_3d(const V& c, const T* d, int i, int j, int k, T (*val)(const V&, const T*, int, int, int))
+{
+    T faces = 0, edges = 0;
+    faces += val(c, d, i - 1, j, k) + val(c, d, i + 1, j, k);
+    faces += val(c, d, i, j - 1, k) + val(c, d, i, j + 1, k);
+    faces += val(c, d, i, j, k - 1) + val(c, d, i, j, k + 1);
+    for (int a = -1; a <= 1; a += 2)
+        for (int b = -1; b <= 1; b += 2) {
+            edges += val(c, d, i + a, j + b, k);
+            edges += val(c, d, i, j + a, k + b);
+            edges += val(c, d, i + a, j, k + b);
+        }
+    return (T(2) * faces + edges - T(24) * d[k * c.plane + (size_t)j * c.P + i]) * T(1.0 / 6.0);
+}
+
+// r32 = (float) src, d = r32 / theta, x = 0
+__global__ void k_cheb3f_init2(Cheb3f c, const float* __restrict__ src, float inv_theta)
+{
+    int i, j, k;
+    if (!cell3(c.g, i, j, k)) return;
+    const size_t o = k * c.plane + (size_t)j * c.P + i;
+    const float r0 = src[o];
+    c.r[o] = r0;
+    c.d0[o] = r0 * inv_theta;
+    c.x[o] = 0.f;
+}
+
+__global__ void k_cheb3f_init(Cheb3f c, const double* __restrict__ src, float inv_theta)
+{
+    int i, j, k;
+    if (!cell3(c.g, i, j, k)) return;
+    const size_t o = k * c.plane + (size_t)j * c.P + i;
+    const float r0 = (float)src[o];
+    c.r[o] = r0;
+    c.d0[o] = r0 * inv_theta;
+    c.x[o] = 0.f;
+}
+
+__global__ void k_cheb3f_sweep(Cheb3f c, const float* __restrict__ din, float* __restrict__ dout, float alpha,
+                               float beta, float c1, float c2, int last)
+{
+    int i, j, k;
+    if (!cell3(c.g, i, j, k)) return;
+    const size_t o = k * c.plane + (size_t)j * c.P + i;
+    const float dc = din[o];
+    const float ad = fmaf(alpha, dc, -beta * l9_3d<float, Cheb3f>(c, din, i, j, k, dvalf));
+    const float x = c.x[o] + dc;
+    const float rn = c.r[o] - ad;
+    c.r[o] = rn;
+    const float dn = fmaf(c1, dc, c2 * rn);
+    dout[o] = dn;
+    c.x[o] = last ? x + dn : x;          // the last sweep folds in x_{K+1} = x_K + d_K
+}
+
+__device__ __forceinline__ double dval1(const Cheb3f& c, const float* d, int i, int j, int k)
+{
+    return (double)dvalf(c, d, i, j, k);
+}
+
+// res = b - M x1 in FP64 (x1 is exactly representable), stored as FP32
+__global__ void k_cheb3f_resid(Cheb3f c, const double* __restrict__ b, const float* __restrict__ x1,
+                               float* __restrict__ res, double alpha, double beta)
+{
+    int i, j, k;
+    if (!cell3(c.g, i, j, k)) return;
+    const size_t o = k * c.plane + (size_t)j * c.P + i;
+    double faces = 0, edges = 0;
+    faces += dval1(c, x1, i - 1, j, k) + dval1(c, x1, i + 1, j, k);
+    faces += dval1(c, x1, i, j - 1, k) + dval1(c, x1, i, j + 1, k);
+    faces += dval1(c, x1, i, j, k - 1) + dval1(c, x1, i, j, k + 1);
+    for (int a = -1; a <= 1; a += 2)
+        for (int bb = -1; bb <= 1; bb += 2) {
+            edges += dval1(c, x1, i + a, j + bb, k);
+            edges += dval1(c, x1, i, j + a, k + bb);
+            edges += dval1(c, x1, i + a, j, k + bb);
+        }
+    const double xc = (double)x1[o];
+    const double l9 = (2.0 * faces + edges - 24.0 * xc) * (1.0 / 6.0);
+    res[o] = (float)(b[o] - fma(alpha, xc, -beta * l9));
+}
+
+__global__ void k_cheb3f_final(Cheb3f c, const float* __restrict__ x1, const float* __restrict__ x2, double* field,
+                               double* ge, const double* cur, Coef cf)
+{
+    int i, j, k;
+    if (!cell3(c.g, i, j, k)) return;
+    const size_t o = k * c.plane + (size_t)j * c.P + i;
+    const double de = cf.cfl * ((double)x1[o] + (double)x2[o]);
+    field[o] += de;
+    if (ge) ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cur[o]);
+}
+
+hipError_t launch_solve3_mixed(hipStream_t st, const Cheb3& c, size_t arr, double* field, double* ge,
+                               const double* cur, const Coef& cf, const ChebSchedule& cs)
+{
+    const long cells = (long)(c.g.hi[0] - c.g.lo[0]) * (c.g.hi[1] - c.g.lo[1]) * (c.g.hi[2] - c.g.lo[2]);
+    const dim3 grid((unsigned)((cells + 255) / 256));
+    // FP32 views: x1 | x2 in the x array, d0 | d1 in d0, the round residual in d1
+    float* x1 = reinterpret_cast<float*>(c.x);
+    float* x2 = x1 + arr;
+    float* d0 = reinterpret_cast<float*>(c.d0);
+    float* d1 = d0 + arr;
+    float* rr = reinterpret_cast<float*>(c.d1);
+    float* res = rr + arr;
+    const int s_round = (cs.sweeps - 1) / 2;
+    for (int round = 0; round < 2; ++round) {
+        Cheb3f f{rr, round == 0 ? x1 : x2, d0, d1, c.g, c.P, c.plane};
+        if (round == 0)
+            hipLaunchKernelGGL(k_cheb3f_init, grid, dim3(256), 0, st, f, (const double*)c.r, cs.inv_thetaf);
+        else {
+            hipLaunchKernelGGL(k_cheb3f_resid, grid, dim3(256), 0, st, f, (const double*)c.r, x1, res, cf.alpha,
+                               cf.beta);
+            // round 2 starts from the residual (kept in FP32)
+            hipLaunchKernelGGL(k_cheb3f_init2, grid, dim3(256), 0, st, f, res, cs.inv_thetaf);
+        }
+        float* din = d0;
+        float* dout = d1;
+        for (int k = 0; k < s_round; ++k) {
+            hipLaunchKernelGGL(k_cheb3f_sweep, grid, dim3(256), 0, st, f, din, dout, (float)cf.alpha, (float)cf.beta,
+                               cs.c1f[k], cs.c2f[k], k == s_round - 1 ? 1 : 0);
+            float* tmp = din;
+            din = dout;
+            dout = tmp;
+        }
+    }
+    hipLaunchKernelGGL(k_cheb3f_final, grid, dim3(256), 0, st, Cheb3f{rr, x1, d0, d1, c.g, c.P, c.plane}, x1, x2,
+                       field, ge, cur, cf);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -27,12 +27,20 @@
 
 namespace c4m {
 
+// Read-only device memory seen through the AMDGPU constant address space
+// (loads with a wave-uniform address become scalar loads).
+typedef const __attribute__((address_space(4))) double CDouble;
+__device__ __forceinline__ CDouble* as_const(const double* p)
+{
+    return (CDouble*)p;
+}
+
 __device__ __forceinline__ const double* pade_row(const PadeLine& L, int m)
 {
     if (L.all) return L.rows + (size_t)m * PADE_TAPS;
     if (m < L.b) return L.rows + (size_t)m * PADE_TAPS;
     if (m >= L.n_out - L.b) return L.rows + (size_t)(m - (L.n_out - L.b) + L.b) * PADE_TAPS;
-    return nullptr;
+    return L.rows + (size_t)(2 * L.b) * PADE_TAPS;   // the interior taps, stored after the boundary rows
 }
 
 __device__ __forceinline__ bool pade_interior(const PadeLine& L, int m_lo, int m_hi)
@@ -65,14 +73,10 @@ struct XArgs {
 };
 
 template <int MODE>
-__device__ __forceinline__ void xlines_tile(const XArgs& xa, const Coef& cf, const PadeTaps& taps, int bxi,
-                                            int byi)
+__device__ __forceinline__ void xlines_tile(const double* __restrict__ src, double* __restrict__ t0,
+                                            double* __restrict__ t1, int N, int P, const PadeLine& L,
+                                            const Coef& cf, const PadeTaps& taps, int bxi, int byi)
 {
-    const double* __restrict__ src = xa.src;
-    double* __restrict__ t0 = xa.t0;
-    double* __restrict__ t1 = xa.t1;
-    const int N = xa.N, P = xa.P;
-    const PadeLine& L = xa.L;
     constexpr bool E = MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE;
     constexpr bool TWO = MODE == XL_E_TRACKED;     // raw derivative as well
     __shared__ double sg[XT_ROWS * XT_STRIDE];
@@ -148,7 +152,7 @@ __device__ __forceinline__ void xlines_tile(const XArgs& xa, const Coef& cf, con
             if (m < L.n_out) {
                 const double* cr = pade_row(L, m);
                 for (int u = 0; u < PADE_TAPS; ++u) {
-                    const double c = cr ? cr[u] : taps.c[u];
+                    const double c = cr[u];
                     a = fma(c, wg[k + u], a);
                     if (TWO) b = fma(c, wr[k + u], b);
                 }
@@ -214,6 +218,12 @@ struct ColShape {
 
 enum { COL_E_TRACKED = 0, COL_E_DISCRETE = 1, COL_HX_TRACKED = 2, COL_HX_DISCRETE = 3, COL_HY = 4 };
 
+// What the column tile does after forming the right-hand side: the FP64
+// Chebyshev solve and update, the FP32-refined solve and update, or only
+// store the right-hand side (and the raw curl for the G_E update) for a
+// separate solver.
+enum { FORM_FP64 = 0, FORM_MIXED = 1, FORM_RHS = 2 };
+
 struct ColArgs {
     const double* src;      // y-line source: Hx (E step) or G_E / Ez (Hx step)
     const double* t0;       // precomputed right-hand side part (T0 or T1), or null
@@ -222,9 +232,144 @@ struct ColArgs {
     double* ge;             // G_E (E step, carried Laplacian)
     UGrid g;                // unknowns of the solved component
     int N, P;
+    double* b_out;          // FORM_RHS: right-hand side on the unknowns
+    double* cv_out;         // FORM_RHS, carried Laplacian: curl^A H (may alias t1)
 };
 
-template <int K, int MODE, class S>
+// Per-lane boundary description of a column tile; the row masks are
+// recomputed where needed rather than held in registers.
+struct ColCtx {
+    bool inner;                     // region strictly inside the unknowns: no boundary handling
+    bool mirror_lo_x, mirror_hi_x;  // Neumann mirror of the column sums at the x ends
+    bool col_active, ny;            // the column holds unknowns; Neumann along y
+    int gy0, ylo, yhi;              // grid row of this lane's row 0; unknown rows [ylo, yhi)
+    int part, lane;
+    __device__ __forceinline__ bool act(int t) const
+    {
+        const int gy = gy0 + t;
+        return col_active && gy >= ylo && gy < yhi;
+    }
+};
+
+// (M v)[t] on this lane's rows, handed to upd(t, m, act) row by row (m is
+// zero off the unknowns), with L9 v = (S(x-1) + S(x+1) + 4 S(x) - 36 v) / 6
+// and S = v(y-1) + 4 v(y) + v(y+1).  The rows next to the part split cross
+// through bnd; the column sums through the LDS.  upd may overwrite v[t]:
+// row t is the last use of v[t].  Two barriers; inner tiles take a path
+// without boundary tests.
+template <int HR, class S, class T, class F>
+__device__ __forceinline__ void apply_m(const ColCtx& c, const T (&v)[HR], T* lds, T* bnd, double alpha,
+                                        double beta, F&& upd)
+{
+    constexpr int CW = S::CW, CWP = S::CWP, NL = S::NL;
+    bnd[(c.part * 2 + 0) * CW + c.lane] = v[0];   // [part][first/last][column]
+    bnd[(c.part * 2 + 1) * CW + c.lane] = v[HR - 1];
+    __syncthreads();
+    const T above = c.part > 0 ? bnd[((c.part - 1) * 2 + 1) * CW + c.lane] : T(0);
+    const T below = c.part < NL - 1 ? bnd[((c.part + 1) * 2 + 0) * CW + c.lane] : T(0);
+    T* my = lds + c.lane + 1 + c.part * HR * CWP;
+    const T b6 = T(beta * (1.0 / 6.0));
+    const T a36 = T(fma(36.0, beta * (1.0 / 6.0), alpha));
+    T sown[HR];
+    if (c.inner) {
+#pragma unroll
+        for (int t = 0; t < HR; ++t) {
+            const T up = t > 0 ? v[t - 1] : above;
+            const T dn = t < HR - 1 ? v[t + 1] : below;
+            sown[t] = fma(T(4), v[t], up + dn);
+            my[t * CWP] = sown[t];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < HR; ++t) {
+            const T* q = my + t * CWP;
+            upd(t, fma(a36, v[t], -b6 * fma(T(4), sown[t], q[-1] + q[1])), true);
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < HR; ++t) {
+            const int gy = c.gy0 + t;
+            T up = t > 0 ? v[t - 1] : above;
+            T dn = t < HR - 1 ? v[t + 1] : below;
+            if (c.ny && gy == c.ylo) up = v[t];
+            if (c.ny && gy == c.yhi - 1) dn = v[t];
+            sown[t] = fma(T(4), v[t], up + dn);
+            my[t * CWP] = sown[t];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < HR; ++t) {
+            const T* q = my + t * CWP;
+            T sl = q[-1], sr = q[1];
+            if (c.mirror_lo_x) sl = sown[t];
+            if (c.mirror_hi_x) sr = sown[t];
+            const T m = fma(a36, v[t], -b6 * fma(T(4), sown[t], sl + sr));
+            const bool a = c.act(t);
+            upd(t, a ? m : T(0), a);
+        }
+    }
+}
+
+// One FP32 Chebyshev round of NSW applications of M on the FP64 right-hand
+// side b (unchanged); x receives the round's solution.
+template <int HR, class S, int NSW>
+__device__ __forceinline__ void cheb32(const ColCtx& c, const double (&b)[HR], float (&x)[HR], float* lds,
+                                       float* bnd, const Coef& cf, const ChebSchedule& cs)
+{
+    float d[HR], r[HR];
+#pragma unroll
+    for (int t = 0; t < HR; ++t) {
+        r[t] = (float)b[t];
+        d[t] = r[t] * cs.inv_thetaf;
+        x[t] = 0.f;
+    }
+#pragma unroll
+    for (int k = 0; k < NSW; ++k) {
+        const float c1 = cs.c1f[k], c2 = cs.c2f[k];
+        apply_m<HR, S>(c, d, lds, bnd, cf.alpha, cf.beta, [&](int t, float m, bool a) {
+            x[t] += d[t];
+            r[t] -= m;
+            d[t] = a ? fmaf(c1, d[t], c2 * r[t]) : 0.f;
+        });
+    }
+#pragma unroll
+    for (int t = 0; t < HR; ++t) x[t] += d[t];
+}
+
+// Truncated Pade line derivative of the streamed line window f for this
+// lane's HR outputs (output t uses f[t + 1 .. t + PADE_TAPS]).  Interior
+// windows run tap-outer so that one tap is live at a time; each output still
+// accumulates its taps in ascending order.  Windows near the line ends take
+// their rows from the boundary table.
+template <int HR, int NPOS>
+__device__ __forceinline__ void line_fir(bool fast, const PadeLine& L, int mfirst, CDouble* tc,
+                                         const double (&f)[NPOS], double (&out)[HR])
+{
+    if (fast) {
+#pragma unroll
+        for (int t = 0; t < HR; ++t) out[t] = 0.0;
+#pragma unroll
+        for (int u = 0; u < PADE_TAPS; ++u) {
+            const double c = tc[u];
+#pragma unroll
+            for (int t = 0; t < HR; ++t) out[t] = fma(c, f[t + 1 + u], out[t]);
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < HR; ++t) {
+            const int m = mfirst + t;
+            double a = 0.0;
+            if (m >= 0 && m < L.n_out) {
+                CDouble* cr = as_const(pade_row(L, m));
+#pragma unroll
+                for (int u = 0; u < PADE_TAPS; ++u) a = fma(cr[u], f[t + 1 + u], a);
+            }
+            out[t] = a;
+        }
+    }
+}
+
+template <int K, int MODE, class S, int FORM = FORM_FP64>
 __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const PadeTaps& taps,
                                          const PadeLine& L, const ChebSchedule& cs, int bxi, int byi)
 {
@@ -238,7 +383,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const
     constexpr bool ESTEP = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE;
     constexpr int NPOS = HR + PADE_TAPS - 1 + 2;    // streamed line positions (+1 each side for G)
     __shared__ double lds[TR * CWP];
-    __shared__ double bnd[2][NL][2][CW];            // [parity][part][0: first row, 1: last row][column]
+    __shared__ double bnd[2 * NL * 2 * CW];         // [parity][part][0: first row, 1: last row][column]
 
     const int tid = threadIdx.x;
     const int lane = tid % CW;                      // region column
@@ -270,6 +415,9 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const
         const bool half_line = ESTEP;
         const bool fast = pade_interior(L, mfirst < 0 ? 0 : mfirst, mfirst + HR - 1);
         const double* colp = a.src + gx;
+        // interior taps: the table row after the boundary rows, read through
+        // the constant address space so the uniform loads go to SGPRs
+        const CDouble* tc = as_const(L.rows + (L.all ? 0 : (size_t)(2 * L.b) * PADE_TAPS));
         double f[NPOS];
 #pragma unroll
         for (int p = 0; p < NPOS; ++p) {
@@ -279,20 +427,9 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const
         if (SPLIT) {
             // raw line derivative P: its second difference across lines
             // completes G; with the carried Laplacian it is also curl^A H
+            line_fir<HR>(fast, L, mfirst, tc, f, cv);
 #pragma unroll
-            for (int t = 0; t < HR; ++t) {
-                const int m = mfirst + t;
-                double ap = 0.0;
-                if (fast) {
-#pragma unroll
-                    for (int u = 0; u < PADE_TAPS; ++u) ap = fma(taps.c[u], f[t + 1 + u], ap);
-                } else if (m >= 0 && m < L.n_out) {
-                    const double* cr = pade_row(L, m);
-                    for (int u = 0; u < PADE_TAPS; ++u) ap = fma(cr ? cr[u] : taps.c[u], f[t + 1 + u], ap);
-                }
-                my[t * CWP] = ap;
-                cv[t] = ap;
-            }
+            for (int t = 0; t < HR; ++t) my[t * CWP] = cv[t];
             // in place: f -> alpha f + (second difference along the line) / 12;
             // half-point lines take even ghosts at their ends, node lines of
             // E vanish on the walls
@@ -314,19 +451,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const
             }
         }
         // line derivative of the conditioned input
-#pragma unroll
-        for (int t = 0; t < HR; ++t) {
-            const int m = mfirst + t;
-            double aq = 0.0;
-            if (fast) {
-#pragma unroll
-                for (int u = 0; u < PADE_TAPS; ++u) aq = fma(taps.c[u], f[t + 1 + u], aq);
-            } else if (m >= 0 && m < L.n_out) {
-                const double* cr = pade_row(L, m);
-                for (int u = 0; u < PADE_TAPS; ++u) aq = fma(cr ? cr[u] : taps.c[u], f[t + 1 + u], aq);
-            }
-            r[t] = aq;
-        }
+        line_fir<HR>(fast, L, mfirst, tc, f, r);
         if (SPLIT) {
             __syncthreads();
             // cross-line part of G: (P(x-1) + P(x+1) - 2 P(x)) / 12
@@ -364,80 +489,129 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const
         }
     }
 
-    // ---------------- Chebyshev on [alpha, alpha + 16/3 beta] ----------------
-    // L9 d = (S(x-1) + S(x+1) + 4 S(x) - 36 d) / 6; A d = alpha d - beta L9 d.
-    const double b6 = cf.beta * (1.0 / 6.0);
-    const double a36 = fma(36.0, b6, cf.alpha);
-    const bool nx = g.neumann[0], ny = g.neumann[1];
-    const bool at_lo_x = gx == g.lo[0], at_hi_x = gx == g.hi[0] - 1;
-    const int rx0 = x0 - HALO_X, ry0 = y0 - K;
-    const bool inner = rx0 > g.lo[0] && rx0 + CW < g.hi[0] && ry0 > g.lo[1] && ry0 + TR < g.hi[1];
-    double d[HR], xs[HR], sown[HR];
+    if (FORM == FORM_RHS) {
+        if (lane < HALO_X || lane >= CW - HALO_X || !col_active) return;
 #pragma unroll
-    for (int t = 0; t < HR; ++t) {
-        d[t] = r[t] * cs.inv_theta;
-        xs[t] = 0.0;
-    }
-    bnd[0][part][0][lane] = d[0];
-    bnd[0][part][1][lane] = d[HR - 1];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const int par = k & 1;
-        const double above = part > 0 ? bnd[par][part - 1][1][lane] : 0.0;
-        const double below = part < NL - 1 ? bnd[par][part + 1][0][lane] : 0.0;
-        const double c1 = cs.c1[k], c2 = cs.c2[k];
-        if (inner) {
-#pragma unroll
-            for (int t = 0; t < HR; ++t) {
-                const double up = t > 0 ? d[t - 1] : above;
-                const double dn = t < HR - 1 ? d[t + 1] : below;
-                sown[t] = fma(4.0, d[t], up + dn);
-                my[t * CWP] = sown[t];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int t = 0; t < HR; ++t) {
-                const double* q = my + t * CWP;
-                const double side = q[-1] + q[1];
-                const double dc = d[t];
-                const double ad = fma(a36, dc, -b6 * fma(4.0, sown[t], side));
-                xs[t] += dc;
-                r[t] -= ad;
-                d[t] = fma(c1, dc, c2 * r[t]);
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < HR; ++t) {
-                const int gy = ry0 + rbase + t;
-                double up = t > 0 ? d[t - 1] : above;
-                double dn = t < HR - 1 ? d[t + 1] : below;
-                if (ny && gy == g.lo[1]) up = d[t];
-                if (ny && gy == g.hi[1] - 1) dn = d[t];
-                sown[t] = fma(4.0, d[t], up + dn);
-                my[t * CWP] = sown[t];
-            }
-            __syncthreads();
-#pragma unroll
-            for (int t = 0; t < HR; ++t) {
-                const int gy = ry0 + rbase + t;
-                const double* q = my + t * CWP;
-                const double sc = sown[t];
-                double sl = q[-1], sr = q[1];
-                if (nx && at_lo_x) sl = sc;
-                if (nx && at_hi_x) sr = sc;
-                const double dc = d[t];
-                const double ad = fma(a36, dc, -b6 * fma(4.0, sc, sl + sr));
-                const bool act = col_active && gy >= g.lo[1] && gy < g.hi[1];
-                xs[t] += dc;
-                const double rn = r[t] - ad;
-                r[t] = act ? rn : 0.0;
-                d[t] = act ? fma(c1, dc, c2 * rn) : 0.0;
-            }
+        for (int t = 0; t < HR; ++t) {
+            const int row = rbase + t;
+            if (row < K || row >= K + OH) continue;
+            const int gy = y0 - K + row;
+            if (gy >= g.hi[1]) continue;
+            const size_t o = (size_t)gy * P + gx;
+            a.b_out[o] = r[t];
+            if (MODE == COL_E_TRACKED) a.cv_out[o] = cv[t];
         }
-        bnd[par ^ 1][part][0][lane] = d[0];
-        bnd[par ^ 1][part][1][lane] = d[HR - 1];
+        return;
+    }
+
+    // ---------------- solve M Phi = b (b in r[]) ----------------
+    const bool nx = g.neumann[0], ny = g.neumann[1];
+    const int rx0 = x0 - HALO_X, ry0 = y0 - K;
+    ColCtx ctx;
+    ctx.inner = rx0 > g.lo[0] && rx0 + CW < g.hi[0] && ry0 > g.lo[1] && ry0 + TR < g.hi[1];
+    ctx.mirror_lo_x = nx && gx == g.lo[0];
+    ctx.mirror_hi_x = nx && gx == g.hi[0] - 1;
+    ctx.col_active = col_active;
+    ctx.ny = ny;
+    ctx.gy0 = ry0 + rbase;
+    ctx.ylo = g.lo[1];
+    ctx.yhi = g.hi[1];
+    ctx.part = part;
+    ctx.lane = lane;
+    double phi[HR];
+    if (FORM == FORM_FP64) {
+        // Chebyshev on [alpha, alpha + 16/3 beta] in FP64, K applications;
+        // L9 d = (S(x-1) + S(x+1) + 4 S(x) - 36 d) / 6, A d = alpha d - beta L9 d
+        const double b6 = cf.beta * (1.0 / 6.0);
+        const double a36 = fma(36.0, b6, cf.alpha);
+        const bool at_lo_x = gx == g.lo[0], at_hi_x = gx == g.hi[0] - 1;
+        const bool inner = ctx.inner;
+        double d[HR], xs[HR], sown[HR];
+#pragma unroll
+        for (int t = 0; t < HR; ++t) {
+            d[t] = r[t] * cs.inv_theta;
+            xs[t] = 0.0;
+        }
+        bnd[(part * 2 + 0) * CW + lane] = d[0];
+        bnd[(part * 2 + 1) * CW + lane] = d[HR - 1];
         __syncthreads();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const double* bp = bnd + (k & 1) * (NL * 2 * CW);
+            double* bq = bnd + ((k & 1) ^ 1) * (NL * 2 * CW);
+            const double above = part > 0 ? bp[((part - 1) * 2 + 1) * CW + lane] : 0.0;
+            const double below = part < NL - 1 ? bp[((part + 1) * 2 + 0) * CW + lane] : 0.0;
+            const double c1 = cs.c1[k], c2 = cs.c2[k];
+            if (inner) {
+#pragma unroll
+                for (int t = 0; t < HR; ++t) {
+                    const double up = t > 0 ? d[t - 1] : above;
+                    const double dn = t < HR - 1 ? d[t + 1] : below;
+                    sown[t] = fma(4.0, d[t], up + dn);
+                    my[t * CWP] = sown[t];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int t = 0; t < HR; ++t) {
+                    const double* q = my + t * CWP;
+                    const double dc = d[t];
+                    const double ad = fma(a36, dc, -b6 * fma(4.0, sown[t], q[-1] + q[1]));
+                    xs[t] += dc;
+                    r[t] -= ad;
+                    d[t] = fma(c1, dc, c2 * r[t]);
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < HR; ++t) {
+                    const int gy = ry0 + rbase + t;
+                    double up = t > 0 ? d[t - 1] : above;
+                    double dn = t < HR - 1 ? d[t + 1] : below;
+                    if (ny && gy == g.lo[1]) up = d[t];
+                    if (ny && gy == g.hi[1] - 1) dn = d[t];
+                    sown[t] = fma(4.0, d[t], up + dn);
+                    my[t * CWP] = sown[t];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int t = 0; t < HR; ++t) {
+                    const int gy = ry0 + rbase + t;
+                    const double* q = my + t * CWP;
+                    const double sc = sown[t];
+                    double sl = q[-1], sr = q[1];
+                    if (nx && at_lo_x) sl = sc;
+                    if (nx && at_hi_x) sr = sc;
+                    const double dc = d[t];
+                    const double ad = fma(a36, dc, -b6 * fma(4.0, sc, sl + sr));
+                    const bool act = col_active && gy >= g.lo[1] && gy < g.hi[1];
+                    xs[t] += dc;
+                    const double rn = r[t] - ad;
+                    r[t] = act ? rn : 0.0;
+                    d[t] = act ? fma(c1, dc, c2 * rn) : 0.0;
+                }
+            }
+            bq[(part * 2 + 0) * CW + lane] = d[0];
+            bq[(part * 2 + 1) * CW + lane] = d[HR - 1];
+            __syncthreads();
+        }
+#pragma unroll
+        for (int t = 0; t < HR; ++t) phi[t] = xs[t] + d[t];
+    } else {
+        // two FP32 Chebyshev rounds with an FP64 residual between them:
+        // x1 = C(b), res = b - M x1 (FP64), Phi = x1 + C(res)
+        constexpr int K1 = (K - 1) / 2, K2 = K - 1 - K1;
+        float* ldsf = reinterpret_cast<float*>(lds);
+        float* bndf = reinterpret_cast<float*>(bnd);
+        float x1[HR];
+        cheb32<HR, S, K1>(ctx, r, x1, ldsf, bndf, cf, cs);
+        double xd[HR];
+#pragma unroll
+        for (int t = 0; t < HR; ++t) xd[t] = (double)x1[t];
+        apply_m<HR, S>(ctx, xd, lds, bnd, cf.alpha, cf.beta,
+                       [&](int t, double m, bool act) { r[t] = act ? r[t] - m : 0.0; });
+        float x2[HR];
+        cheb32<HR, S, K2>(ctx, r, x2, ldsf, bndf, cf, cs);
+#pragma unroll
+        for (int t = 0; t < HR; ++t) phi[t] = (double)x1[t] + (double)x2[t];
     }
 
     // ---------------- update ----------------
@@ -449,7 +623,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const
         const int gy = y0 - K + row;
         if (gy >= g.hi[1]) continue;
         const size_t o = (size_t)gy * P + gx;
-        const double de = cf.cfl * (xs[t] + d[t]);
+        const double de = cf.cfl * phi[t];
         a.field[o] += de;
         if (MODE == COL_E_TRACKED) a.ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cv[t]);
     }
@@ -494,6 +668,16 @@ inline auto with_k_shape(int K, int shape, F&& f)
         case 7: return f.template operator()<7, Shape0>();
         default: return f.template operator()<8, Shape0>();
     }
+}
+
+// Mixed precision: the tile halo K = 2 s + 1 for s FP32 sweeps per round;
+// instantiated for s = 1, 2, 3 with the default shape.
+template <class F>
+inline auto with_k_mixed(int K, F&& f)
+{
+    if (K <= 3) return f.template operator()<3, Shape0>();
+    if (K <= 5) return f.template operator()<5, Shape0>();
+    return f.template operator()<7, Shape0>();
 }
 
 // unknowns of the 2D components

@@ -42,6 +42,15 @@ def test_config_validation_without_device():
     assert lib.c4m_workspace_bytes(ctypes.byref(forced), ctypes.byref(out)) == L.OK
     cfg3 = make_config(dim=3, n=32, cfl=0.5)
     assert lib.c4m_workspace_bytes(ctypes.byref(cfg3), ctypes.byref(out)) == L.EUNSTABLE
+    # the PCG form takes more temporaries; it runs in FP64 only
+    pcg = make_config(dim=2, n=64, solver="pcg")
+    pb = ctypes.c_size_t()
+    assert lib.c4m_workspace_bytes(ctypes.byref(pcg), ctypes.byref(pb)) == L.OK
+    assert pb.value > out.value
+    pcg32 = make_config(dim=2, n=64, solver="pcg", precision="fp32_refined")
+    assert lib.c4m_workspace_bytes(ctypes.byref(pcg32), ctypes.byref(pb)) == L.EINVAL
+    bad_iter = make_config(dim=2, n=64, solver="pcg", max_iter=-1)
+    assert lib.c4m_workspace_bytes(ctypes.byref(bad_iter), ctypes.byref(pb)) == L.EINVAL
     # create rejects a misaligned or small workspace before any device call
     h = ctypes.c_void_p()
     assert lib.c4m_create(ctypes.byref(cfg), ctypes.c_void_p(16), 1 << 30, None, ctypes.byref(h)) == L.EINVAL
