@@ -243,7 +243,12 @@ def main():
     got = {x: prob.get(x) for x in names}
     ex = exact_fields(n, k, steps * ht, (steps + 0.5) * ht)
     l2_exact = rel_l2(got, ex, names)
-    sweeps = prob.info()["sweeps"]
+    pinf = prob.info()
+    sweeps = pinf["sweeps"]
+    pcg_stats = None
+    if args.solver == "pcg":
+        pcg_stats = {"last_iters": pinf["last_iters"], "max_iters": pinf["max_iters"],
+                     "last_rel_residual": pinf["last_rel_residual"], "noconv": pinf["noconv"]}
     prob.close()
 
     # ---- profiled pass: per-kernel durations from HIP events on the stream
@@ -324,6 +329,7 @@ def main():
                    "solver": f"chebyshev x{sweeps}" if args.solver == "chebyshev" else "pcg"},
         "l2_vs_exact": l2_exact,
         "parity_sample": parity,
+        **({"pcg": pcg_stats} if pcg_stats else {}),
         "roofline": roofline,
         "cpu_baseline": cpu,
     }

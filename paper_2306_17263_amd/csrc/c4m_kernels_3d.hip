@@ -3,7 +3,7 @@
 // Step 1 (Section 3.4), per E component s (s1 = s+1, s2 = s+2 mod 3):
 //   b   = Z (delta_{s1} G(H_{s2}) - delta_{s2} G(H_{s1}))      k_term3 twice
 //   c   = delta_{s1} H_{s2} - delta_{s2} H_{s1}                 (carried l) k_term3 twice
-//   Phi = M^{-1} b (19-point M), E_s += r Phi, G_E += ...       k_cheb3_*
+//   Phi = M^{-1} b (19-point M), E_s += r Phi, G_E += ...       k_cheb3t
 // Step 2, per H component s:
 //   b   = -(1/Z) (delta_{s1} G_{E,s2} - delta_{s2} G_{E,s1}),   H_s += r M^{-1} b.
 //
@@ -14,8 +14,10 @@
 // in LDS (coalesced loads), then every thread runs the truncated Pade FIR
 // over a register window of 8 consecutive outputs.
 //
-// Chebyshev: one launch per sweep (x += d, r -= M d, d <- c1 d + c2 r) over
-// the unknowns, with the 19-point stencil read through the caches.
+// Chebyshev (FP64): three-term form, one z-marching launch per application
+// of M with the planes of the iterate staged in LDS (k_cheb3t).  The
+// FP32-refined form runs its two FP32 rounds as per-sweep kernels on FP32
+// views of the temporaries (k_cheb3f_*).
 #include "c4m_internal.h"
 
 namespace c4m {
@@ -158,70 +160,105 @@ __device__ __forceinline__ bool cell3(const UGrid& g, int& i, int& j, int& k)
     return true;
 }
 
-__global__ void k_cheb3_init(Cheb3 c, double inv_theta)
-{
-    int i, j, k;
-    if (!cell3(c.g, i, j, k)) return;
-    const size_t o = k * c.plane + (size_t)j * c.P + i;
-    c.d0[o] = c.r[o] * inv_theta;
-    c.x[o] = 0.0;
-}
+// ---------------------------------------------------------------------------
+// FP64 solve: Chebyshev in three-term form on the same schedule,
+//   x_1 = b / theta,  x_{k+1} = x_k + c1_{k-1} (x_k - x_{k-1}) + c2_{k-1} (b - M x_k),
+// k = 1..K, Phi = x_{K+1} (K applications of M).  Each application is one
+// z-marching pass over the grid: a workgroup owns a 64 x 4 column tile and
+// a chunk of planes, and keeps the three planes z-1, z, z+1 of x_k (with a
+// one-point ring, boundary rules applied when loading) in a 4-deep LDS ring.
+// The first pass reads only b; the last writes the field update.
+// ---------------------------------------------------------------------------
+constexpr int C3_TX = 64, C3_TY = 4, C3_CZ = 16;
+constexpr int C3_LX = C3_TX + 2, C3_LY = C3_TY + 2, C3_PL = C3_LX * C3_LY;
 
-// d value at a neighbour of an unknown: Dirichlet beyond the range -> 0,
-// Neumann -> mirrored back into the range.
-__device__ __forceinline__ double dval(const Cheb3& c, const double* d, int i, int j, int k)
+struct Cheb3T {
+    const double* b;
+    const double* xk;       // x_k (unused in the first pass: x_1 = b / theta)
+    const double* xkm1;     // x_{k-1} (unused in the first pass: x_0 = 0)
+    double* xout;           // x_{k+1} (unused in the last pass)
+    double* field;          // last pass: field += cfl Phi
+    double* ge;             // last pass, carried Laplacian: G_E update (or null)
+    const double* cur;      // raw curl for the G_E update
+    UGrid g;
+    int P;
+    size_t plane;
+    double inv_theta, c1, c2;
+    Coef cf;
+};
+
+// Index of grid point (i, j, k) after the boundary rules of the unknowns:
+// Dirichlet outside the range -> -1 (zero), Neumann -> mirrored onto the
+// edge unknown.
+__device__ __forceinline__ long rule_index(const Cheb3T& a, int i, int j, int k)
 {
     int q[3] = {i, j, k};
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (q[a] < c.g.lo[a]) {
-            if (!c.g.neumann[a]) return 0.0;
-            q[a] = c.g.lo[a];
-        } else if (q[a] >= c.g.hi[a]) {
-            if (!c.g.neumann[a]) return 0.0;
-            q[a] = c.g.hi[a] - 1;
+    for (int d = 0; d < 3; ++d) {
+        if (q[d] < a.g.lo[d]) {
+            if (!a.g.neumann[d]) return -1;
+            q[d] = a.g.lo[d];
+        } else if (q[d] >= a.g.hi[d]) {
+            if (!a.g.neumann[d]) return -1;
+            q[d] = a.g.hi[d] - 1;
         }
     }
-    return d[q[2] * c.plane + (size_t)q[1] * c.P + q[0]];
+    return (long)q[2] * (long)a.plane + (long)q[1] * a.P + q[0];
 }
 
-// L9 (3D) = (1/6)(2 sum faces + sum edges - 24 centre); A d = alpha d - beta L9 d
-__global__ void k_cheb3_sweep(Cheb3 c, const double* __restrict__ din, double* __restrict__ dout,
-                              double alpha, double beta, double c1, double c2)
+template <bool FIRST, bool LAST>
+__global__ __launch_bounds__(256) void k_cheb3t(Cheb3T a)
 {
-    int i, j, k;
-    if (!cell3(c.g, i, j, k)) return;
-    const size_t o = k * c.plane + (size_t)j * c.P + i;
-    const double dc = din[o];
-    double faces = 0.0, edges = 0.0;
-    faces += dval(c, din, i - 1, j, k) + dval(c, din, i + 1, j, k);
-    faces += dval(c, din, i, j - 1, k) + dval(c, din, i, j + 1, k);
-    faces += dval(c, din, i, j, k - 1) + dval(c, din, i, j, k + 1);
-    for (int a = -1; a <= 1; a += 2)
-        for (int b = -1; b <= 1; b += 2) {
-            edges += dval(c, din, i + a, j + b, k);
-            edges += dval(c, din, i, j + a, k + b);
-            edges += dval(c, din, i + a, j, k + b);
+    __shared__ double ring[4][C3_PL];
+    const int tid = threadIdx.x;
+    const int tx = tid % C3_TX, ty = tid / C3_TX;
+    const int bx = a.g.lo[0] + blockIdx.x * C3_TX, by = a.g.lo[1] + blockIdx.y * C3_TY;
+    const int i = bx + tx, j = by + ty;
+    const int z0 = a.g.lo[2] + blockIdx.z * C3_CZ;
+    const int z1 = min(z0 + C3_CZ, a.g.hi[2]);
+    const bool own = i < a.g.hi[0] && j < a.g.hi[1];
+    const double* src = FIRST ? a.b : a.xk;
+    const double scale = FIRST ? a.inv_theta : 1.0;
+    auto load = [&](int z) {
+        double* buf = ring[z & 3];
+        for (int e = tid; e < C3_PL; e += 256) {
+            const int ly = e / C3_LX, lx = e - ly * C3_LX;
+            const long q = rule_index(a, bx + lx - 1, by + ly - 1, z);
+            buf[e] = q < 0 ? 0.0 : scale * src[q];
         }
-    const double l9 = (2.0 * faces + edges - 24.0 * dc) * (1.0 / 6.0);
-    const double ad = fma(alpha, dc, -beta * l9);
-    c.x[o] += dc;
-    const double rn = c.r[o] - ad;
-    c.r[o] = rn;
-    dout[o] = fma(c1, dc, c2 * rn);
-}
-
-// field += cfl (x + d); with the carried Laplacian of E also
-// G_E += (1 + 4/r^2) dE - (2/r) Z c.
-__global__ void k_cheb3_final(Cheb3 c, const double* __restrict__ dlast, double* field, double* ge,
-                              const double* cur, Coef cf)
-{
-    int i, j, k;
-    if (!cell3(c.g, i, j, k)) return;
-    const size_t o = k * c.plane + (size_t)j * c.P + i;
-    const double de = cf.cfl * (c.x[o] + dlast[o]);
-    field[o] += de;
-    if (ge) ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cur[o]);
+    };
+    load(z0 - 1);
+    load(z0);
+    const double b6 = a.cf.beta * (1.0 / 6.0);
+    const int c0 = (ty + 1) * C3_LX + tx + 1;
+    for (int z = z0; z < z1; ++z) {
+        load(z + 1);
+        __syncthreads();
+        if (own) {
+            const double* pm = ring[(z - 1) & 3];
+            const double* pc = ring[z & 3];
+            const double* pp = ring[(z + 1) & 3];
+            const double xc = pc[c0];
+            // faces: x, y in the plane and z across planes; edges: the four
+            // in-plane diagonals and the x/y neighbours of the planes z +- 1
+            const double faces = pc[c0 - 1] + pc[c0 + 1] + pc[c0 - C3_LX] + pc[c0 + C3_LX] + pm[c0] + pp[c0];
+            const double edges = pc[c0 - C3_LX - 1] + pc[c0 - C3_LX + 1] + pc[c0 + C3_LX - 1] +
+                                 pc[c0 + C3_LX + 1] + pm[c0 - 1] + pm[c0 + 1] + pm[c0 - C3_LX] +
+                                 pm[c0 + C3_LX] + pp[c0 - 1] + pp[c0 + 1] + pp[c0 - C3_LX] + pp[c0 + C3_LX];
+            const double mx = fma(a.cf.alpha, xc, -b6 * (2.0 * faces + edges - 24.0 * xc));
+            const size_t o = (size_t)z * a.plane + (size_t)j * a.P + i;
+            const double bv = a.b[o];
+            const double xp = FIRST ? 0.0 : a.xkm1[o];
+            const double xn = xc + fma(a.c1, xc - xp, a.c2 * (bv - mx));
+            if (LAST) {
+                const double de = a.cf.cfl * xn;
+                a.field[o] += de;
+                if (a.ge) a.ge[o] += fma(a.cf.ge_gain, de, -a.cf.ge_curl * a.cur[o]);
+            } else {
+                a.xout[o] = xn;
+            }
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -421,19 +458,34 @@ hipError_t launch_term3(hipStream_t st, int axis, int mode, const Term3& t, doub
 hipError_t launch_solve3(hipStream_t st, const Cheb3& c, double* field, double* ge, const double* cur,
                          const Coef& cf, const ChebSchedule& cs)
 {
-    const long cells = (long)(c.g.hi[0] - c.g.lo[0]) * (c.g.hi[1] - c.g.lo[1]) * (c.g.hi[2] - c.g.lo[2]);
-    const dim3 grid((unsigned)((cells + 255) / 256));
-    hipLaunchKernelGGL(k_cheb3_init, grid, dim3(256), 0, st, c, cs.inv_theta);
-    double* din = c.d0;
-    double* dout = c.d1;
-    for (int k = 0; k < cs.sweeps; ++k) {
-        hipLaunchKernelGGL(k_cheb3_sweep, grid, dim3(256), 0, st, c, din, dout, cf.alpha, cf.beta, cs.c1[k],
-                           cs.c2[k]);
-        double* tmp = din;
-        din = dout;
-        dout = tmp;
+    const dim3 grid((unsigned)((c.g.hi[0] - c.g.lo[0] + C3_TX - 1) / C3_TX),
+                    (unsigned)((c.g.hi[1] - c.g.lo[1] + C3_TY - 1) / C3_TY),
+                    (unsigned)((c.g.hi[2] - c.g.lo[2] + C3_CZ - 1) / C3_CZ));
+    // x_k rotates through three arrays: x, d0, d1 (b stays in r)
+    double* bufs[3] = {c.x, c.d0, c.d1};
+    const int K = cs.sweeps;
+    for (int k = 1; k <= K; ++k) {
+        Cheb3T a{};
+        a.b = c.r;
+        a.xk = bufs[k % 3];
+        a.xkm1 = bufs[(k - 1) % 3];
+        a.xout = bufs[(k + 1) % 3];
+        a.field = field;
+        a.ge = ge;
+        a.cur = cur;
+        a.g = c.g;
+        a.P = c.P;
+        a.plane = c.plane;
+        a.inv_theta = cs.inv_theta;
+        a.c1 = cs.c1[k - 1];
+        a.c2 = cs.c2[k - 1];
+        a.cf = cf;
+        const bool first = k == 1, last = k == K;
+        if (first && last) hipLaunchKernelGGL((k_cheb3t<true, true>), grid, dim3(256), 0, st, a);
+        else if (first) hipLaunchKernelGGL((k_cheb3t<true, false>), grid, dim3(256), 0, st, a);
+        else if (last) hipLaunchKernelGGL((k_cheb3t<false, true>), grid, dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((k_cheb3t<false, false>), grid, dim3(256), 0, st, a);
     }
-    hipLaunchKernelGGL(k_cheb3_final, grid, dim3(256), 0, st, c, din, field, ge, cur, cf);
     return hipGetLastError();
 }
 
