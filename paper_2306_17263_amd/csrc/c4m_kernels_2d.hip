@@ -7,14 +7,20 @@ namespace c4m {
 template <int MODE>
 __global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps)
 {
-    xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, blockIdx.x, blockIdx.y);
+    const int ntx = xlines_tiles_x(xa.L.n_out), nty = xlines_tiles_y(xa.N);
+    int l;
+    if (!xcd_tile(ntx * nty, l)) return;
+    xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, l % ntx, l / ntx);
 }
 
 template <int K, int MODE, class S, int FORM>
 __global__ __launch_bounds__(S::NTC) __attribute__((amdgpu_waves_per_eu(S::NL == 4 ? 4 : 2))) void k_col(
     ColArgs a, Coef cf, PadeTaps taps, PadeLine L, ChebSchedule cs)
 {
-    col_tile<K, MODE, S, FORM>(a, cf, taps, L, cs, blockIdx.x, blockIdx.y);
+    const int ntx = col_tiles_x<K, S>(a.g), nty = col_tiles_y<K, S>(a.g);
+    int l;
+    if (!xcd_tile(ntx * nty, l)) return;
+    col_tile<K, MODE, S, FORM>(a, cf, taps, L, cs, l / nty, l % nty);   // y fastest
 }
 
 // ---------------------------------------------------------------------------
@@ -26,12 +32,12 @@ static hipError_t launch_col(int shape, bool mixed, hipStream_t st, const ColArg
 {
     if (mixed)
         return with_k_mixed(cs.sweeps, [&]<int K, class S>() {
-            const dim3 grid(col_tiles_x<K, S>(a.g), col_tiles_y<K, S>(a.g));
+            const dim3 grid(xcd_grid(col_tiles_x<K, S>(a.g) * col_tiles_y<K, S>(a.g)));
             hipLaunchKernelGGL((k_col<K, MODE, S, FORM_MIXED>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);
             return hipGetLastError();
         });
     return with_k_shape(cs.sweeps, shape, [&]<int K, class S>() {
-        const dim3 grid(col_tiles_x<K, S>(a.g), col_tiles_y<K, S>(a.g));
+        const dim3 grid(xcd_grid(col_tiles_x<K, S>(a.g) * col_tiles_y<K, S>(a.g)));
         hipLaunchKernelGGL((k_col<K, MODE, S, FORM_FP64>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);
         return hipGetLastError();
     });
@@ -43,7 +49,7 @@ template <int MODE>
 static hipError_t launch_col_rhs(hipStream_t st, const ColArgs& a, const Coef& cf, const PadeTaps& taps,
                                  const PadeLine& L, const ChebSchedule& cs)
 {
-    const dim3 grid(col_tiles_x<0, Shape0>(a.g), col_tiles_y<0, Shape0>(a.g));
+    const dim3 grid(xcd_grid(col_tiles_x<0, Shape0>(a.g) * col_tiles_y<0, Shape0>(a.g)));
     hipLaunchKernelGGL((k_col<0, MODE, Shape0, FORM_RHS>), grid, dim3(Shape0::NTC), 0, st, a, cf, taps, L, cs);
     return hipGetLastError();
 }
@@ -53,7 +59,7 @@ hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const
                            const PadeLine& line_h2n)
 {
     // x-lines of Hy: N inputs, N-1 outputs, rows 1..N-1
-    dim3 grid(xlines_tiles_x(line_h2n.n_out), xlines_tiles_y(N));
+    const dim3 grid(xcd_grid(xlines_tiles_x(line_h2n.n_out) * xlines_tiles_y(N)));
     (void)hx;
     const XArgs xa{hy, t0, t1, N, P, line_h2n};
     if (tracked)
@@ -77,7 +83,7 @@ hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, doub
                            const PadeLine& line_n2h)
 {
     // x-lines of G_E: N+1 inputs, N outputs (Hy half points), rows 1..N-1
-    dim3 grid(xlines_tiles_x(line_n2h.n_out), xlines_tiles_y(N));
+    const dim3 grid(xcd_grid(xlines_tiles_x(line_n2h.n_out) * xlines_tiles_y(N)));
     const XArgs xa{src, t0, t1, N, P, line_n2h};
     if (tracked)
         hipLaunchKernelGGL(k_xlines<XL_H_TRACKED>, grid, dim3(256), 0, st, xa, cf, taps);

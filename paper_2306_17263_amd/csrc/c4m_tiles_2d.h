@@ -382,8 +382,16 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const
     constexpr bool SPLIT = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE || MODE == COL_HX_DISCRETE;
     constexpr bool ESTEP = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE;
     constexpr int NPOS = HR + PADE_TAPS - 1 + 2;    // streamed line positions (+1 each side for G)
-    __shared__ double lds[TR * CWP];
-    __shared__ double bnd[2 * NL * 2 * CW];         // [parity][part][0: first row, 1: last row][column]
+    // LDS: the column sums [TR][CWP], the rows next to the part splits
+    // [parity][part][first/last][column], and with the carried Laplacian the
+    // curl of H on the output rows [TR][CW] (kept out of registers during
+    // the solve).
+    constexpr bool PARK_CV = MODE == COL_E_TRACKED && FORM != FORM_RHS;
+    constexpr int LDS_DOUBLES = TR * CWP + (FORM == FORM_RHS ? 0 : 2 * NL * 2 * CW) + (PARK_CV ? TR * CW : 0);
+    __shared__ double lds_all[LDS_DOUBLES];
+    double* lds = lds_all;
+    double* bnd = lds_all + TR * CWP;
+    double* cvb = bnd + (FORM == FORM_RHS ? 0 : 2 * NL * 2 * CW);
 
     const int tid = threadIdx.x;
     const int lane = tid % CW;                      // region column
@@ -486,6 +494,7 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const
             double v = 0.0;
             if (row >= K && row < K + OH && col_active && gy < g.hi[1]) v = a.t1[(size_t)gy * P + gx] - cv[t];
             cv[t] = v;
+            if (PARK_CV) cvb[row * CW + lane] = v;
         }
     }
 
@@ -625,8 +634,23 @@ __device__ __forceinline__ void col_tile(const ColArgs& a, const Coef& cf, const
         const size_t o = (size_t)gy * P + gx;
         const double de = cf.cfl * phi[t];
         a.field[o] += de;
-        if (MODE == COL_E_TRACKED) a.ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cv[t]);
+        if (MODE == COL_E_TRACKED) a.ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cvb[row * CW + lane]);
     }
+}
+
+// XCD-aware tile order.  Workgroup IDs of a launch are dealt to the XCDs in
+// turn (ID mod 8), and each XCD has its own L2.  XCD x takes the x-th
+// contiguous range of the tile sequence, so tiles that share halo data run
+// at about the same time on the same L2.  The grid has 8 ceil(T/8) groups;
+// the few past the last tile return at once.
+constexpr int NXCD = 8;
+__host__ __device__ inline int xcd_grid(int tiles) { return NXCD * ((tiles + NXCD - 1) / NXCD); }
+__device__ __forceinline__ bool xcd_tile(int tiles, int& l)
+{
+    const int per = (tiles + NXCD - 1) / NXCD;
+    const int id = (int)blockIdx.x;
+    l = (id % NXCD) * per + id / NXCD;
+    return l < tiles;
 }
 
 // Tile counts of the two 2D kernels.
