@@ -227,7 +227,7 @@ struct c4m_problem {
     size_t ws_bytes = 0, used = 0;
     double* f[6] = {};                  // Ex Ey Ez Hx Hy Hz
     double* ge[3] = {};                 // G_E per E component (carried Laplacian)
-    double* tmp[8] = {};
+    double* tmp[9] = {};
     double* pcg_part = nullptr;         // PCG per-workgroup partial sums
     PcgState* pcg_state = nullptr;      // PCG scalars and statistics
     double* pade_dev[2] = {};           // [0] node->half (n_in N+1), [1] half->node (n_in N)
@@ -328,9 +328,9 @@ Layout layout(const c4m_config* c)
     L.n_fields = c->dim == 2 ? 3 : 6;
     L.n_ge = c->lap_mode == C4M_LAP_TRACKED ? (c->dim == 2 ? 1 : 3) : 0;
     const bool pcg = c->solver == C4M_SOLVER_PCG;
-    // 2D: T0, T1 (+ x, r, two directions, M p, 1/diag for PCG);
-    // 3D: b, x, d0, d1, curl (+ M p, 1/diag for PCG)
-    L.n_tmp = c->dim == 2 ? (pcg ? 8 : 2) : (pcg ? 7 : 5);
+    // 2D: T0, T1 (+ x, r, two directions, M p, 1/diag, z for PCG);
+    // 3D: b, x, d0, d1, curl (+ M p, 1/diag, z for PCG)
+    L.n_tmp = c->dim == 2 ? (pcg ? 9 : 2) : (pcg ? 8 : 5);
     L.pcg_bytes = pcg ? align256(3 * ((L.arr + 255) / 256) * sizeof(double)) + 256 : 0;
     for (int k = 0; k < 2; ++k) {
         const int n_out = (k == 0 ? N + 1 : N) - 1;
@@ -468,6 +468,7 @@ c4m_status step3(c4m_problem* p)
         a.p[1] = d1;
         a.q = p->tmp[5];
         a.dinv = p->tmp[6];
+        a.z = p->tmp[7];
         a.part = p->pcg_part;
         a.st = p->pcg_state;
         a.g = unknowns(p->box[comp]);

@@ -110,6 +110,7 @@ struct PcgArgs {
     double* p[2];         // search directions (alternate per iteration)
     double* q;            // M p
     double* dinv;         // 1 / diag(M)
+    double* z;            // preconditioned residual r / diag(M)
     double* part;         // [3][nparts] per-workgroup partial sums
     PcgState* st;
     UGrid g;

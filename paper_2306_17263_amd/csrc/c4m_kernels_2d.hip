@@ -108,7 +108,7 @@ hipError_t launch_solve_h_2d(hipStream_t st, int shape, bool mixed, bool tracked
 }
 
 // PCG forms of the two solves.  Temporaries: pt[0] x, pt[1] r (= b),
-// pt[2], pt[3] search directions, pt[4] M p, pt[5] 1/diag(M).
+// pt[2], pt[3] search directions, pt[4] M p, pt[5] 1/diag(M), pt[6] z.
 static PcgArgs pcg_args(double* const* pt, const UGrid& g, int P, const Coef& cf, double* part, PcgState* pst,
                         double rtol)
 {
@@ -119,6 +119,7 @@ static PcgArgs pcg_args(double* const* pt, const UGrid& g, int P, const Coef& cf
     a.p[1] = pt[3];
     a.q = pt[4];
     a.dinv = pt[5];
+    a.z = pt[6];
     a.part = part;
     a.st = pst;
     a.g = g;
@@ -155,7 +156,7 @@ hipError_t launch_pcg_h_2d(hipStream_t st, bool tracked, const double* src, doub
     e = launch_pcg(st, 2, pcg_args(pt, ugrid_hx(N), P, cf, part, pst, rtol), max_iter, hx, nullptr, nullptr, cf);
     if (e != hipSuccess) return e;
     // Hy: the x-line right-hand side T1 is b
-    double* pty[6] = {pt[0], t1, pt[2], pt[3], pt[4], pt[5]};
+    double* pty[7] = {pt[0], t1, pt[2], pt[3], pt[4], pt[5], pt[6]};
     return launch_pcg(st, 2, pcg_args(pty, ugrid_hy(N), P, cf, part, pst, rtol), max_iter, hy, nullptr, nullptr,
                       cf);
 }

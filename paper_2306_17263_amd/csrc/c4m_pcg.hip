@@ -14,17 +14,21 @@ namespace c4m {
 namespace {
 
 constexpr int PCG_THREADS = 256;
+constexpr int PCG_MAX_BLOCKS = 2048;   // grid cap: threads stride over the cells
 
-// Unknown (i, j, k) of thread e in the box g (x fastest).
-__device__ __forceinline__ bool pcg_cell(const UGrid& g, long e, int& i, int& j, int& k)
+// Unknown (i, j, k) number e of the box g (x fastest).
+__device__ __forceinline__ void pcg_cell(const UGrid& g, long e, int& i, int& j, int& k)
 {
-    const int nx = g.hi[0] - g.lo[0], ny = g.hi[1] - g.lo[1], nz = g.hi[2] - g.lo[2];
-    if (e >= (long)nx * ny * nz) return false;
+    const int nx = g.hi[0] - g.lo[0], ny = g.hi[1] - g.lo[1];
     i = g.lo[0] + (int)(e % nx);
     const long rest = e / nx;
     j = g.lo[1] + (int)(rest % ny);
     k = g.lo[2] + (int)(rest / ny);
-    return true;
+}
+
+__device__ __forceinline__ long pcg_cells(const UGrid& g)
+{
+    return (long)(g.hi[0] - g.lo[0]) * (g.hi[1] - g.lo[1]) * (g.hi[2] - g.lo[2]);
 }
 
 // Index of a stencil neighbour: Dirichlet outside the unknowns -> -1 (value
@@ -75,16 +79,27 @@ __device__ __forceinline__ void for_neighbours(const PcgArgs& a, int i, int j, i
     }
 }
 
-// Diagonal of M at an unknown: alpha - beta (centre + mirrored weights) / 6;
-// a Neumann mirror that maps a neighbour onto the cell itself adds its
-// weight to the diagonal.
+// Diagonal of M at an unknown.  A neighbour lands on the cell itself when
+// every axis it steps along is a Neumann axis at that edge (even ghost); its
+// weight then adds to the centre: alpha - beta (centre + those weights) / 6.
 template <int DIM>
-__device__ __forceinline__ double m_diag(const PcgArgs& a, int i, int j, int k, long self)
+__device__ __forceinline__ double m_diag(const PcgArgs& a, int i, int j, int k)
 {
-    double w = DIM == 2 ? -20.0 : -24.0;
-    for_neighbours<DIM>(a, i, j, k, [&](long q, double wt) {
-        if (q == self) w += wt;
-    });
+    const int q[3] = {i, j, k};
+    double lo[3], hi[3];                  // 1 if the step -1 / +1 along d lands on the cell
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        lo[d] = a.g.neumann[d] && q[d] == a.g.lo[d] ? 1.0 : 0.0;
+        hi[d] = a.g.neumann[d] && q[d] == a.g.hi[d] - 1 ? 1.0 : 0.0;
+    }
+    double w;
+    if (DIM == 2) {
+        const double sx = lo[0] + hi[0], sy = lo[1] + hi[1];
+        w = -20.0 + 4.0 * (sx + sy) + sx * sy;
+    } else {
+        const double s0 = lo[0] + hi[0], s1 = lo[1] + hi[1], s2 = lo[2] + hi[2];
+        w = -24.0 + 2.0 * (s0 + s1 + s2) + s0 * s1 + s1 * s2 + s0 * s2;
+    }
     return fma(-a.beta, w * (1.0 / 6.0), a.alpha);
 }
 
@@ -133,24 +148,36 @@ __device__ __forceinline__ double total(const PcgArgs& a, int q, double* lds)
     return block_sum(s, lds);
 }
 
-// x = 0, r = b (in place), p_old = 0; rz = <r, z>, bb = <b, b> with z = r / diag.
+// Calls f(o, i, j, k) for this thread's unknowns: a grid-stride sweep in a
+// fixed order, so every partial sum is formed the same way on every run.
+template <class F>
+__device__ __forceinline__ void for_cells(const PcgArgs& a, F&& f)
+{
+    const long n = pcg_cells(a.g);
+    for (long e = (long)blockIdx.x * PCG_THREADS + threadIdx.x; e < n; e += (long)gridDim.x * PCG_THREADS) {
+        int i, j, k;
+        pcg_cell(a.g, e, i, j, k);
+        f((long)k * (long)a.plane + (long)j * a.P + i, i, j, k);
+    }
+}
+
+// x = 0, r = b (in place), p_old = 0, z = r / diag; rz = <r, z>, bb = <b, b>.
 template <int DIM>
 __global__ __launch_bounds__(PCG_THREADS) void k_pcg_init(PcgArgs a)
 {
     __shared__ double lds[PCG_THREADS / 64];
     __shared__ int flag;
-    int i, j, k;
     double v[2] = {0.0, 0.0};
-    if (pcg_cell(a.g, (long)blockIdx.x * PCG_THREADS + threadIdx.x, i, j, k)) {
-        const long o = (long)k * (long)a.plane + (long)j * a.P + i;
+    for_cells(a, [&](long o, int i, int j, int k) {
         const double rr = a.r[o];
-        const double di = 1.0 / m_diag<DIM>(a, i, j, k, o);
+        const double di = 1.0 / m_diag<DIM>(a, i, j, k);
         a.dinv[o] = di;
+        a.z[o] = rr * di;
         a.x[o] = 0.0;
         a.p[0][o] = 0.0;
-        v[0] = rr * rr * di;
-        v[1] = rr * rr;
-    }
+        v[0] += rr * rr * di;
+        v[1] += rr * rr;
+    });
     double s[2];
     s[0] = block_sum(v[0], lds);
     s[1] = block_sum(v[1], lds);
@@ -180,12 +207,9 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_mp(PcgArgs a, int it)
     const double* __restrict__ pold = a.p[it & 1];
     double* __restrict__ pnew = a.p[(it & 1) ^ 1];
     const double beta = a.st->beta;
-    int i, j, k;
     double v[1] = {0.0};
-    if (pcg_cell(a.g, (long)blockIdx.x * PCG_THREADS + threadIdx.x, i, j, k)) {
-        const long o = (long)k * (long)a.plane + (long)j * a.P + i;
-        // z = r / diag(M), recomputed at the cell and its neighbours
-        auto pval = [&](long q) { return fma(beta, pold[q], a.r[q] * a.dinv[q]); };
+    for_cells(a, [&](long o, int i, int j, int k) {
+        auto pval = [&](long q) { return fma(beta, pold[q], a.z[q]); };
         const double pc = pval(o);
         double side = 0.0;
         for_neighbours<DIM>(a, i, j, k, [&](long q, double wt) {
@@ -195,8 +219,8 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_mp(PcgArgs a, int it)
         const double qv = fma(a.alpha, pc, -a.beta * l9);
         pnew[o] = pc;
         a.q[o] = qv;
-        v[0] = pc * qv;
-    }
+        v[0] += pc * qv;
+    });
     double s[1];
     s[0] = block_sum(v[0], lds);
     if (!publish_partials<1>(a, s, &flag)) return;
@@ -207,8 +231,8 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_mp(PcgArgs a, int it)
     }
 }
 
-// x += alpha p, r -= alpha q; partials <r, z>, <r, r>.  The last workgroup
-// sets beta, the convergence flag and the iteration count.
+// x += alpha p, r -= alpha q, z = r / diag; partials <r, z>, <r, r>.  The
+// last workgroup sets beta, the convergence flag and the iteration count.
 template <int DIM>
 __global__ __launch_bounds__(PCG_THREADS) void k_pcg_update(PcgArgs a, int it)
 {
@@ -217,16 +241,16 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_update(PcgArgs a, int it)
     __shared__ int flag;
     const double* __restrict__ pc = a.p[(it & 1) ^ 1];
     const double alpha = a.st->alpha;
-    int i, j, k;
     double v[2] = {0.0, 0.0};
-    if (pcg_cell(a.g, (long)blockIdx.x * PCG_THREADS + threadIdx.x, i, j, k)) {
-        const long o = (long)k * (long)a.plane + (long)j * a.P + i;
+    for_cells(a, [&](long o, int, int, int) {
         a.x[o] = fma(alpha, pc[o], a.x[o]);
         const double rn = fma(-alpha, a.q[o], a.r[o]);
+        const double zn = rn * a.dinv[o];
         a.r[o] = rn;
-        v[0] = rn * rn * a.dinv[o];
-        v[1] = rn * rn;
-    }
+        a.z[o] = zn;
+        v[0] += rn * zn;
+        v[1] += rn * rn;
+    });
     double s[2];
     s[0] = block_sum(v[0], lds);
     s[1] = block_sum(v[1], lds);
@@ -249,7 +273,6 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_update(PcgArgs a, int it)
 __global__ __launch_bounds__(PCG_THREADS) void k_pcg_final(PcgArgs a, double* field, double* ge, const double* cur,
                                                             Coef cf)
 {
-    int i, j, k;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         PcgState* st = a.st;
         st->last_iters = st->iters;
@@ -257,11 +280,11 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_final(PcgArgs a, double* fi
         st->last_rel = st->bb > 0.0 ? sqrt(st->rr / st->bb) : 0.0;
         if (!st->done) st->noconv = 1;
     }
-    if (!pcg_cell(a.g, (long)blockIdx.x * PCG_THREADS + threadIdx.x, i, j, k)) return;
-    const long o = (long)k * (long)a.plane + (long)j * a.P + i;
-    const double de = cf.cfl * a.x[o];
-    field[o] += de;
-    if (ge) ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cur[o]);
+    for_cells(a, [&](long o, int, int, int) {
+        const double de = cf.cfl * a.x[o];
+        field[o] += de;
+        if (ge) ge[o] += fma(cf.ge_gain, de, -cf.ge_curl * cur[o]);
+    });
 }
 
 }  // namespace
@@ -269,7 +292,8 @@ __global__ __launch_bounds__(PCG_THREADS) void k_pcg_final(PcgArgs a, double* fi
 size_t pcg_partials(const UGrid& g)
 {
     const long cells = (long)(g.hi[0] - g.lo[0]) * (g.hi[1] - g.lo[1]) * (g.hi[2] - g.lo[2]);
-    return (size_t)((cells + PCG_THREADS - 1) / PCG_THREADS);
+    const long blocks = (cells + PCG_THREADS - 1) / PCG_THREADS;
+    return (size_t)(blocks < PCG_MAX_BLOCKS ? blocks : PCG_MAX_BLOCKS);
 }
 
 // One solve M x = b (b in a.r, overwritten) of at most max_iter iterations,
