@@ -170,7 +170,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="2d", choices=["2d", "batch", "3d", "serve"],
+    ap.add_argument("--workload", default="2d", choices=["2d", "batch", "3d", "serve", "sweep"],
                     help="2d: the N=2048 refinement-sweep cavity (default); batch: 512 seeded 2D "
                          "cavities of uneven N; 3d: the cube cavity")
     ap.add_argument("--count", type=int, default=512)
@@ -197,6 +197,8 @@ def main():
         return bench_3d(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "sweep":
+        return bench_sweep(args)
 
     import torch
     if not torch.cuda.is_available():
@@ -384,15 +386,28 @@ def bench_batch(args):
         ht = s["r"] * h
         ex = mode_fields(2, s["n"], s["k"], steps * ht, (steps + 0.5) * ht, amp=s["amp"], with_laplacian=False)
         errs.append(rel_l2({a: p.get(a) for a in names}, ex, names))
-    # the same problems one after another through the single-problem path
-    t1 = time.perf_counter()
+    # the plain FP64 stepper: the same problems one after another through the
+    # single-problem path (created and loaded before the clock starts)
+    plain = dict(settings, precision="fp64")
+    singles = []
     for s, init in zip(specs, inits):
-        q = Problem(2, s["n"], s["r"], stream=st, **settings)
+        q = Problem(2, s["n"], s["r"], stream=st, **plain)
         for name in q.fields():
             q.set(name, init[name])
+        singles.append(q)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for q in singles:
         q.step(steps)
     torch.cuda.synchronize()
     seq = time.perf_counter() - t1
+    errs_plain = []
+    for q, s in zip(singles, specs):
+        ht = s["r"] / s["n"]
+        ex = mode_fields(2, s["n"], s["k"], steps * ht, (steps + 0.5) * ht, amp=s["amp"], with_laplacian=False)
+        errs_plain.append(rel_l2({a: q.get(a) for a in names}, ex, names))
+        q.close()
+    err_ratio = max(e / f for e, f in zip(errs, errs_plain))
     cpu = parity = None
     if not args.no_cpu_baseline:
         import oracle
@@ -434,7 +449,9 @@ def bench_batch(args):
                    "problems": len(specs), "cells_per_step": cells, "tile_x": tuned["tile_x"],
                    "tile_y": tuned["tile_y"], "autotune_timings_s": tuned["timings"]},
         "l2_vs_exact": {"max": max(errs), "median": float(np.median(errs))},
-        "sequential_single_problem_s": round(seq, 4), "speedup_vs_sequential": round(seq / elapsed, 3),
+        "plain_fp64_sequential_s": round(seq, 4), "speedup_vs_plain_fp64_sequential": round(seq / elapsed, 3),
+        "l2_vs_exact_plain_fp64": {"max": max(errs_plain), "median": float(np.median(errs_plain))},
+        "max_l2_ratio_vs_plain_fp64": err_ratio,
         "parity_sample": parity,
         "step_frac": round(88.0 * value * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
         "cpu_baseline": cpu,
@@ -496,6 +513,65 @@ def bench_3d(args):
         "l2_vs_exact": l2,
         "per_class_avg_us": {c: round(v, 1) for c, v in per.items()},
         "step_frac": round(192.0 * value * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_sweep(args):
+    """Refinement sweep of the 2D TM cavity: N = 128 .. 2048, mode (4, 3),
+    CFL 0.5, T = 1 (2N steps each): L2 error against the exact mode, the
+    observed order between successive N, and the throughput of each run."""
+    import math
+    import torch
+    from paper_2306_17263_amd import Problem
+    ns = (128, 256, 512, 1024, 2048)
+    k = (4, 3)
+    cfl = 0.5
+    names = ["ez", "hx", "hy"]
+    st = torch.cuda.Stream()
+    runs = []
+    total_cells, total_s = 0.0, 0.0
+    for n in ns:
+        ht = cfl / n
+        steps = int(round(1.0 / ht))
+        init = exact_fields(n, k, 0.0, ht / 2)
+        p = Problem(2, n, cfl, stream=st, closure=args.closure, lap_mode=args.lap, precision=args.precision)
+
+        def load():
+            for name in p.fields():
+                p.set(name, init[name])
+
+        load()
+        p.step(min(args.warmup, steps))
+        load()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(st)
+        p.step(steps)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        elapsed = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3)
+        ex = exact_fields(n, k, steps * ht, (steps + 0.5) * ht)
+        err = rel_l2({x: p.get(x) for x in names}, ex, names)
+        p.close()
+        runs.append({"n": n, "steps": steps, "l2_vs_exact": err, "seconds": round(elapsed, 5),
+                     "mcell_steps_per_s": round(n * n * steps / elapsed / 1e6, 2)})
+        total_cells += n * n * steps
+        total_s += elapsed
+    for a, b in zip(runs, runs[1:]):
+        b["observed_order"] = round(math.log2(a["l2_vs_exact"] / b["l2_vs_exact"]), 3)
+    line = {
+        "metric": "Mcell-steps/s at fixed L2 error vs FP64 oracle + % HBM roofline",
+        "value": round(total_cells / total_s / 1e6, 2), "unit": "Mcell-steps/s", "n_gpus": 1,
+        "steps": sum(r["steps"] for r in runs), "warmup": args.warmup,
+        "ms_per_step": round(total_s * 1e3 / sum(r["steps"] for r in runs), 5), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic (exact PEC cavity mode sampled on the Yee grids)",
+        "config": {"workload": f"2D TM PEC cavity refinement sweep N=128..2048, mode (4, 3), CFL 0.5, T=1, "
+                               f"{args.closure} closure, {args.lap} Laplacian, {args.precision}"},
+        "runs": runs,
     }
     print(json.dumps(line), flush=True)
 
