@@ -50,7 +50,8 @@ typedef enum {
     C4M_ENOMEM = -2,       /* workspace too small                               */
     C4M_EDEVICE = -3,      /* a HIP call failed                                 */
     C4M_ESTATE = -4,       /* call not valid in the handle's state              */
-    C4M_ENOCONV = -5,      /* CG did not reach its tolerance (sticky, see info) */
+    C4M_ENOCONV = -5,      /* PCG missed its tolerance: reported as c4m_info.noconv *
+                            * (sticky); c4m_step does not wait to find out      */
     C4M_EUNSTABLE = -6,    /* CFL number above the paper's stability bound      */
     C4M_ENONFINITE = -7    /* a non-finite value was detected (sticky)          */
 } c4m_status;
@@ -166,8 +167,11 @@ c4m_status c4m_get_info(c4m_problem* p, c4m_info* info);
 /* Release the host handle (the workspace stays the caller's). */
 c4m_status c4m_destroy(c4m_problem* p);
 
-/* Batched form: `count` independent problems (2D, any mix of n) on one
- * workspace, advanced together by one persistent launch per half-step. */
+/* Batched form: `count` independent problems (2D, any mix of n; shared cfl,
+ * z, closure, lap_mode, precision; Chebyshev solve only) on one workspace.
+ * Each kernel phase of a step is one persistent launch over the (problem,
+ * tile) items of every problem; a step is captured once as a HIP graph and
+ * replayed.  EINVAL for 3D problems, mixed settings or the PCG solver. */
 c4m_status c4m_batch_workspace_bytes(const c4m_config* cfgs, int32_t count, size_t* bytes);
 c4m_status c4m_batch_create(const c4m_config* cfgs, int32_t count, void* d_workspace,
                             size_t bytes, void* hip_stream, c4m_batch** out);

@@ -30,8 +30,9 @@ enum { PH_XE = 0, PH_CE = 1, PH_XH = 2, PH_CHX = 3, PH_CHY = 4, NPH = 5 };
 struct PhaseQueue {
     const int* prefix;       // [count + 1] first work item of each problem
     int count;
-    int* ctr;                // [0]: next item, [1]: workgroups finished
+    int* ctr;                // [0, NXCD): next item of each chunk, [NXCD]: workgroups finished
 };
+static_assert(NXCD + 1 <= 16, "the counters of a phase share one 64-byte line");
 
 __device__ __forceinline__ int find_problem(const PhaseQueue& q, int item)
 {
@@ -45,23 +46,40 @@ __device__ __forceinline__ int find_problem(const PhaseQueue& q, int item)
 }
 
 // Claim the next item for the whole workgroup; -1 when the queue is empty.
+// The item sequence is cut into NXCD contiguous chunks with one counter
+// each.  Workgroup IDs are dealt to the XCDs in turn, so a workgroup takes
+// items from the chunk of its XCD first and from the others once that is
+// empty: the items an XCD runs at the same time are neighbours and share
+// their halo data in that XCD's L2.
 __device__ __forceinline__ int claim(const PhaseQueue& q, int total, int* slot)
 {
     __syncthreads();                         // every thread has read the previous item
-    if (threadIdx.x == 0) *slot = atomicAdd(q.ctr, 1);
+    if (threadIdx.x == 0) {
+        const int per = (total + NXCD - 1) / NXCD;
+        const int home = (int)(blockIdx.x % NXCD);
+        int item = -1;
+        for (int j = 0; j < NXCD && item < 0; ++j) {
+            const int c = (home + j) % NXCD;
+            const int len = min(per, total - c * per);
+            if (len <= 0) continue;
+            const int k = atomicAdd(q.ctr + c, 1);
+            if (k < len) item = c * per + k;
+        }
+        *slot = item;
+    }
     __syncthreads();
-    const int it = *slot;
-    return it < total ? it : -1;
+    return *slot;
 }
 
+// The last workgroup to leave resets the chunk counters and its own count.
 __device__ __forceinline__ void finish(const PhaseQueue& q)
 {
     if (threadIdx.x == 0) {
         __threadfence();
-        const int done = atomicAdd(q.ctr + 1, 1);
+        const int done = atomicAdd(q.ctr + NXCD, 1);
         if (done == (int)gridDim.x - 1) {
-            atomicExch(q.ctr, 0);
-            atomicExch(q.ctr + 1, 0);
+            for (int c = 0; c < NXCD; ++c) atomicExch(q.ctr + c, 0);
+            atomicExch(q.ctr + NXCD, 0);
         }
     }
 }
@@ -95,9 +113,10 @@ __global__ __launch_bounds__(S::NTC) __attribute__((amdgpu_waves_per_eu(S::NL ==
         const int p = find_problem(q, it);
         const int local = it - q.prefix[p];
         const int tx = bp[p].tiles_x[phase];
+        const int ty = (q.prefix[p + 1] - q.prefix[p]) / tx;
         const ColArgs& ca = phase == PH_CE ? bp[p].ce : (phase == PH_CHX ? bp[p].chx : bp[p].chy);
         const PadeLine& L = phase == PH_CE ? bp[p].xe.L : bp[p].xh.L;
-        col_tile<K, MODE, S, FORM>(ca, cf, taps, L, cs, local % tx, local / tx);
+        col_tile<K, MODE, S, FORM>(ca, cf, taps, L, cs, local / ty, local % ty);   // y fastest
     }
     finish(q);
 }
@@ -191,7 +210,7 @@ struct c4m_batch {
     std::vector<c4m_problem*> probs;
     BatchProb* d_probs = nullptr;
     int* d_prefix = nullptr;       // [NPH][count + 1]
-    int* d_ctr = nullptr;          // [NPH][2] (each on its own 64-byte line)
+    int* d_ctr = nullptr;          // [NPH][16]: chunk counters and the finished count (64 bytes a phase)
     int total[NPH] = {};
     Coef coef{};
     PadeTaps taps_xe{}, taps_xh{};

@@ -129,6 +129,24 @@ __global__ __launch_bounds__(256) void k_term3(Term3 t, double alpha, PadeTaps t
     };
     double out[T3_SEG];
     fir(sv + a * BS + seg * T3_SEG, out);
+    if (D == 0) {
+        // x-lines: a thread's outputs run along x, so store through the LDS
+        // and let consecutive lanes write consecutive x positions
+        constexpr int OS = NO + 1;
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < T3_SEG; ++k) sv[a * OS + seg * T3_SEG + k] = out[k];
+        __syncthreads();
+        for (int e = tid; e < A * NO; e += 256) {
+            const int la = e / NO, c = e - la * NO;
+            const int wl = w0 + la, m = m0 + c;
+            if (wl >= t.tg.hi[W] || m >= L.n_out) continue;
+            const size_t oi = s * t.plane + (size_t)wl * t.P + (t.tg.lo[0] + m);
+            const double v = t.scale * sv[la * OS + c];
+            t.out[oi] = t.accumulate ? t.out[oi] + v : v;
+        }
+        return;
+    }
     const int wi = w0 + a;
     if (wi >= t.tg.hi[W]) return;
 #pragma unroll
