@@ -178,6 +178,61 @@ PadeHost build_pade(int n_in, int closure, bool node_to_half)
     return ph;
 }
 
+// Device image of one line kind: the raw rows, the conditioned rows and the
+// interior pair taps, each block starting on a 256-byte boundary.
+int pade_table_rows(int n_out) { return n_out <= 2 * PADE_B ? n_out : 2 * PADE_B + 1; }
+size_t round32(size_t v) { return (v + 31) & ~(size_t)31; }
+size_t line_image_doubles(int n_out)
+{
+    const size_t rows = (size_t)pade_table_rows(n_out);
+    return round32(rows * PADE_TAPS) + round32(rows * COND_TAPS) + round32(PAIR_TAPS);
+}
+
+// Conditioned rows: R(m) = sum_u c_m[u] g(m - R + u), where the conditioned
+// source g(j) = alpha f(j) + (f(j-1) + f(j+1) - 2 f(j)) / 12 on the line,
+// with even ghosts at both ends of a half-point line, zero at the end nodes
+// of a node line, and zero off the line.  Folded into taps on f[m-R-1 ..
+// m+R+2].  The interior row has no end effects.
+std::vector<double> build_line_image(const PadeHost& ph, double alpha, bool half_line)
+{
+    const int n_out = ph.n_out, n_in = ph.n_in;
+    const int rows = pade_table_rows(n_out);
+    std::vector<double> img(line_image_doubles(n_out), 0.0);
+    std::copy(ph.rows.begin(), ph.rows.end(), img.begin());
+    double* crow = img.data() + round32((size_t)rows * PADE_TAPS);
+    double* pairs = crow + round32((size_t)rows * COND_TAPS);
+    for (int r = 0; r < rows; ++r) {
+        const bool interior = !ph.all && r == 2 * ph.b;
+        const int m = ph.all || r < ph.b ? r : (interior ? -1 : r - ph.b + (n_out - ph.b));
+        const double* c = ph.rows.data() + (size_t)r * PADE_TAPS;
+        double* out = crow + (size_t)r * COND_TAPS;
+        for (int u = 0; u < PADE_TAPS; ++u) {
+            // position j = m - R + u, i.e. window slot u + 1; g(j) uses slots u, u+1, u+2
+            double w[3] = {1.0 / 12.0, alpha - 2.0 / 12.0, 1.0 / 12.0};
+            if (!interior) {
+                const int j = m - PADE_R + u;
+                if (j < 0 || j >= n_in) continue;
+                if (!half_line && (j == 0 || j == n_in - 1)) continue;
+                if (half_line && j == 0) {
+                    w[1] += w[0];
+                    w[0] = 0.0;
+                }
+                if (half_line && j == n_in - 1) {
+                    w[1] += w[2];
+                    w[2] = 0.0;
+                }
+            }
+            for (int v = 0; v < 3; ++v) out[u + v] += c[u] * w[v];
+        }
+    }
+    if (!ph.all) {
+        const double* ci = crow + (size_t)(2 * ph.b) * COND_TAPS;
+        for (int j = 0; j < COND_TAPS / 2; ++j) pairs[j] = ci[COND_TAPS / 2 - 1 - j];
+        for (int j = 0; j < PADE_TAPS / 2; ++j) pairs[COND_TAPS / 2 + j] = ph.taps.c[PADE_TAPS / 2 - 1 - j];
+    }
+    return img;
+}
+
 // ---------------------------------------------------------------------------
 // Chebyshev schedule on [alpha, alpha + 16/3 beta] (Saad's Chebyshev
 // acceleration); the number of M-applications is the smallest K with
@@ -233,6 +288,7 @@ struct c4m_problem {
     double* pade_dev[2] = {};           // [0] node->half (n_in N+1), [1] half->node (n_in N)
     int* counter = nullptr;
     PadeHost pade_host[2];
+    std::vector<double> line_img[2];    // device table images (kept until the upload completed)
     PadeLine line[2]{};
     ChebSchedule cheb{};
     Coef coef{};
@@ -296,7 +352,7 @@ c4m_status validate(const c4m_config* c)
     if (c->solver != C4M_SOLVER_CHEBYSHEV && c->solver != C4M_SOLVER_PCG)
         return fail(C4M_EINVAL, "bad solver");
     if (c->sweeps < 0 || c->sweeps > MAX_SWEEPS) return fail(C4M_EINVAL, "sweeps out of range");
-    if (c->tile_x < 0 || c->tile_x > 2) return fail(C4M_EINVAL, "tile_x (column tile shape) must be 0, 1 or 2");
+    if (c->tile_x < 0 || c->tile_x > 5) return fail(C4M_EINVAL, "tile_x (column tile shape) must be in 0..5");
     if (c->tile_y < 0 || c->tile_y > 8) return fail(C4M_EINVAL, "tile_y (persistent grid multiplier) out of range");
     // Section 4: r <= 1/(sqrt(d) ||A^{-1}||) with ||A^{-1}|| ~ 6/5
     const double bound = 5.0 / (6.0 * sqrt((double)c->dim));
@@ -334,8 +390,7 @@ Layout layout(const c4m_config* c)
     L.pcg_bytes = pcg ? align256(3 * ((L.arr + 255) / 256) * sizeof(double)) + 256 : 0;
     for (int k = 0; k < 2; ++k) {
         const int n_out = (k == 0 ? N + 1 : N) - 1;
-        const int rows = n_out <= 2 * PADE_B ? n_out : 2 * PADE_B + 1;
-        L.table_bytes[k] = align256((size_t)rows * PADE_TAPS * sizeof(double));
+        L.table_bytes[k] = align256(line_image_doubles(n_out) * sizeof(double));
     }
     L.total = (size_t)(L.n_fields + L.n_ge + L.n_tmp) * L.arr_bytes + L.pcg_bytes + L.table_bytes[0] +
               L.table_bytes[1] + 256;
@@ -713,8 +768,13 @@ c4m_status c4m_create(const c4m_config* cfg, void* d_workspace, size_t bytes, vo
         const int n_in = k == 0 ? p->N + 1 : p->N;
         p->pade_host[k] = build_pade(n_in, cfg->closure, k == 0);
         const PadeHost& ph = p->pade_host[k];
-        p->line[k] = PadeLine{p->pade_dev[k], ph.n_in, ph.n_out, ph.b, ph.all};
-        hipError_t e = hipMemcpyAsync(p->pade_dev[k], ph.rows.data(), ph.rows.size() * sizeof(double),
+        // line 1 (Step 1 y-lines of Hx) runs over half points, line 0 over nodes
+        p->line_img[k] = build_line_image(ph, p->coef.alpha, k == 1);
+        const int rows = pade_table_rows(ph.n_out);
+        const double* crows = p->pade_dev[k] + round32((size_t)rows * PADE_TAPS);
+        const double* pairs = crows + round32((size_t)rows * COND_TAPS);
+        p->line[k] = PadeLine{p->pade_dev[k], ph.n_in, ph.n_out, ph.b, ph.all, crows, pairs};
+        hipError_t e = hipMemcpyAsync(p->pade_dev[k], p->line_img[k].data(), p->line_img[k].size() * sizeof(double),
                                       hipMemcpyHostToDevice, p->stream);
         if (e != hipSuccess) {
             delete p;

@@ -21,6 +21,14 @@ namespace c4m {
 constexpr int PADE_R = 12;
 constexpr int PADE_TAPS = 2 * PADE_R + 2;
 constexpr int PADE_B = 2 * PADE_R;   // explicit rows at each end of a line
+// Rows of the derivative of the conditioned source alpha f + (second
+// difference of f along the line) / 12, folded into taps on the raw values
+// f[m-R-1 .. m+R+2] (the end rules of the conditioning included).
+constexpr int COND_TAPS = PADE_TAPS + 2;
+// Interior rows are antisymmetric about m + 1/2: tap pairs on
+// f[m-j] - f[m+1+j], j = 0 .. COND_TAPS/2 - 1 (conditioned) and
+// j = 0 .. PADE_TAPS/2 - 1 (raw), stored after the conditioned rows.
+constexpr int PAIR_TAPS = COND_TAPS / 2 + PADE_TAPS / 2;
 
 struct PadeTaps {
     double c[PADE_TAPS];             // interior (Toeplitz) row, tap u at c[u + PADE_R]
@@ -28,11 +36,15 @@ struct PadeTaps {
 
 // Device view of one line kind (a given n_in and node/half orientation).
 // Rows m < b and m >= n_out - b use rows[] (b rows at each end, stored left
-// block then right block); if `all` is set every row is explicit (short
-// lines) and rows[m] is row m.
+// block then right block, then the interior row); if `all` is set every
+// row is explicit (short lines) and rows[m] is row m.  crows has the same
+// row order with COND_TAPS taps per row; pairs holds the interior pair taps
+// (conditioned first).
 struct PadeLine {
     const double* rows;              // [n_rows][PADE_TAPS]
     int n_in, n_out, b, all;
+    const double* crows;             // [n_rows][COND_TAPS]
+    const double* pairs;             // [PAIR_TAPS]
 };
 
 // Spectral bounds of M = alpha I - beta L9: [alpha, alpha + 16/3 beta]

@@ -1,6 +1,6 @@
 // c4m_kernels_2d.hip -- single-problem launches of the 2D TM kernels (the
 // tile code lives in c4m_tiles_2d.h and is shared with the batched form).
-#include "c4m_tiles_2d.h"
+#include "c4m_stream_2d.h"
 
 namespace c4m {
 
@@ -23,6 +23,30 @@ __global__ __launch_bounds__(S::NTC) __attribute__((amdgpu_waves_per_eu(S::NL ==
     col_tile<K, MODE, S, FORM>(a, cf, taps, L, cs, l / nty, l % nty);   // y fastest
 }
 
+template <int K, int MODE, int TRX, int U, int LA>
+__global__ __launch_bounds__(SW_COLS * SW_WAVES) void k_strip(ColArgs a, Coef cf, PadeLine L, ChebSchedule cs)
+{
+    using SS = StripShape<K, MODE, TRX, U, LA>;
+    const int ntx = strip_tiles_x<SS>(a.g), nty = strip_tiles_y<SS>(a.g);
+    const int items = ntx * nty;
+    int l;
+    if (!xcd_tile((items + SW_WAVES - 1) / SW_WAVES, l)) return;
+    const int item = l * SW_WAVES + (int)(threadIdx.x / SW_COLS);
+    if (item >= items) return;
+    strip_tile<K, MODE, TRX, U, LA>(a, cf, L, cs, item / nty, item % nty);   // y fastest
+}
+
+template <int K, int MODE, int TRX, int U, int LA>
+static hipError_t launch_strip(hipStream_t st, const ColArgs& a, const Coef& cf, const PadeLine& L,
+                               const ChebSchedule& cs)
+{
+    using SS = StripShape<K, MODE, TRX, U, LA>;
+    const int items = strip_tiles_x<SS>(a.g) * strip_tiles_y<SS>(a.g);
+    const dim3 grid(xcd_grid((items + SW_WAVES - 1) / SW_WAVES));
+    hipLaunchKernelGGL((k_strip<K, MODE, TRX, U, LA>), grid, dim3(SW_COLS * SW_WAVES), 0, st, a, cf, L, cs);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
@@ -36,6 +60,11 @@ static hipError_t launch_col(int shape, bool mixed, hipStream_t st, const ColArg
             hipLaunchKernelGGL((k_col<K, MODE, S, FORM_MIXED>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);
             return hipGetLastError();
         });
+    if (shape >= 3 && cs.sweeps == 5) {
+        if (shape == 3) return launch_strip<5, MODE, 32, 16, 2>(st, a, cf, L, cs);
+        if (shape == 4) return launch_strip<5, MODE, 48, 16, 2>(st, a, cf, L, cs);
+        return launch_strip<5, MODE, 64, 16, 2>(st, a, cf, L, cs);
+    }
     return with_k_shape(cs.sweeps, shape, [&]<int K, class S>() {
         const dim3 grid(xcd_grid(col_tiles_x<K, S>(a.g) * col_tiles_y<K, S>(a.g)));
         hipLaunchKernelGGL((k_col<K, MODE, S, FORM_FP64>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);

@@ -35,12 +35,18 @@ __device__ __forceinline__ CDouble* as_const(const double* p)
     return (CDouble*)p;
 }
 
+// table row of Pade output m: explicit rows near the ends, else the
+// interior row stored after them
+__host__ __device__ inline int pade_row_index(const PadeLine& L, int m)
+{
+    if (L.all || m < L.b) return m;
+    if (m >= L.n_out - L.b) return m - (L.n_out - L.b) + L.b;
+    return 2 * L.b;
+}
+
 __device__ __forceinline__ const double* pade_row(const PadeLine& L, int m)
 {
-    if (L.all) return L.rows + (size_t)m * PADE_TAPS;
-    if (m < L.b) return L.rows + (size_t)m * PADE_TAPS;
-    if (m >= L.n_out - L.b) return L.rows + (size_t)(m - (L.n_out - L.b) + L.b) * PADE_TAPS;
-    return L.rows + (size_t)(2 * L.b) * PADE_TAPS;   // the interior taps, stored after the boundary rows
+    return L.rows + (size_t)pade_row_index(L, m) * PADE_TAPS;
 }
 
 __device__ __forceinline__ bool pade_interior(const PadeLine& L, int m_lo, int m_hi)
