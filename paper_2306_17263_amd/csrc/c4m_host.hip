@@ -18,13 +18,13 @@ hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const
                            const PadeLine& line_h2n);
 hipError_t launch_solve_e_2d(hipStream_t st, int shape, bool mixed, bool tracked, const double* hx, double* ez, double* ge,
                              const double* t0, const double* t1, int N, int P, const Coef& cf,
-                             const PadeTaps& taps, const PadeLine& line_h2n, const ChebSchedule& cs);
+                             const PadeTaps& taps, const PadeLine& line_h2n, const ChebSchedule& cs, double* yb);
 hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, double* t0, double* t1,
                            int N, int P, const Coef& cf, const PadeTaps& taps,
                            const PadeLine& line_n2h);
 hipError_t launch_solve_h_2d(hipStream_t st, int shape, bool mixed, bool tracked, const double* src, double* hx, double* hy,
                              const double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
-                             const PadeLine& line_n2h, const ChebSchedule& cs);
+                             const PadeLine& line_n2h, const ChebSchedule& cs, double* yb);
 hipError_t launch_pcg_e_2d(hipStream_t st, bool tracked, const double* hx, double* ez, double* ge,
                            const double* t0, double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                            const PadeLine& line_h2n, const ChebSchedule& cs, double* const* pt, double* part,
@@ -286,6 +286,7 @@ struct c4m_problem {
     double* pcg_part = nullptr;         // PCG per-workgroup partial sums
     PcgState* pcg_state = nullptr;      // PCG scalars and statistics
     double* pade_dev[2] = {};           // [0] node->half (n_in N+1), [1] half->node (n_in N)
+    double* yband = nullptr;            // 2D strip form: band derivatives near the y-line ends
     int* counter = nullptr;
     PadeHost pade_host[2];
     std::vector<double> line_img[2];    // device table images (kept until the upload completed)
@@ -352,7 +353,7 @@ c4m_status validate(const c4m_config* c)
     if (c->solver != C4M_SOLVER_CHEBYSHEV && c->solver != C4M_SOLVER_PCG)
         return fail(C4M_EINVAL, "bad solver");
     if (c->sweeps < 0 || c->sweeps > MAX_SWEEPS) return fail(C4M_EINVAL, "sweeps out of range");
-    if (c->tile_x < 0 || c->tile_x > 5) return fail(C4M_EINVAL, "tile_x (column tile shape) must be in 0..5");
+    if (c->tile_x < 0 || c->tile_x > 7) return fail(C4M_EINVAL, "tile_x (column tile shape) must be in 0..7");
     if (c->tile_y < 0 || c->tile_y > 8) return fail(C4M_EINVAL, "tile_y (persistent grid multiplier) out of range");
     // Section 4: r <= 1/(sqrt(d) ||A^{-1}||) with ||A^{-1}|| ~ 6/5
     const double bound = 5.0 / (6.0 * sqrt((double)c->dim));
@@ -369,7 +370,7 @@ c4m_status validate(const c4m_config* c)
 
 struct Layout {
     int P;
-    size_t plane, arr, arr_bytes, table_bytes[2], pcg_bytes, total;
+    size_t plane, arr, arr_bytes, table_bytes[2], pcg_bytes, band_bytes, total;
     int n_fields, n_ge, n_tmp;
 };
 
@@ -392,8 +393,10 @@ Layout layout(const c4m_config* c)
         const int n_out = (k == 0 ? N + 1 : N) - 1;
         L.table_bytes[k] = align256(line_image_doubles(n_out) * sizeof(double));
     }
-    L.total = (size_t)(L.n_fields + L.n_ge + L.n_tmp) * L.arr_bytes + L.pcg_bytes + L.table_bytes[0] +
-              L.table_bytes[1] + 256;
+    // 2D strip form: raw and conditioned derivatives of the band rows at both ends
+    L.band_bytes = c->dim == 2 ? align256((size_t)4 * YB_ROWS * L.P * sizeof(double)) : 0;
+    L.total = (size_t)(L.n_fields + L.n_ge + L.n_tmp) * L.arr_bytes + L.pcg_bytes + L.band_bytes +
+              L.table_bytes[0] + L.table_bytes[1] + 256;
     return L;
 }
 
@@ -604,7 +607,7 @@ c4m_status step_once(c4m_problem* p)
         else if (s == C4M_OK)
             s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
                 return launch_solve_e_2d(p->stream, p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, tracked, hx, ez, ge, t0, t1, N, P, p->coef,
-                                         p->pade_host[1].taps, p->line[1], p->cheb);
+                                         p->pade_host[1].taps, p->line[1], p->cheb, p->yband);
             });
         if (s == C4M_OK)
             s = timed(p, C4M_K_RHS_H, "rhs H", [&] {
@@ -620,7 +623,7 @@ c4m_status step_once(c4m_problem* p)
         else if (s == C4M_OK)
             s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
                 return launch_solve_h_2d(p->stream, p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, tracked, tracked ? ge : ez, hx, hy, t1, N, P,
-                                         p->coef, p->pade_host[0].taps, p->line[0], p->cheb);
+                                         p->coef, p->pade_host[0].taps, p->line[0], p->cheb, p->yband);
             });
         return s;
     }
@@ -741,6 +744,7 @@ c4m_status c4m_create(const c4m_config* cfg, void* d_workspace, size_t bytes, vo
         p->pcg_state = (PcgState*)take(256);
         p->pcg_part = (double*)take(L.pcg_bytes - 256);
     }
+    if (L.band_bytes) p->yband = (double*)take(L.band_bytes);
     p->pade_dev[0] = (double*)take(L.table_bytes[0]);
     p->pade_dev[1] = (double*)take(L.table_bytes[1]);
     p->counter = (int*)take(256);

@@ -29,6 +29,9 @@ constexpr int COND_TAPS = PADE_TAPS + 2;
 // f[m-j] - f[m+1+j], j = 0 .. COND_TAPS/2 - 1 (conditioned) and
 // j = 0 .. PADE_TAPS/2 - 1 (raw), stored after the conditioned rows.
 constexpr int PAIR_TAPS = COND_TAPS / 2 + PADE_TAPS / 2;
+// Rows per end of the band table of the 2D strip form (room for every row
+// of a short line).
+constexpr int YB_ROWS = 2 * PADE_B;
 
 struct PadeTaps {
     double c[PADE_TAPS];             // interior (Toeplitz) row, tap u at c[u + PADE_R]

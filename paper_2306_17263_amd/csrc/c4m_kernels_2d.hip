@@ -1,5 +1,9 @@
 // c4m_kernels_2d.hip -- single-problem launches of the 2D TM kernels (the
 // tile code lives in c4m_tiles_2d.h and is shared with the batched form).
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "c4m_stream_2d.h"
 
 namespace c4m {
@@ -23,27 +27,64 @@ __global__ __launch_bounds__(S::NTC) __attribute__((amdgpu_waves_per_eu(S::NL ==
     col_tile<K, MODE, S, FORM>(a, cf, taps, L, cs, l / nty, l % nty);   // y fastest
 }
 
-template <int K, int MODE, int TRX, int U, int LA>
-__global__ __launch_bounds__(SW_COLS * SW_WAVES) void k_strip(ColArgs a, Coef cf, PadeLine L, ChebSchedule cs)
+template <int K, int MODE, int U, int LA, int WPE>
+__global__ __launch_bounds__(SW_COLS * SW_WAVES) __attribute__((amdgpu_waves_per_eu(WPE))) void k_strip(
+    ColArgs a, Coef cf, PadeLine L, ChebSchedule cs, StripPlan plan)
 {
-    using SS = StripShape<K, MODE, TRX, U, LA>;
-    const int ntx = strip_tiles_x<SS>(a.g), nty = strip_tiles_y<SS>(a.g);
-    const int items = ntx * nty;
+    using SS = StripShape<K, MODE, U, LA>;
+    const int items = plan.items();
     int l;
     if (!xcd_tile((items + SW_WAVES - 1) / SW_WAVES, l)) return;
-    const int item = l * SW_WAVES + (int)(threadIdx.x / SW_COLS);
+    // the wave index is uniform over the wave: say so, so that everything
+    // derived from it (rows, offsets, table rows) lives in scalar registers
+    const int item = l * SW_WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / SW_COLS));
     if (item >= items) return;
-    strip_tile<K, MODE, TRX, U, LA>(a, cf, L, cs, item / nty, item % nty);   // y fastest
+    int strip, y0, tr;
+    plan.item(item, strip, y0, tr);
+    strip_tile<K, MODE, U, LA>(a, cf, L, cs, a.g.lo[0] + strip * SS::OW, y0, tr);
 }
 
-template <int K, int MODE, int TRX, int U, int LA>
+template <bool SPLIT>
+__global__ __launch_bounds__(256) void k_yband(const double* src, double* yb, int N, int P, PadeLine L)
+{
+    yband_entry<SPLIT>(src, yb, N, P, L, (int)(blockIdx.x * 256 + threadIdx.x), (int)blockIdx.y, (int)blockIdx.z);
+}
+
+template <int K, int MODE, int U, int LA, int WPE>
 static hipError_t launch_strip(hipStream_t st, const ColArgs& a, const Coef& cf, const PadeLine& L,
                                const ChebSchedule& cs)
 {
-    using SS = StripShape<K, MODE, TRX, U, LA>;
-    const int items = strip_tiles_x<SS>(a.g) * strip_tiles_y<SS>(a.g);
-    const dim3 grid(xcd_grid((items + SW_WAVES - 1) / SW_WAVES));
-    hipLaunchKernelGGL((k_strip<K, MODE, TRX, U, LA>), grid, dim3(SW_COLS * SW_WAVES), 0, st, a, cf, L, cs);
+    using SS = StripShape<K, MODE, U, LA>;
+    auto kern = k_strip<K, MODE, U, LA, WPE>;
+    // plans of this kernel per problem geometry, made on first use
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int, int, int, int>, StripPlan> plans;
+    const StripPlan* plan = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        const auto key = std::make_tuple(a.N, a.g.lo[0], a.g.hi[0], a.g.lo[1], a.g.hi[1], L.n_in);
+        auto it = plans.find(key);
+        if (it == plans.end()) {
+            int dev = 0, cus = 0, blocks = 0;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, SW_COLS * SW_WAVES, 0);
+            const int slots = (cus > 0 ? cus : 256) * (blocks > 0 ? blocks : 1) * SW_WAVES;
+            StripPlan pl{};
+            if (!strip_plan<SS, K, U>(a.g, L, slots, pl)) return hipErrorInvalidValue;
+            it = plans.emplace(key, pl).first;
+        }
+        plan = &it->second;
+    }
+    if (SS::YPART) {
+        const dim3 gb((a.N + 1 + 255) / 256, band_rows(L), 2);
+        if (SS::SPLIT)
+            hipLaunchKernelGGL(k_yband<true>, gb, dim3(256), 0, st, a.src, a.yb, a.N, a.P, L);
+        else
+            hipLaunchKernelGGL(k_yband<false>, gb, dim3(256), 0, st, a.src, a.yb, a.N, a.P, L);
+    }
+    const dim3 grid(xcd_grid((plan->items() + SW_WAVES - 1) / SW_WAVES));
+    hipLaunchKernelGGL(kern, grid, dim3(SW_COLS * SW_WAVES), 0, st, a, cf, L, cs, *plan);
     return hipGetLastError();
 }
 
@@ -60,10 +101,12 @@ static hipError_t launch_col(int shape, bool mixed, hipStream_t st, const ColArg
             hipLaunchKernelGGL((k_col<K, MODE, S, FORM_MIXED>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);
             return hipGetLastError();
         });
-    if (shape >= 3 && cs.sweeps == 5) {
-        if (shape == 3) return launch_strip<5, MODE, 32, 16, 2>(st, a, cf, L, cs);
-        if (shape == 4) return launch_strip<5, MODE, 48, 16, 2>(st, a, cf, L, cs);
-        return launch_strip<5, MODE, 64, 16, 2>(st, a, cf, L, cs);
+    if (shape >= 3 && cs.sweeps == 5 && a.yb && strip_span_fits(a)) {
+        if (shape == 3) return launch_strip<5, MODE, 8, 1, 3>(st, a, cf, L, cs);
+        if (shape == 4) return launch_strip<5, MODE, 8, 2, 2>(st, a, cf, L, cs);
+        if (shape == 5) return launch_strip<5, MODE, 4, 1, 3>(st, a, cf, L, cs);
+        if (shape == 6) return launch_strip<5, MODE, 8, 1, 2>(st, a, cf, L, cs);
+        return launch_strip<5, MODE, 16, 1, 3>(st, a, cf, L, cs);
     }
     return with_k_shape(cs.sweeps, shape, [&]<int K, class S>() {
         const dim3 grid(xcd_grid(col_tiles_x<K, S>(a.g) * col_tiles_y<K, S>(a.g)));
@@ -100,9 +143,10 @@ hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const
 
 hipError_t launch_solve_e_2d(hipStream_t st, int shape, bool mixed, bool tracked, const double* hx, double* ez, double* ge,
                              const double* t0, const double* t1, int N, int P, const Coef& cf,
-                             const PadeTaps& taps, const PadeLine& line_h2n, const ChebSchedule& cs)
+                             const PadeTaps& taps, const PadeLine& line_h2n, const ChebSchedule& cs, double* yb)
 {
     ColArgs a{hx, t0, t1, ez, ge, ugrid_ez(N), N, P};
+    a.yb = yb;
     if (tracked) return launch_col<COL_E_TRACKED>(shape, mixed, st, a, cf, taps, line_h2n, cs);
     return launch_col<COL_E_DISCRETE>(shape, mixed, st, a, cf, taps, line_h2n, cs);
 }
@@ -123,16 +167,18 @@ hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, doub
 
 hipError_t launch_solve_h_2d(hipStream_t st, int shape, bool mixed, bool tracked, const double* src, double* hx, double* hy,
                              const double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
-                             const PadeLine& line_n2h, const ChebSchedule& cs)
+                             const PadeLine& line_n2h, const ChebSchedule& cs, double* yb)
 {
     // Hx: Dirichlet in x (nodes 1..N-1), Neumann in y (half points 0..N-1);
     // right-hand side -(1/Z) delta_y G_E along columns
     ColArgs ax{src, nullptr, nullptr, hx, nullptr, ugrid_hx(N), N, P};
+    ax.yb = yb;
     hipError_t e = tracked ? launch_col<COL_HX_TRACKED>(shape, mixed, st, ax, cf, taps, line_n2h, cs)
                            : launch_col<COL_HX_DISCRETE>(shape, mixed, st, ax, cf, taps, line_n2h, cs);
     if (e != hipSuccess) return e;
     // Hy: Neumann in x, Dirichlet in y; right-hand side T1 from the x-lines
     ColArgs ay{nullptr, t1, nullptr, hy, nullptr, ugrid_hy(N), N, P};
+    ay.yb = yb;
     return launch_col<COL_HY>(shape, mixed, st, ay, cf, taps, line_n2h, cs);
 }
 

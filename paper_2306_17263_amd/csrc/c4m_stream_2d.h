@@ -26,16 +26,17 @@ namespace c4m {
 
 // Value held by lane l - 1 (by lane l + 1), 0 in lane 0 (lane 63): DPP
 // wavefront shifts by one lane, each half of the double separately.
+// (bound_ctrl: a lane without a source lane reads zero)
 __device__ __forceinline__ double from_left(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x138, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x138, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 __device__ __forceinline__ double from_right(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x130, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
@@ -43,11 +44,11 @@ constexpr int SW_COLS = 64;          // columns of a strip (one wavefront)
 constexpr int SW_WIN = COND_TAPS;    // raw rows in the Pade window
 constexpr int SW_WAVES = 4;          // strips per workgroup
 
-// Strip shapes: TRX region rows (OH = TRX - 2 K output rows), unrolled U
-// steps at a time, per-row inputs fetched LA steps ahead.
-template <int K, int MODE, int TRX, int U, int LA>
+// Strip shapes: unrolled U steps at a time, per-row inputs fetched LA steps
+// ahead.  The region rows TR (a multiple of U; OH = TR - 2 K output rows)
+// are chosen per launch so that the strips fill the machine in whole rounds.
+template <int K, int MODE, int U, int LA>
 struct StripShape {
-    static constexpr int OH = TRX - 2 * K;
     static constexpr bool YPART = MODE != COL_HY;
     static constexpr bool SPLIT = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE || MODE == COL_HX_DISCRETE;
     static constexpr bool ESTEP = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE;
@@ -55,43 +56,122 @@ struct StripShape {
     static constexpr bool CARRY = MODE == COL_E_TRACKED;
     static constexpr int HX = K + (SPLIT ? 1 : 0);   // halo columns on each side
     static constexpr int OW = SW_COLS - 2 * HX;     // output columns
-    static constexpr int TR = TRX;                  // region rows = steps
     static constexpr int NW = YPART ? SW_WIN + LA : 1;
     static constexpr int NQ = LA + 1;               // per-row prefetch queue
-    static_assert(TR % U == 0, "region rows must be a multiple of the unroll");
-    static_assert(OW > 0 && OH > 0, "strip too small for K");
+    static_assert(OW > 0, "strip too narrow for K");
+    static_assert(U % 4 == 0, "the boundary form runs 4 steps per block");
 };
+
+// Band of Pade rows near each end of the y-lines whose derivatives a
+// strip takes from a table pass (k_yband) instead of its interior pair
+// form: rows m <= b and m >= n_out - 1 - b (every row of a short line).
+// Layout: yb[((q * 2 + e) * YB_ROWS + r) * P + gx], q = 0 raw, 1
+// conditioned; e = 0 low end (m = r), 1 high end (m = n_out - rows + r).
+__host__ __device__ inline int band_rows(const PadeLine& L) { return L.all ? L.n_out : L.b + 1; }
 
 template <class SS>
 __host__ __device__ inline int strip_tiles_x(const UGrid& g)
 {
     return (g.hi[0] - g.lo[0] + SS::OW - 1) / SS::OW;
 }
-template <class SS>
-__host__ __device__ inline int strip_tiles_y(const UGrid& g)
+__host__ __device__ inline int strip_tiles_y(const UGrid& g, int oh)
 {
-    return (g.hi[1] - g.lo[1] + SS::OH - 1) / SS::OH;
+    return (g.hi[1] - g.lo[1] + oh - 1) / oh;
 }
 
-// One strip: region columns gx = x0 - HX + lane, output rows [y0, y0 + OH).
-// INNER: every region row and column is strictly inside the unknowns and
-// every Pade row of the region is an interior row, so no masks and the
-// antisymmetric interior taps (pair form) apply.
-template <int K, int MODE, int TRX, int U, int LA, bool INNER>
-__device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, const PadeLine& L,
-                                          const ChebSchedule& cs, int x0, int y0)
+// Buffer (MUBUF) accesses with the hardware range check: a lane whose
+// offset is BUF_NULL (beyond every array's byte size, which stays below
+// 2^32 - 16 for the 2D sizes accepted) reads 0 and its store is dropped,
+// so masked accesses need no branch and an unrolled block of steps stays
+// one basic block.
+constexpr unsigned BUF_NULL = 0xFFFFFFF0u;
+typedef unsigned u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const double* p, unsigned bytes)
 {
-    using SS = StripShape<K, MODE, TRX, U, LA>;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<double*>(p), 0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double buf_ld(__amdgpu_buffer_rsrc_t r, unsigned off)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+// per-lane offset voff plus a wave-uniform offset soff (only where every
+// lane's access is in range)
+__device__ __forceinline__ double buf_ld_s(__amdgpu_buffer_rsrc_t r, unsigned voff, unsigned soff)
+{
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+__device__ __forceinline__ void buf_st(__amdgpu_buffer_rsrc_t r, unsigned off, double v)
+{
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 0);
+}
+
+// The arrays a strip reads and writes (null pointers skipped), as one
+// byte range: every 2D array has N + 1 rows of P doubles.
+struct StripSpan {
+    const double* base;
+    unsigned bytes;
+    __host__ __device__ unsigned delta(const double* p) const
+    {
+        return p ? (unsigned)((const char*)p - (const char*)base) : 0u;
+    }
+};
+__host__ __device__ inline size_t strip_span_bytes(const ColArgs& a, const double*& base)
+{
+    const double* ptrs[6] = {a.src, a.t0, a.t1, a.field, a.ge, a.yb};
+    const size_t arr = (size_t)(a.N + 1) * (size_t)a.P * sizeof(double);
+    const size_t band = (size_t)4 * YB_ROWS * (size_t)a.P * sizeof(double);
+    uintptr_t lo = ~(uintptr_t)0, hi = 0;
+    for (int i = 0; i < 6; ++i) {
+        if (!ptrs[i]) continue;
+        const uintptr_t p = (uintptr_t)ptrs[i];
+        lo = p < lo ? p : lo;
+        const uintptr_t end = p + (i == 5 ? band : arr);
+        hi = end > hi ? end : hi;
+    }
+    base = (const double*)lo;
+    return (size_t)(hi - lo);
+}
+__host__ __device__ inline StripSpan strip_span(const ColArgs& a)
+{
+    StripSpan s;
+    s.bytes = (unsigned)strip_span_bytes(a, s.base);
+    return s;
+}
+// the launcher takes the strip form only when this holds
+__host__ inline bool strip_span_fits(const ColArgs& a)
+{
+    const double* base;
+    return strip_span_bytes(a, base) < (size_t)BUF_NULL;
+}
+
+// One strip: region columns gx = x0 - HX + lane, output rows [y0, y0 + TR - 2K).
+// XB: some lanes of the strip lie on or beyond the x ends of the unknowns
+// (lane masks, Neumann mirrors, zero source off the stored columns).
+// YB: some region rows lie on or beyond the y ends, or some Pade rows of the
+// region are in the end bands (row masks and mirrors; band derivatives from
+// the table pass).  Elsewhere the interior (Toeplitz) Pade rows apply, in
+// pair form.  UU steps per unrolled block.
+// Every load goes to an address inside its array (rows and columns clamped,
+// values outside replaced afterwards), stores of masked lanes are dropped by
+// the buffer range check.
+template <int K, int MODE, int U, int LA, bool XB, bool YB, int UU>
+__device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, const PadeLine& L,
+                                          const ChebSchedule& cs, int x0, int y0, const int TR)
+{
+    using SS = StripShape<K, MODE, U, LA>;
     constexpr bool YPART = SS::YPART, SPLIT = SS::SPLIT, HAS_T0 = SS::HAS_T0, CARRY = SS::CARRY;
-    constexpr int HX = SS::HX, TR = SS::TR, NW = SS::NW, NQ = SS::NQ;
+    constexpr int HX = SS::HX, NQ = SS::NQ;
+    // the raw derivative of row m + 1 needs rows m - 11 .. m + 14 only
+    constexpr int W0 = YPART ? 2 : 0;
+    constexpr int NW = SS::NW - W0;
     const int lane = (int)(threadIdx.x % SW_COLS);
     const UGrid& g = a.g;
-    const int P = a.P;
+    const int P = a.P, N = a.N;
     const int gx = x0 - HX + lane;
-    const bool col_active = gx >= g.lo[0] && gx < g.hi[0];
-    const bool col_data = gx >= 0 && gx <= a.N;
+    const bool col_active = !XB || (gx >= g.lo[0] && gx < g.hi[0]);
+    const bool col_data = !XB || (gx >= 0 && gx <= N);
     const bool nx = g.neumann[0], ny = g.neumann[1];
-    const bool mlo = nx && gx == g.lo[0], mhi = nx && gx == g.hi[0] - 1;
+    const bool mlo = XB && nx && gx == g.lo[0], mhi = XB && nx && gx == g.hi[0] - 1;
     const bool lane_out = lane >= HX && lane < SW_COLS - HX && col_active;
     const int ylo = g.lo[1], yhi = g.hi[1];
     const int ry0 = y0 - K;                             // grid row of region row 0
@@ -99,35 +179,59 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
     const int mbase = ry0 - mofs;                       // Pade output index of region row 0
     const int gbase = mbase - (SW_WIN / 2 - 1);         // raw row in window slot 0 at region row 0
     const int n_in = L.n_in, n_out = L.n_out;
-    const double* __restrict__ src = a.src;
-    const double* __restrict__ t0 = a.t0;
-    const double* __restrict__ t1 = a.t1;
-    double* __restrict__ field = a.field;
-    double* __restrict__ ge = a.ge;
-    const size_t cofs = (size_t)(col_data ? gx : 0);
+
+    // one buffer over every array of the strip (their span stays below
+    // BUF_NULL: checked by the launcher); each array is a byte offset in it
+    const StripSpan sp = strip_span(a);
+    const __amdgpu_buffer_rsrc_t rb = buf_rsrc(sp.base, sp.bytes);
+    const unsigned dsrc = sp.delta(a.src), dt0 = sp.delta(a.t0), dt1 = sp.delta(a.t1);
+    const unsigned dfield = sp.delta(a.field), dge = sp.delta(a.ge);
+    const unsigned rowb = (unsigned)P * (unsigned)sizeof(double);
+    const int gxc = gx < 0 ? 0 : (gx > N ? N : gx);
+    const unsigned laneb = (unsigned)gxc * (unsigned)sizeof(double);
+    auto clampi = [](int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); };
 
     const double b6 = cf.beta * (1.0 / 6.0);
     const double a36 = fma(36.0, b6, cf.alpha);
     const double ysign = SS::ESTEP ? -cf.z : (MODE == COL_HY ? 0.0 : -1.0 / cf.z);
 
+    // raw source row gg (zero off the stored columns; rows off the line only
+    // feed derivatives of band rows, which are replaced)
     auto load_raw = [&](int gg) -> double {
-        if (INNER) return src[(size_t)gg * P + cofs];
-        return (gg >= 0 && gg < n_in && col_data) ? src[(size_t)gg * P + cofs] : 0.0;
+        const double v = buf_ld_s(rb, laneb, dsrc + (unsigned)(YB ? clampi(gg, 0, n_in - 1) : gg) * rowb);
+        return col_data ? v : 0.0;
     };
-    // grid rows of the per-row inputs: t0 of region row ry; field, G_E and
-    // t1 of the output row that leaves the pipeline at step ry
-    auto row_act = [&](int gy) -> bool { return INNER ? true : (col_active && gy >= ylo && gy < yhi); };
-    auto load_t0 = [&](int ry) -> double {
-        const int gy = ry0 + ry;
-        return (ry < TR && row_act(gy)) ? t0[(size_t)gy * P + cofs] : 0.0;
+    // band values (q = 0 raw, 1 conditioned) of Pade row m, zero off the line
+    const int nbr = band_rows(L);
+    const unsigned dyb = sp.delta(a.yb);
+    auto in_band = [&](int m) -> bool { return YB && (m <= L.b || m >= n_out - 1 - L.b || L.all); };
+    auto band = [&](int q, int m) -> double {
+        const int e = m < nbr ? 0 : 1;
+        const int r = clampi(e ? m - (n_out - nbr) : m, 0, nbr - 1);
+        const double v = buf_ld_s(rb, laneb, dyb + (unsigned)((q * 2 + e) * YB_ROWS + r) * rowb);
+        return (m >= 0 && m < n_out && col_data) ? v : 0.0;
     };
+    auto row_in = [&](int gy) -> bool { return !YB || (gy >= ylo && gy < yhi); };
     auto out_row = [&](int ry) -> bool {   // step ry updates grid row ry0 + ry - K
-        const int gy = ry0 + ry - K;
-        return ry >= 2 * K && ry < TR && gy < yhi;
+        return ry >= 2 * K && ry < TR && (!YB || ry0 + ry - K < yhi);
+    };
+    // per-row inputs: t0 of region row ry; field, G_E and t1 of the output
+    // row that leaves the pipeline at step ry (rows clamped into the valid
+    // range: values of other rows are never used)
+    auto prefetch = [&](int ry, double& t0v, double& fv, double& gv, double& t1v) {
+        const int rt = ry < TR ? ry : TR - 1;
+        const int gyt = YB ? clampi(ry0 + rt, ylo, yhi - 1) : ry0 + rt;
+        t0v = HAS_T0 ? buf_ld_s(rb, laneb, dt0 + (unsigned)gyt * rowb) : 0.0;
+        const int ro = rt < 2 * K ? 2 * K : rt;
+        const int gyo = YB ? clampi(ry0 + ro - K, ylo, yhi - 1) : ry0 + ro - K;
+        const unsigned so = (unsigned)gyo * rowb;
+        fv = buf_ld_s(rb, laneb, dfield + so);
+        gv = CARRY ? buf_ld_s(rb, laneb, dge + so) : 0.0;
+        t1v = CARRY ? buf_ld_s(rb, laneb, dt1 + so) : 0.0;
     };
 
     // ---- state
-    double fw[NW];                 // raw window: slot i holds raw row gbase + ry + i
+    double fw[NW];                 // raw window: slot i holds raw row gbase + W0 + ry + i
     double t0q[NQ], fq[NQ], gq[NQ], t1q[NQ];
     double pd[K + 1];              // raw Pade derivative of the last K + 1 rows
     double dp1[K], dp2[K], rp1[K], xp1[K];
@@ -137,32 +241,45 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
     for (int j = 0; j <= K; ++j) pd[j] = 0.0;
     if (YPART) {
 #pragma unroll
-        for (int i = 1; i < NW; ++i) fw[i] = load_raw(gbase - 1 + i);
+        for (int i = W0 ? 0 : 1; i < NW; ++i) fw[i] = load_raw(gbase + W0 - 1 + i);
     }
 #pragma unroll
-    for (int i = 1; i < NQ; ++i) {
-        const int ry = i - 1;
-        t0q[i] = HAS_T0 ? load_t0(ry) : 0.0;
-        const bool o = out_row(ry) && lane_out;
-        const size_t off = (size_t)(o ? ry0 + ry - K : 0) * P + cofs;
-        fq[i] = o ? field[off] : 0.0;
-        gq[i] = (CARRY && o) ? ge[off] : 0.0;
-        t1q[i] = (CARRY && o) ? t1[off] : 0.0;
+    for (int i = 1; i < NQ; ++i) prefetch(i - 1, t0q[i], fq[i], gq[i], t1q[i]);
+
+    CDouble* pq = as_const(L.pairs) + COND_TAPS / 2;    // raw interior pair taps
+    // interior raw derivative from 26 consecutive rows w(0..25) (rows
+    // m - 12 .. m + 13): sum_j p_j (f(m - j) - f(m + 1 + j))
+    auto fir_pair = [&](auto&& w) -> double {
+        double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < PADE_TAPS / 2; j += 2) {
+            p0 = fma(pq[j], w(PADE_TAPS / 2 - 1 - j) - w(PADE_TAPS / 2 + j), p0);
+            if (j + 1 < PADE_TAPS / 2) p1 = fma(pq[j + 1], w(PADE_TAPS / 2 - 2 - j) - w(PADE_TAPS / 2 + 1 + j), p1);
+        }
+        return p0 + p1;
+    };
+    // raw derivatives of the rows mbase - 1 and mbase before step 0 (fw[i]
+    // holds row mbase - 12 + i)
+    double pm1 = 0.0, pm0 = 0.0;
+    if (YPART) {
+        const double extra = load_raw(mbase - PADE_R - 1);
+        pm1 = fir_pair([&](int i) { return i == 0 ? extra : fw[i - 1]; });
+        pm0 = fir_pair([&](int i) { return fw[i]; });
+        if (YB) {
+            pm1 = in_band(mbase - 1) ? band(0, mbase - 1) : pm1;
+            pm0 = in_band(mbase) ? band(0, mbase) : pm0;
+        }
     }
 
-    CDouble* tab = as_const(L.rows);
-    CDouble* ctab = as_const(L.crows);
-    CDouble* pq = as_const(L.pairs);                    // 14 conditioned, then 13 raw pair taps
-
-    for (int blk = 0; blk < TR; blk += U) {
+    for (int blk = 0; blk < TR; blk += UU) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
+        for (int u = 0; u < UU; ++u) {
             const int ry = blk + u;
             // ---- advance the window and the prefetch queues
             if (YPART) {
 #pragma unroll
                 for (int i = 0; i < NW - 1; ++i) fw[i] = fw[i + 1];
-                fw[NW - 1] = load_raw(gbase + ry + NW - 1);
+                fw[NW - 1] = load_raw(gbase + W0 + ry + NW - 1);
             }
 #pragma unroll
             for (int i = 0; i < NQ - 1; ++i) {
@@ -171,62 +288,40 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
                 gq[i] = gq[i + 1];
                 t1q[i] = t1q[i + 1];
             }
-            {
-                const int rn = ry + LA;
-                t0q[NQ - 1] = HAS_T0 ? load_t0(rn) : 0.0;
-                const bool o = out_row(rn) && lane_out;
-                const size_t off = (size_t)(o ? ry0 + rn - K : 0) * P + cofs;
-                fq[NQ - 1] = o ? field[off] : 0.0;
-                gq[NQ - 1] = (CARRY && o) ? ge[off] : 0.0;
-                t1q[NQ - 1] = (CARRY && o) ? t1[off] : 0.0;
-            }
+            prefetch(ry + LA, t0q[NQ - 1], fq[NQ - 1], gq[NQ - 1], t1q[NQ - 1]);
 
             // ---- line derivatives of Pade row m = mbase + ry: raw (pr) and of
-            // the conditioned source (cr); the window holds rows m - 13 .. m + 14
+            // the conditioned source (cr).  The conditioning along the line
+            // commutes with the interior (Toeplitz) rows, so there
+            // R(m) = alpha P(m) + (P(m-1) + P(m+1) - 2 P(m)) / 12.
             double pr = 0.0, cr = 0.0;
             if (YPART) {
-                if (INNER) {
-                    double dl[SW_WIN / 2];
-#pragma unroll
-                    for (int j = 0; j < SW_WIN / 2; ++j) dl[j] = fw[SW_WIN / 2 - 1 - j] - fw[SW_WIN / 2 + j];
-#pragma unroll
-                    for (int j = 0; j < PADE_TAPS / 2; ++j) pr = fma(pq[SW_WIN / 2 + j], dl[j], pr);
-                    if (SPLIT) {
-#pragma unroll
-                        for (int j = 0; j < SW_WIN / 2; ++j) cr = fma(pq[j], dl[j], cr);
-                    } else {
-                        cr = pr;
-                    }
+                const int m = mbase + ry;
+                double pp1 = fir_pair([&](int i2) { return fw[i2]; });
+                if (YB) pp1 = in_band(m + 1) ? band(0, m + 1) : pp1;
+                pr = pm0;
+                if (SPLIT) {
+                    cr = fma(cf.alpha, pm0, (pm1 + pp1 - 2.0 * pm0) * (1.0 / 12.0));
+                    if (YB) cr = in_band(m) ? band(1, m) : cr;
                 } else {
-                    const int m = mbase + ry;
-                    if (m >= 0 && m < n_out) {
-                        const int row = pade_row_index(L, m);
-                        CDouble* tp = tab + (size_t)row * PADE_TAPS;
-#pragma unroll
-                        for (int u2 = 0; u2 < PADE_TAPS; ++u2) pr = fma(tp[u2], fw[1 + u2], pr);
-                        if (SPLIT) {
-                            CDouble* tq = ctab + (size_t)row * COND_TAPS;
-#pragma unroll
-                            for (int w = 0; w < COND_TAPS; ++w) cr = fma(tq[w], fw[w], cr);
-                        } else {
-                            cr = pr;
-                        }
-                    }
+                    cr = pm0;
                 }
+                pm1 = pm0;
+                pm0 = pp1;
             }
 
             // ---- right-hand side of region row ry
             const int gy = ry0 + ry;
-            double b = 0.0;
+            double b;
             {
                 double v = 0.0;
                 if (YPART) {
-                    double s = cr;
-                    if (SPLIT) s += (from_left(pr) + from_right(pr) - 2.0 * pr) * (1.0 / 12.0);
-                    v = ysign * s;
+                    double sum = cr;
+                    if (SPLIT) sum += (from_left(pr) + from_right(pr) - 2.0 * pr) * (1.0 / 12.0);
+                    v = ysign * sum;
                 }
                 if (HAS_T0) v += t0q[0];
-                b = row_act(gy) ? v : 0.0;
+                b = (row_in(gy) && col_active) ? v : 0.0;
             }
             if (CARRY) {
 #pragma unroll
@@ -243,22 +338,22 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
             for (int j = 0; j < K; ++j) {
                 const int gq_ = gy - j - 1;
                 double up = dp2[j], cen = dp1[j], dw = dn[j];
-                if (!INNER) {
-                    if (ny && gq_ == ylo) up = cen;
-                    if (ny && gq_ == yhi - 1) dw = cen;
+                if (YB) {
+                    up = (ny && gq_ == ylo) ? cen : up;
+                    dw = (ny && gq_ == yhi - 1) ? cen : dw;
                 }
                 const double sown = fma(4.0, cen, up + dw);
                 double sl = from_left(sown), sr = from_right(sown);
-                if (!INNER) {
-                    if (mlo) sl = sown;
-                    if (mhi) sr = sown;
+                if (XB) {
+                    sl = mlo ? sown : sl;
+                    sr = mhi ? sown : sr;
                 }
-                const double ad = fma(a36, cen, -b6 * fma(4.0, sown, sl + sr));
+                // r - M d with M d = a36 d - b6 (4 S + S(x-1) + S(x+1))
                 xn[j + 1] = j == 0 ? cen : xp1[j] + cen;
-                double r_ = rp1[j] - ad;
+                double r_ = fma(b6, fma(4.0, sown, sl + sr), fma(-a36, cen, rp1[j]));
                 double d_ = fma(cs.c1[j], cen, cs.c2[j] * r_);
-                if (!INNER) {
-                    const bool act = col_active && gq_ >= ylo && gq_ < yhi;
+                if (XB || YB) {
+                    const bool act = row_in(gq_) && col_active;
                     r_ = act ? r_ : 0.0;
                     d_ = act ? d_ : 0.0;
                 }
@@ -273,39 +368,188 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
                 xp1[j] = xn[j];
             }
 
-            // ---- update of grid row gy - K
-            if (out_row(ry) && lane_out) {
-                const double phi = xn[K] + dn[K];
-                const size_t o = (size_t)(gy - K) * P + cofs;
-                const double de = cf.cfl * phi;
-                field[o] = fq[0] + de;
-                if (CARRY) ge[o] = gq[0] + fma(cf.ge_gain, de, -cf.ge_curl * (t1q[0] - pd[0]));
+            // ---- update of grid row gy - K (other lanes and rows: BUF_NULL)
+            {
+                const bool ok = out_row(ry) && lane_out;
+                const unsigned row = (unsigned)(gy - K) * rowb + laneb;
+                const double de = cf.cfl * (xn[K] + dn[K]);
+                buf_st(rb, ok ? dfield + row : BUF_NULL, fq[0] + de);
+                if (CARRY)
+                    buf_st(rb, ok ? dge + row : BUF_NULL,
+                           gq[0] + fma(cf.ge_gain, de, -cf.ge_curl * (t1q[0] - pd[0])));
             }
         }
     }
 }
 
-template <int K, int MODE, int TRX, int U, int LA>
-__device__ __forceinline__ void strip_tile(const ColArgs& a, const Coef& cf, const PadeLine& L,
-                                           const ChebSchedule& cs, int bxi, int byi)
+// Which form a strip takes: 0 interior, 1 x ends (XB), 2 y ends (XB and YB).
+template <class SS, int K>
+__host__ __device__ inline int strip_variant(const UGrid& g, const PadeLine& L, int x0, int y0, int tr)
 {
-    using SS = StripShape<K, MODE, TRX, U, LA>;
-    const UGrid& g = a.g;
-    const int x0 = g.lo[0] + bxi * SS::OW;
-    const int y0 = g.lo[1] + byi * SS::OH;
     const int rx0 = x0 - SS::HX, ry0 = y0 - K;
     const int mofs = SS::ESTEP ? 1 : 0;
-    bool inner = rx0 > g.lo[0] && rx0 + SW_COLS < g.hi[0] && ry0 > g.lo[1] && ry0 + SS::TR < g.hi[1];
+    // x: every lane strictly inside the unknowns (no mirror, no mask)
+    const bool xin = rx0 > g.lo[0] && rx0 + SW_COLS < g.hi[0];
+    // y: every region row strictly inside; the Pade rows of the region and
+    // two beyond each end stay out of the bands, and the window in the line
+    bool yin = ry0 > g.lo[1] && ry0 + tr < g.hi[1];
     if (SS::YPART) {
-        // Pade rows of the region are interior rows; the window rows stay in the line
-        const int m_lo = ry0 - mofs, m_hi = ry0 - mofs + SS::TR - 1;
-        inner = inner && pade_interior(L, m_lo, m_hi) && m_lo - SW_WIN / 2 >= 0 &&
-                m_hi + SW_WIN / 2 + SS::NW - SW_WIN < L.n_in;
+        const int m_lo = ry0 - mofs, m_hi = ry0 - mofs + tr - 1;
+        yin = yin && !L.all && m_lo - 2 >= L.b && m_hi + 2 < L.n_out - L.b && m_lo - SW_WIN / 2 >= 0 &&
+              m_hi + SW_WIN / 2 + SS::NW - SW_WIN < L.n_in;
     }
-    if (inner)
-        strip_run<K, MODE, TRX, U, LA, true>(a, cf, L, cs, x0, y0);
+    return !yin ? 2 : (!xin ? 1 : 0);
+}
+
+// Strip plan: the segments (first output row y0, region rows tr) of the
+// strips with some lane at the x ends (type 0: the first xa and the last
+// xb strips) and of the other strips (type 1).  Segment lengths are chosen
+// so that the estimated work of the items (cost per step of their form
+// times steps plus the window fill) is about equal and the items fill whole
+// rounds of the resident wave slots.  Items: the type-0 strips first, then
+// the type-1 strips, segments of a strip consecutive.
+constexpr int STRIP_MAXSEG = 192;
+struct StripPlan {
+    int strips, xa, xb;
+    int nseg[2];
+    short y0[2][STRIP_MAXSEG];
+    short tr[2][STRIP_MAXSEG];
+    __host__ __device__ int items() const
+    {
+        return (xa + xb) * nseg[0] + (strips - xa - xb) * nseg[1];
+    }
+    // strip index, output row and region rows of item it
+    __host__ __device__ void item(int it, int& strip, int& y0v, int& trv) const
+    {
+        const int ix = (xa + xb) * nseg[0];
+        int t, k, sg;
+        if (it < ix) {
+            t = 0;
+            k = it / nseg[0];
+            sg = it - k * nseg[0];
+            strip = k < xa ? k : strips - xb + (k - xa);
+        } else {
+            t = 1;
+            it -= ix;
+            k = it / nseg[1];
+            sg = it - k * nseg[1];
+            strip = xa + k;
+        }
+        y0v = y0[t][sg];
+        trv = tr[t][sg];
+    }
+};
+
+template <int K, int MODE, int U, int LA>
+__device__ __forceinline__ void strip_tile(const ColArgs& a, const Coef& cf, const PadeLine& L,
+                                           const ChebSchedule& cs, int x0, int y0, int tr)
+{
+    using SS = StripShape<K, MODE, U, LA>;
+    const int v = strip_variant<SS, K>(a.g, L, x0, y0, tr);
+    if (v == 0)
+        strip_run<K, MODE, U, LA, false, false, U>(a, cf, L, cs, x0, y0, tr);
+    else if (v == 1)
+        strip_run<K, MODE, U, LA, true, false, U>(a, cf, L, cs, x0, y0, tr);
     else
-        strip_run<K, MODE, TRX, U, LA, false>(a, cf, L, cs, x0, y0);
+        strip_run<K, MODE, U, LA, true, true, U>(a, cf, L, cs, x0, y0, tr);
+}
+
+constexpr double STRIP_COST[3] = {1.0, 1.3, 1.9};
+constexpr int STRIP_FILL_STEPS = 6;
+template <class SS, int K, int U>
+inline bool strip_plan(const UGrid& g, const PadeLine& L, int slots, StripPlan& plan)
+{
+    const int strips = strip_tiles_x<SS>(g);
+    plan.strips = strips;
+    plan.xa = plan.xb = 0;
+    auto x0_of = [&](int i) { return g.lo[0] + i * SS::OW; };
+    auto xin = [&](int i) {
+        const int rx0 = x0_of(i) - SS::HX;
+        return rx0 > g.lo[0] && rx0 + SW_COLS < g.hi[0];
+    };
+    while (plan.xa < strips && !xin(plan.xa)) ++plan.xa;
+    while (plan.xa + plan.xb < strips && !xin(strips - 1 - plan.xb)) ++plan.xb;
+    const int nstr[2] = {plan.xa + plan.xb, strips - plan.xa - plan.xb};
+    const int rep[2] = {0, plan.xa};    // a strip of each type
+    const int tr_min = ((2 * K + 1) + U - 1) / U * U;
+    const int span = g.hi[1] - g.lo[1];
+    auto cost = [&](int t, int y0, int tr) {
+        return STRIP_COST[strip_variant<SS, K>(g, L, x0_of(rep[t]), y0, tr)] * (tr + STRIP_FILL_STEPS);
+    };
+    // segments of a strip of type t for a target cost; -1 if too many
+    auto layout = [&](int t, double target, bool store, double& worst) -> int {
+        int n = 0;
+        for (int y0 = g.lo[1]; y0 < g.hi[1];) {
+            int tr = tr_min;
+            while (tr + U - 2 * K <= span + 2 * U && cost(t, y0, tr + U) <= target) tr += U;
+            const double c = cost(t, y0, tr);
+            worst = c > worst ? c : worst;
+            if (n == STRIP_MAXSEG) return -1;
+            if (store) {
+                plan.y0[t][n] = (short)y0;
+                plan.tr[t][n] = (short)tr;
+            }
+            ++n;
+            y0 += tr - 2 * K;
+        }
+        return n;
+    };
+    double best_t = 0.0, best_make = 0.0;
+    for (double t = STRIP_COST[0] * (tr_min + STRIP_FILL_STEPS); t < 1e7; t *= 1.03) {
+        double worst = 0.0;
+        int items = 0;
+        bool ok = true;
+        for (int k = 0; k < 2; ++k) {
+            if (!nstr[k]) continue;
+            const int n = layout(k, t, false, worst);
+            if (n < 0) ok = false;
+            items += n * nstr[k];
+        }
+        if (!ok) continue;
+        const double make = (double)((items + slots - 1) / slots) * worst;
+        if (best_t == 0.0 || make < best_make) {
+            best_t = t;
+            best_make = make;
+        }
+        if (items <= slots / 8) break;
+    }
+    if (best_t == 0.0) return false;
+    for (int k = 0; k < 2; ++k) {
+        double worst = 0.0;
+        plan.nseg[k] = nstr[k] ? layout(k, best_t, true, worst) : 0;
+    }
+    return true;
+}
+
+// Table pass for the strips: raw and conditioned y-line derivatives of
+// the band rows of every stored column (one thread per column, band row and
+// end), with the exact rows of A^{-1} near the line ends and the end rules
+// of the source conditioning folded into the conditioned rows.
+template <bool SPLIT>
+__device__ __forceinline__ void yband_entry(const double* __restrict__ src, double* __restrict__ yb, int N, int P,
+                                            const PadeLine& L, int gx, int r, int e)
+{
+    const int nbr = band_rows(L), n_out = L.n_out, n_in = L.n_in;
+    if (gx > N || r >= nbr || (e == 1 && L.all)) return;
+    const int m = e ? n_out - nbr + r : r;
+    const int row = pade_row_index(L, m);
+    CDouble* tp = as_const(L.rows) + (size_t)row * PADE_TAPS;
+    CDouble* tq = as_const(L.crows) + (size_t)row * COND_TAPS;
+    double f[COND_TAPS];    // rows m - R - 1 .. m + R + 2, zero off the line
+#pragma unroll
+    for (int w = 0; w < COND_TAPS; ++w) {
+        const int j = m - PADE_R - 1 + w;
+        f[w] = (j >= 0 && j < n_in) ? src[(size_t)j * P + gx] : 0.0;
+    }
+    double pr = 0.0, cr = 0.0;
+#pragma unroll
+    for (int u = 0; u < PADE_TAPS; ++u) pr = fma(tp[u], f[u + 1], pr);
+    if (SPLIT) {
+#pragma unroll
+        for (int w = 0; w < COND_TAPS; ++w) cr = fma(tq[w], f[w], cr);
+    }
+    yb[((size_t)(0 * 2 + e) * YB_ROWS + r) * P + gx] = pr;
+    yb[((size_t)(1 * 2 + e) * YB_ROWS + r) * P + gx] = SPLIT ? cr : pr;
 }
 
 }  // namespace c4m

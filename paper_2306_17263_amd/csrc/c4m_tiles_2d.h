@@ -240,6 +240,7 @@ struct ColArgs {
     int N, P;
     double* b_out;          // FORM_RHS: right-hand side on the unknowns
     double* cv_out;         // FORM_RHS, carried Laplacian: curl^A H (may alias t1)
+    double* yb = nullptr;   // strip form: y-line derivatives near the line ends
 };
 
 // Per-lane boundary description of a column tile; the row masks are
