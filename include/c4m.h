@@ -101,11 +101,16 @@ typedef struct {
     int32_t sweeps;     /* Chebyshev M-applications per solve (0 = enough for 1e-16)   */
     int32_t max_iter;   /* PCG iteration cap per solve (0 = 16)                         */
     double rtol;        /* PCG relative residual target (0 = 1e-14)                    */
-    int32_t tile_x;     /* kernel tile override (0 = built-in / autotuned)             */
+    int32_t tile_x;     /* column kernel shape, 0..4 (0 = built-in, see below)         */
     int32_t tile_y;
     uint32_t flags;     /* C4M_FLAG_*                                                  */
     int32_t reserved[5];
 } c4m_config;
+/* tile_x, single 2D problems (FP64 Chebyshev): 0 = wave strips (one
+ * wavefront per 64 columns walks down a row segment, no LDS; falls back
+ * to 3 where it does not apply), 4 = wave strips unrolled 16 steps,
+ * 1 = 64 x 4 column tiles, 2 = 128 x 2, 3 = 128 x 4.  Batched form:
+ * 0 = 128 x 4 column tiles, 1 = 64 x 4, 2 = 128 x 2.  3D: ignored. */
 
 typedef struct {
     int64_t steps;            /* whole steps taken since create                       */

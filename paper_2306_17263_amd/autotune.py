@@ -1,8 +1,12 @@
 """Autotuner for the kernel launch shape.
 
 Tunables (fields of c4m_config):
-  tile_x  column-kernel tile shape: 0 = 128 columns x 4 lanes per column,
-          1 = 64 x 4, 2 = 128 x 2 (shapes 1 and 2 exist for 4..6 sweeps);
+  tile_x  column-kernel shape.  Single 2D problems: 0 = wave strips (one
+          wavefront per 64 columns streaming down a row segment, 8 steps
+          per unrolled block), 4 = wave strips with 16 steps per block,
+          1 = 64 x 4 column tiles, 2 = 128 x 2, 3 = 128 x 4.  Batched form:
+          0 = 128 columns x 4 lanes per column, 1 = 64 x 4, 2 = 128 x 2
+          (shapes 1 and 2 exist for 4..6 sweeps);
   tile_y  batched form only: persistent-grid multiplier (workgroups per
           launch = multiplier x what fits on the device at once).
 The halo depth of the column tiles equals the number of Chebyshev sweeps,
@@ -20,7 +24,8 @@ import os
 import time
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "c4m_autotune.json")
-SHAPES = (0, 1, 2)
+SHAPES = (0, 1, 2)            # batched form
+SINGLE_SHAPES = (0, 4, 3)     # single 2D problems: strips, strips x16, 128 x 4 tiles
 GRID_MULT = (1, 2)
 
 
@@ -96,7 +101,7 @@ def tune_single(n: int, dim: int = 2, cfl: float = 0.5, steps: int = 8, use_cach
     st = torch.cuda.Stream()
     timings = {}
     # the 3D path and the FP32-refined form have one column-tile shape
-    shapes = SHAPES if dim == 2 and settings.get("precision", "fp64") == "fp64" else (0,)
+    shapes = SINGLE_SHAPES if dim == 2 and settings.get("precision", "fp64") == "fp64" else (0,)
     for shape in shapes:
         p = Problem(dim, n, cfl, stream=st, tile_x=shape, **settings)
         p.step(1)

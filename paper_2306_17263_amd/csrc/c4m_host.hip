@@ -353,7 +353,7 @@ c4m_status validate(const c4m_config* c)
     if (c->solver != C4M_SOLVER_CHEBYSHEV && c->solver != C4M_SOLVER_PCG)
         return fail(C4M_EINVAL, "bad solver");
     if (c->sweeps < 0 || c->sweeps > MAX_SWEEPS) return fail(C4M_EINVAL, "sweeps out of range");
-    if (c->tile_x < 0 || c->tile_x > 7) return fail(C4M_EINVAL, "tile_x (column tile shape) must be in 0..7");
+    if (c->tile_x < 0 || c->tile_x > 4) return fail(C4M_EINVAL, "tile_x (column kernel shape) must be in 0..4");
     if (c->tile_y < 0 || c->tile_y > 8) return fail(C4M_EINVAL, "tile_y (persistent grid multiplier) out of range");
     // Section 4: r <= 1/(sqrt(d) ||A^{-1}||) with ||A^{-1}|| ~ 6/5
     const double bound = 5.0 / (6.0 * sqrt((double)c->dim));

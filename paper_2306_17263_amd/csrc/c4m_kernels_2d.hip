@@ -50,6 +50,21 @@ __global__ __launch_bounds__(256) void k_yband(const double* src, double* yb, in
     yband_entry<SPLIT>(src, yb, N, P, L, (int)(blockIdx.x * 256 + threadIdx.x), (int)blockIdx.y, (int)blockIdx.z);
 }
 
+// Dispatch a callable templated on K (2 .. 8) for the strip form.
+template <class F>
+inline hipError_t with_k_strip(int K, F&& f)
+{
+    switch (K) {
+        case 2: return f.template operator()<2>();
+        case 3: return f.template operator()<3>();
+        case 4: return f.template operator()<4>();
+        case 5: return f.template operator()<5>();
+        case 6: return f.template operator()<6>();
+        case 7: return f.template operator()<7>();
+        default: return f.template operator()<8>();
+    }
+}
+
 template <int K, int MODE, int U, int LA, int WPE>
 static hipError_t launch_strip(hipStream_t st, const ColArgs& a, const Coef& cf, const PadeLine& L,
                                const ChebSchedule& cs)
@@ -101,13 +116,13 @@ static hipError_t launch_col(int shape, bool mixed, hipStream_t st, const ColArg
             hipLaunchKernelGGL((k_col<K, MODE, S, FORM_MIXED>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);
             return hipGetLastError();
         });
-    if (shape >= 3 && cs.sweeps == 5 && a.yb && strip_span_fits(a)) {
-        if (shape == 3) return launch_strip<5, MODE, 8, 1, 3>(st, a, cf, L, cs);
-        if (shape == 4) return launch_strip<5, MODE, 8, 2, 2>(st, a, cf, L, cs);
-        if (shape == 5) return launch_strip<5, MODE, 4, 1, 3>(st, a, cf, L, cs);
-        if (shape == 6) return launch_strip<5, MODE, 8, 1, 2>(st, a, cf, L, cs);
-        return launch_strip<5, MODE, 16, 1, 3>(st, a, cf, L, cs);
-    }
+    // shape 0 (default) and 4: the strip form where it applies; 1, 2, 3:
+    // the column tiles (64 x 4, 128 x 2, 128 x 4 lanes)
+    if ((shape == 0 || shape == 4) && cs.sweeps >= 2 && a.yb && strip_span_fits(a))
+        return with_k_strip(cs.sweeps, [&]<int K>() {
+            if (shape == 0) return launch_strip<K, MODE, 8, 1, 3>(st, a, cf, L, cs);
+            return launch_strip<K, MODE, 16, 1, 3>(st, a, cf, L, cs);
+        });
     return with_k_shape(cs.sweeps, shape, [&]<int K, class S>() {
         const dim3 grid(xcd_grid(col_tiles_x<K, S>(a.g) * col_tiles_y<K, S>(a.g)));
         hipLaunchKernelGGL((k_col<K, MODE, S, FORM_FP64>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);

@@ -59,7 +59,7 @@ def test_explicit_sweep_counts(sweeps):
     assert rel_l2_all(gf, of, EH) <= tol
 
 
-@pytest.mark.parametrize("shape", [1, 2])
+@pytest.mark.parametrize("shape", [1, 2, 3, 4])
 @pytest.mark.parametrize("lap", ["tracked", "discrete"])
 def test_tile_shapes_parity(shape, lap):
     # the alternative column-tile shapes of the autotuner give the same scheme

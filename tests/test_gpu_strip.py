@@ -1,0 +1,70 @@
+"""Wave-strip form of the 2D column kernel (the default single-problem
+path) against the CPU oracle and against the column-tile form.
+
+The strip form streams each 64-column strip down a row segment; strips
+near the x ends, segments near the y ends (the Pade band rows taken from
+the table pass) and interior strips take different code, and the segment
+lengths come from a per-geometry plan.  These cases put every form on the
+oracle at sizes from one strip to many, for each sweep count the strip
+form is built for.
+"""
+import numpy as np
+import pytest
+
+from gpu_util import initial_fields, rel_l2, rel_l2_all, run_pair
+
+pytestmark = pytest.mark.gpu
+
+EH = ["ez", "hx", "hy"]
+
+
+@pytest.mark.parametrize("n", [8, 9, 40, 49, 50, 97, 130, 301])
+@pytest.mark.parametrize("lap", ["tracked", "discrete"])
+def test_strip_oracle_parity(n, lap):
+    gf, of = run_pair(2, n, 0.5, 6, closure="paper" if n % 2 else "reflect", lap=lap, seed=100 + n)
+    assert rel_l2_all(gf, of, EH) <= 1e-12
+    if "lz" in gf:
+        assert rel_l2(gf["lz"], of["lz"]) <= 1e-9
+
+
+@pytest.mark.parametrize("sweeps", [2, 3, 4, 6, 7, 8])
+def test_strip_sweep_counts(sweeps):
+    # every K the strip form is built for: the same K Chebyshev applications
+    # as the column tiles (3), so the two agree to rounding
+    from paper_2306_17263_amd import Problem
+    n = 150
+    init = initial_fields(2, n, 0.45, seed=sweeps)
+    out = {}
+    for shape in (3, 0):
+        g = Problem(2, n, 0.45, sweeps=sweeps, tile_x=shape)
+        for name in g.fields():
+            g.set(name, init[name])
+        g.step(4)
+        out[shape] = {a: g.get(a) for a in EH}
+        g.close()
+    assert rel_l2_all(out[0], out[3], EH) <= 1e-13
+
+
+@pytest.mark.parametrize("cfl", [0.2, 0.35, 0.58])
+def test_strip_cfl(cfl):
+    gf, of = run_pair(2, 120, cfl, 5, seed=7)
+    assert rel_l2_all(gf, of, EH) <= 1e-12
+
+
+def test_strip_matches_tiles_large():
+    # N = 2048 (many strips and segments): strips (0, 4) against the
+    # 128 x 4 column tiles (3), random data, a few steps
+    from paper_2306_17263_amd import Problem
+    n = 2048
+    init = initial_fields(2, n, 0.5, seed=21)
+    out = {}
+    for shape in (3, 0, 4):
+        p = Problem(2, n, 0.5, tile_x=shape)
+        for name in p.fields():
+            p.set(name, init[name])
+        p.step(3)
+        out[shape] = {a: p.get(a) for a in p.fields()}
+        p.close()
+    for shape in (0, 4):
+        assert rel_l2_all(out[shape], out[3], EH) <= 1e-13, shape
+        assert rel_l2(out[shape]["lz"], out[3]["lz"]) <= 1e-10
