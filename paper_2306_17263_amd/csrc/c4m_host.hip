@@ -15,13 +15,14 @@ namespace c4m {
 // kernels (c4m_kernels_2d.hip, c4m_kernels_3d.hip, c4m_kernels_common.hip)
 hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const double* hy, double* t0,
                            double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
-                           const PadeLine& line_h2n);
+                           const PadeLine& line_h2n, double* yb);
+bool strip_form_2d(int shape, bool mixed, int sweeps);
 hipError_t launch_solve_e_2d(hipStream_t st, int shape, bool mixed, bool tracked, const double* hx, double* ez, double* ge,
                              const double* t0, const double* t1, int N, int P, const Coef& cf,
                              const PadeTaps& taps, const PadeLine& line_h2n, const ChebSchedule& cs, double* yb);
 hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, double* t0, double* t1,
                            int N, int P, const Coef& cf, const PadeTaps& taps,
-                           const PadeLine& line_n2h);
+                           const PadeLine& line_n2h, double* yb);
 hipError_t launch_solve_h_2d(hipStream_t st, int shape, bool mixed, bool tracked, const double* src, double* hx, double* hy,
                              const double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                              const PadeLine& line_n2h, const ChebSchedule& cs, double* yb);
@@ -593,11 +594,18 @@ c4m_status step_once(c4m_problem* p)
     if (p->dim == 2) {
         double *hx = p->f[C4M_HX], *hy = p->f[C4M_HY], *ez = p->f[C4M_EZ], *ge = p->ge[2];
         double *t0 = p->tmp[0], *t1 = p->tmp[1];
+        const bool pcg = p->cfg.solver == C4M_SOLVER_PCG;
+        // the strip form (band table filled by the x-line launches): one
+        // buffer resource spans the arrays it touches, so the used part of
+        // the workspace must stay below 4 GiB
+        double* yb = (!pcg && p->yband && p->used < (size_t)0xFFFFF000u &&
+                      strip_form_2d(p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, p->cheb.sweeps))
+                         ? p->yband
+                         : nullptr;
         c4m_status s = timed(p, C4M_K_RHS_E, "rhs E", [&] {
             return launch_rhs_e_2d(p->stream, tracked, hx, hy, t0, t1, N, P, p->coef,
-                                   p->pade_host[1].taps, p->line[1]);
+                                   p->pade_host[1].taps, p->line[1], yb);
         });
-        const bool pcg = p->cfg.solver == C4M_SOLVER_PCG;
         if (s == C4M_OK && pcg)
             s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
                 return launch_pcg_e_2d(p->stream, tracked, hx, ez, ge, t0, t1, N, P, p->coef, p->pade_host[1].taps,
@@ -607,12 +615,12 @@ c4m_status step_once(c4m_problem* p)
         else if (s == C4M_OK)
             s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
                 return launch_solve_e_2d(p->stream, p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, tracked, hx, ez, ge, t0, t1, N, P, p->coef,
-                                         p->pade_host[1].taps, p->line[1], p->cheb, p->yband);
+                                         p->pade_host[1].taps, p->line[1], p->cheb, yb);
             });
         if (s == C4M_OK)
             s = timed(p, C4M_K_RHS_H, "rhs H", [&] {
                 return launch_rhs_h_2d(p->stream, tracked, tracked ? ge : ez, t0, t1, N, P, p->coef,
-                                       p->pade_host[0].taps, p->line[0]);
+                                       p->pade_host[0].taps, p->line[0], yb);
             });
         if (s == C4M_OK && pcg)
             s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
@@ -623,7 +631,7 @@ c4m_status step_once(c4m_problem* p)
         else if (s == C4M_OK)
             s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
                 return launch_solve_h_2d(p->stream, p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, tracked, tracked ? ge : ez, hx, hy, t1, N, P,
-                                         p->coef, p->pade_host[0].taps, p->line[0], p->cheb, p->yband);
+                                         p->coef, p->pade_host[0].taps, p->line[0], p->cheb, yb);
             });
         return s;
     }

@@ -8,10 +8,34 @@
 
 namespace c4m {
 
+// Band rows of the strip form's y-lines, computed by extra workgroups of
+// the x-line launch that precedes each strip solve.
+struct YbandArgs {
+    const double* src;      // y-line source of the following solve
+    double* yb;             // band table (null: no band work)
+    PadeLine L;
+    int split;              // conditioned derivatives as well
+};
+__host__ __device__ inline int yband_blocks(const YbandArgs& y, int N)
+{
+    return y.yb ? ((N + 1 + 255) / 256) * band_rows(y.L) * 2 : 0;
+}
+
 template <int MODE>
-__global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps)
+__global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps, YbandArgs yba)
 {
     const int ntx = xlines_tiles_x(xa.L.n_out), nty = xlines_tiles_y(xa.N);
+    const int xgrid = xcd_grid(ntx * nty);
+    if ((int)blockIdx.x >= xgrid) {
+        const int id = (int)blockIdx.x - xgrid, nbx = (xa.N + 1 + 255) / 256, nbr = band_rows(yba.L);
+        const int bx = id % nbx, r = (id / nbx) % nbr, e = id / (nbx * nbr);
+        const int gx = bx * 256 + (int)threadIdx.x;
+        if (yba.split)
+            yband_entry<true>(yba.src, yba.yb, xa.N, xa.P, yba.L, gx, r, e);
+        else
+            yband_entry<false>(yba.src, yba.yb, xa.N, xa.P, yba.L, gx, r, e);
+        return;
+    }
     int l;
     if (!xcd_tile(ntx * nty, l)) return;
     xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, l % ntx, l / ntx);
@@ -44,10 +68,11 @@ __global__ __launch_bounds__(SW_COLS * SW_WAVES) __attribute__((amdgpu_waves_per
     strip_tile<K, MODE, U, LA>(a, cf, L, cs, a.g.lo[0] + strip * SS::OW, y0, tr);
 }
 
-template <bool SPLIT>
-__global__ __launch_bounds__(256) void k_yband(const double* src, double* yb, int N, int P, PadeLine L)
+// Whether a 2D single-problem solve takes the strip form (the host then
+// provides the band table, in a workspace whose span fits one buffer).
+bool strip_form_2d(int shape, bool mixed, int sweeps)
 {
-    yband_entry<SPLIT>(src, yb, N, P, L, (int)(blockIdx.x * 256 + threadIdx.x), (int)blockIdx.y, (int)blockIdx.z);
+    return (shape == 0 || shape == 4) && !mixed && sweeps >= 2 && sweeps <= MAX_SWEEPS;
 }
 
 // Dispatch a callable templated on K (2 .. 8) for the strip form.
@@ -91,13 +116,6 @@ static hipError_t launch_strip(hipStream_t st, const ColArgs& a, const Coef& cf,
         }
         plan = &it->second;
     }
-    if (SS::YPART) {
-        const dim3 gb((a.N + 1 + 255) / 256, band_rows(L), 2);
-        if (SS::SPLIT)
-            hipLaunchKernelGGL(k_yband<true>, gb, dim3(256), 0, st, a.src, a.yb, a.N, a.P, L);
-        else
-            hipLaunchKernelGGL(k_yband<false>, gb, dim3(256), 0, st, a.src, a.yb, a.N, a.P, L);
-    }
     const dim3 grid(xcd_grid((plan->items() + SW_WAVES - 1) / SW_WAVES));
     hipLaunchKernelGGL(kern, grid, dim3(SW_COLS * SW_WAVES), 0, st, a, cf, L, cs, *plan);
     return hipGetLastError();
@@ -116,9 +134,10 @@ static hipError_t launch_col(int shape, bool mixed, hipStream_t st, const ColArg
             hipLaunchKernelGGL((k_col<K, MODE, S, FORM_MIXED>), grid, dim3(S::NTC), 0, st, a, cf, taps, L, cs);
             return hipGetLastError();
         });
-    // shape 0 (default) and 4: the strip form where it applies; 1, 2, 3:
-    // the column tiles (64 x 4, 128 x 2, 128 x 4 lanes)
-    if ((shape == 0 || shape == 4) && cs.sweeps >= 2 && a.yb && strip_span_fits(a))
+    // shape 0 (default) and 4: the strip form where it applies (the caller
+    // passes the band table only then); 1, 2, 3: the column tiles (64 x 4,
+    // 128 x 2, 128 x 4 lanes)
+    if (strip_form_2d(shape, mixed, cs.sweeps) && a.yb)
         return with_k_strip(cs.sweeps, [&]<int K>() {
             if (shape == 0) return launch_strip<K, MODE, 8, 1, 3>(st, a, cf, L, cs);
             return launch_strip<K, MODE, 16, 1, 3>(st, a, cf, L, cs);
@@ -143,16 +162,17 @@ static hipError_t launch_col_rhs(hipStream_t st, const ColArgs& a, const Coef& c
 
 hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const double* hy, double* t0,
                            double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
-                           const PadeLine& line_h2n)
+                           const PadeLine& line_h2n, double* yb)
 {
-    // x-lines of Hy: N inputs, N-1 outputs, rows 1..N-1
-    const dim3 grid(xcd_grid(xlines_tiles_x(line_h2n.n_out) * xlines_tiles_y(N)));
-    (void)hx;
+    // x-lines of Hy: N inputs, N-1 outputs, rows 1..N-1; with the strip
+    // form also the band rows of the y-lines of Hx
+    const YbandArgs yba{hx, yb, line_h2n, 1};
+    const dim3 grid(xcd_grid(xlines_tiles_x(line_h2n.n_out) * xlines_tiles_y(N)) + yband_blocks(yba, N));
     const XArgs xa{hy, t0, t1, N, P, line_h2n};
     if (tracked)
-        hipLaunchKernelGGL(k_xlines<XL_E_TRACKED>, grid, dim3(256), 0, st, xa, cf, taps);
+        hipLaunchKernelGGL(k_xlines<XL_E_TRACKED>, grid, dim3(256), 0, st, xa, cf, taps, yba);
     else
-        hipLaunchKernelGGL(k_xlines<XL_E_DISCRETE>, grid, dim3(256), 0, st, xa, cf, taps);
+        hipLaunchKernelGGL(k_xlines<XL_E_DISCRETE>, grid, dim3(256), 0, st, xa, cf, taps, yba);
     return hipGetLastError();
 }
 
@@ -168,15 +188,17 @@ hipError_t launch_solve_e_2d(hipStream_t st, int shape, bool mixed, bool tracked
 
 hipError_t launch_rhs_h_2d(hipStream_t st, bool tracked, const double* src, double* t0, double* t1,
                            int N, int P, const Coef& cf, const PadeTaps& taps,
-                           const PadeLine& line_n2h)
+                           const PadeLine& line_n2h, double* yb)
 {
-    // x-lines of G_E: N+1 inputs, N outputs (Hy half points), rows 1..N-1
-    const dim3 grid(xcd_grid(xlines_tiles_x(line_n2h.n_out) * xlines_tiles_y(N)));
+    // x-lines of G_E: N+1 inputs, N outputs (Hy half points), rows 1..N-1;
+    // with the strip form also the band rows of the y-lines of the same source
+    const YbandArgs yba{src, yb, line_n2h, tracked ? 0 : 1};
+    const dim3 grid(xcd_grid(xlines_tiles_x(line_n2h.n_out) * xlines_tiles_y(N)) + yband_blocks(yba, N));
     const XArgs xa{src, t0, t1, N, P, line_n2h};
     if (tracked)
-        hipLaunchKernelGGL(k_xlines<XL_H_TRACKED>, grid, dim3(256), 0, st, xa, cf, taps);
+        hipLaunchKernelGGL(k_xlines<XL_H_TRACKED>, grid, dim3(256), 0, st, xa, cf, taps, yba);
     else
-        hipLaunchKernelGGL(k_xlines<XL_H_DISCRETE>, grid, dim3(256), 0, st, xa, cf, taps);
+        hipLaunchKernelGGL(k_xlines<XL_H_DISCRETE>, grid, dim3(256), 0, st, xa, cf, taps, yba);
     return hipGetLastError();
 }
 

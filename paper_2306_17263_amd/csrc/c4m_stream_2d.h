@@ -137,12 +137,6 @@ __host__ __device__ inline StripSpan strip_span(const ColArgs& a)
     s.bytes = (unsigned)strip_span_bytes(a, s.base);
     return s;
 }
-// the launcher takes the strip form only when this holds
-__host__ inline bool strip_span_fits(const ColArgs& a)
-{
-    const double* base;
-    return strip_span_bytes(a, base) < (size_t)BUF_NULL;
-}
 
 // One strip: region columns gx = x0 - HX + lane, output rows [y0, y0 + TR - 2K).
 // XB: some lanes of the strip lie on or beyond the x ends of the unknowns
@@ -181,7 +175,8 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
     const int n_in = L.n_in, n_out = L.n_out;
 
     // one buffer over every array of the strip (their span stays below
-    // BUF_NULL: checked by the launcher); each array is a byte offset in it
+    // BUF_NULL: the caller takes the strip form only then); each array is a
+    // byte offset in it
     const StripSpan sp = strip_span(a);
     const __amdgpu_buffer_rsrc_t rb = buf_rsrc(sp.base, sp.bytes);
     const unsigned dsrc = sp.delta(a.src), dt0 = sp.delta(a.t0), dt1 = sp.delta(a.t1);
