@@ -96,7 +96,10 @@ __global__ __launch_bounds__(256) void k_batch_x(const BatchProb* __restrict__ b
         const int local = it - q.prefix[p];
         const int tx = bp[p].tiles_x[phase];
         const XArgs& xa = phase == PH_XE ? bp[p].xe : bp[p].xh;
-        xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, local % tx, local / tx);
+        if constexpr (MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE)
+            xlines_e_tile<MODE == XL_E_TRACKED>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, local % tx, local / tx);
+        else
+            xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, local % tx, local / tx);
     }
     finish(q);
 }
@@ -336,8 +339,8 @@ c4m_status build_tables(c4m_batch* b, char* cur)
         d.chy = ColArgs{nullptr, v.tmp[1], nullptr, v.f[C4M_HY], nullptr, ugrid_hy(N), N, v.P};
         const int K = v.cheb.sweeps;
         int tiles[NPH];
-        d.tiles_x[PH_XE] = xlines_tiles_x(v.line[1].n_out);
-        tiles[PH_XE] = d.tiles_x[PH_XE] * xlines_tiles_y(N);
+        d.tiles_x[PH_XE] = xe_tiles_x(v.line[1].n_out);
+        tiles[PH_XE] = d.tiles_x[PH_XE] * xe_tiles_y(N);
         tiles[PH_CE] = col_tiles_k(K, shape, mixed, d.ce.g, &d.tiles_x[PH_CE]);
         d.tiles_x[PH_XH] = xlines_tiles_x(v.line[0].n_out);
         tiles[PH_XH] = d.tiles_x[PH_XH] * xlines_tiles_y(N);

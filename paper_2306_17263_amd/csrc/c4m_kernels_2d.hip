@@ -21,10 +21,23 @@ __host__ __device__ inline int yband_blocks(const YbandArgs& y, int N)
     return y.yb ? ((N + 1 + 255) / 256) * band_rows(y.L) * 2 : 0;
 }
 
+// Step 1 x-lines take the raw-derivative tiles (xlines_e_tile), Step 2
+// the direct ones.
+template <int MODE>
+__host__ __device__ inline int xl_tiles_x(int n_out)
+{
+    return (MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE) ? xe_tiles_x(n_out) : xlines_tiles_x(n_out);
+}
+template <int MODE>
+__host__ __device__ inline int xl_tiles_y(int N)
+{
+    return (MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE) ? xe_tiles_y(N) : xlines_tiles_y(N);
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps, YbandArgs yba)
 {
-    const int ntx = xlines_tiles_x(xa.L.n_out), nty = xlines_tiles_y(xa.N);
+    const int ntx = xl_tiles_x<MODE>(xa.L.n_out), nty = xl_tiles_y<MODE>(xa.N);
     const int xgrid = xcd_grid(ntx * nty);
     if ((int)blockIdx.x >= xgrid) {
         const int id = (int)blockIdx.x - xgrid, nbx = (xa.N + 1 + 255) / 256, nbr = band_rows(yba.L);
@@ -38,7 +51,10 @@ __global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps
     }
     int l;
     if (!xcd_tile(ntx * nty, l)) return;
-    xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, l % ntx, l / ntx);
+    if constexpr (MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE)
+        xlines_e_tile<MODE == XL_E_TRACKED>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, l % ntx, l / ntx);
+    else
+        xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, l % ntx, l / ntx);
 }
 
 template <int K, int MODE, class S, int FORM>
@@ -167,7 +183,7 @@ hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const
     // x-lines of Hy: N inputs, N-1 outputs, rows 1..N-1; with the strip
     // form also the band rows of the y-lines of Hx
     const YbandArgs yba{hx, yb, line_h2n, 1};
-    const dim3 grid(xcd_grid(xlines_tiles_x(line_h2n.n_out) * xlines_tiles_y(N)) + yband_blocks(yba, N));
+    const dim3 grid(xcd_grid(xe_tiles_x(line_h2n.n_out) * xe_tiles_y(N)) + yband_blocks(yba, N));
     const XArgs xa{hy, t0, t1, N, P, line_h2n};
     if (tracked)
         hipLaunchKernelGGL(k_xlines<XL_E_TRACKED>, grid, dim3(256), 0, st, xa, cf, taps, yba);

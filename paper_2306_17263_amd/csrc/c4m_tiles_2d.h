@@ -193,6 +193,136 @@ __device__ __forceinline__ void xlines_tile(const double* __restrict__ src, doub
 }
 
 // ===========================================================================
+// x-lines of Step 1 from raw derivatives only.  The conditioning G splits
+// into the part along the line and the part across it; the derivative
+// along the line commutes with both away from the line ends (interior
+// Toeplitz rows), so with P = the raw line derivative of a row
+//   T0 = Z (alpha P + (P(m-1) + P(m+1) - 2 P(m)) / 12 + (P_s + P_n - 2 P) / 12)
+// (P_s, P_n: the rows below and above), and T1 = P.  Near the line ends
+// the along-line part comes from the conditioned table rows instead.
+// Tile: P on 32 rows (j0 - 1 .. j0 + 30) x 64 outputs (m0 - 1 .. m0 + 62),
+// 256 threads, 8 outputs per thread from a register window; T0 and T1 on
+// the inner 30 x 62.
+// ===========================================================================
+constexpr int XE_PROWS = 32;
+constexpr int XE_OROWS = XE_PROWS - 2;
+constexpr int XE_POUT = 64;
+constexpr int XE_OUT = XE_POUT - 2;
+constexpr int XE_SEG = 8;
+constexpr int XE_IN = XE_POUT + PADE_TAPS - 1;     // staged inputs per row (89)
+constexpr int XE_STRIDE = XE_IN + 2;               // odd
+constexpr int XE_PSTRIDE = XE_POUT + 1;            // odd
+constexpr int XE_WIN = XE_SEG + PADE_TAPS - 1;
+
+__host__ __device__ inline int xe_tiles_x(int n_out) { return (n_out + XE_OUT - 1) / XE_OUT; }
+__host__ __device__ inline int xe_tiles_y(int N) { return (N - 1 + XE_OROWS - 1) / XE_OROWS; }
+
+template <bool TWO>
+__device__ __forceinline__ void xlines_e_tile(const double* __restrict__ src, double* __restrict__ t0,
+                                              double* __restrict__ t1, int N, int P, const PadeLine& L,
+                                              const Coef& cf, int bxi, int byi)
+{
+    __shared__ double sh[XE_PROWS * XE_STRIDE];       // raw rows, later the T0 tile
+    __shared__ double sp[XE_PROWS * XE_PSTRIDE];      // P
+    const int tid = threadIdx.x;
+    const int m0 = bxi * XE_OUT;                       // first T0 output of the tile
+    const int j0 = 1 + byi * XE_OROWS;                 // first T0 row
+    const int n_in = L.n_in, n_out = L.n_out;
+    const int g0 = m0 - 1 - PADE_R;                    // line position of staged column 0
+    // ---- stage the raw rows j0 - 1 .. j0 + 30 (zero off the grid and line)
+    for (int e = tid; e < XE_PROWS * XE_IN; e += 256) {
+        const int rr = e / XE_IN, q = e - rr * XE_IN;
+        const int j = j0 - 1 + rr, g = g0 + q;
+        double v = 0.0;
+        if (j <= N && g >= 0 && g < n_in) v = src[(size_t)j * P + g];
+        sh[rr * XE_STRIDE + q] = v;
+    }
+    __syncthreads();
+    // ---- P on the 32 x 64 outputs; 8 per thread
+    const int row = tid % XE_PROWS;
+    const int seg = tid / XE_PROWS;
+    const int mb = m0 - 1 + seg * XE_SEG;              // Pade output of this thread's first P
+    const double* w = sh + row * XE_STRIDE + seg * XE_SEG;   // staged position of f[mb - 12]
+    double pv[XE_SEG];
+    const bool fast = pade_interior(L, mb, mb + XE_SEG - 1);
+    if (fast) {
+        CDouble* tc = as_const(L.rows + (size_t)(2 * L.b) * PADE_TAPS);
+        double f[XE_WIN];
+#pragma unroll
+        for (int u = 0; u < XE_WIN; ++u) f[u] = w[u];
+#pragma unroll
+        for (int k = 0; k < XE_SEG; ++k) pv[k] = 0.0;
+#pragma unroll
+        for (int u = 0; u < PADE_TAPS; ++u) {
+            const double c = tc[u];
+#pragma unroll
+            for (int k = 0; k < XE_SEG; ++k) pv[k] = fma(c, f[k + u], pv[k]);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < XE_SEG; ++k) {
+            const int m = mb + k;
+            double a = 0.0;
+            if (m >= 0 && m < n_out) {
+                CDouble* cr = as_const(pade_row(L, m));
+                for (int u = 0; u < PADE_TAPS; ++u) a = fma(cr[u], w[k + u], a);
+            }
+            pv[k] = a;
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < XE_SEG; ++k) sp[row * XE_PSTRIDE + seg * XE_SEG + k] = pv[k];
+    __syncthreads();
+    // ---- T0 on the inner rows and outputs, through the LDS for row stores
+    double t0v[XE_SEG];
+    const bool out_row = row >= 1 && row <= XE_OROWS;
+#pragma unroll
+    for (int k = 0; k < XE_SEG; ++k) {
+        const int c = seg * XE_SEG + k;                // P column (output m = mb + k)
+        const int m = mb + k;
+        double v = 0.0;
+        if (out_row && c >= 1 && c <= XE_OUT) {
+            const double* q = sp + row * XE_PSTRIDE + c;
+            const double pc = q[0];
+            const double across = (q[-XE_PSTRIDE] + q[XE_PSTRIDE] - 2.0 * pc) * (1.0 / 12.0);
+            double along;
+            if (!L.all && m - 1 >= L.b && m + 1 < n_out - L.b) {
+                along = fma(cf.alpha, pc, (q[-1] + q[1] - 2.0 * pc) * (1.0 / 12.0));
+            } else {
+                along = 0.0;
+                if (m >= 0 && m < n_out) {
+                    // conditioned table row: raw positions m - 13 .. m + 14
+                    CDouble* cr = as_const(L.crows + (size_t)pade_row_index(L, m) * COND_TAPS);
+                    const double* wr = sh + row * XE_STRIDE + c - 1;   // staged f[m - 13]
+                    for (int u = 0; u < COND_TAPS; ++u) along = fma(cr[u], wr[u], along);
+                }
+            }
+            v = cf.z * (along + across);
+        }
+        t0v[k] = v;
+    }
+    __syncthreads();
+    constexpr int OS = XE_OUT + 1;
+    if (out_row) {
+#pragma unroll
+        for (int k = 0; k < XE_SEG; ++k) {
+            const int c = seg * XE_SEG + k;
+            if (c >= 1 && c <= XE_OUT) sh[(row - 1) * OS + c - 1] = t0v[k];
+        }
+    }
+    __syncthreads();
+    // E step: node i = m + 1
+    for (int e = tid; e < XE_OROWS * XE_OUT; e += 256) {
+        const int rr = e / XE_OUT, c = e - rr * XE_OUT;
+        const int jj = j0 + rr, m = m0 + c;
+        if (jj <= N - 1 && m < n_out) {
+            t0[(size_t)jj * P + m + 1] = sh[rr * OS + c];
+            if (TWO) t1[(size_t)jj * P + m + 1] = sp[(rr + 1) * XE_PSTRIDE + c + 1];
+        }
+    }
+}
+
+// ===========================================================================
 // Column kernel: y-line Pade + Chebyshev solve + update.
 // A workgroup covers a region of CW = 128 columns and TR rows.  The column
 // of region row r is held by NL lanes: lane (c, q) keeps rows
