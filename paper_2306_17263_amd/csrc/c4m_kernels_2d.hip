@@ -127,7 +127,7 @@ static hipError_t launch_strip(hipStream_t st, const ColArgs& a, const Coef& cf,
             (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, SW_COLS * SW_WAVES, 0);
             const int slots = (cus > 0 ? cus : 256) * (blocks > 0 ? blocks : 1) * SW_WAVES;
             StripPlan pl{};
-            if (!strip_plan<SS, K, U>(a.g, L, slots, pl)) return hipErrorInvalidValue;
+            if (!strip_plan<SS, K, U>(a.g, L, slots, (cus > 0 ? cus : 256) * 4, pl)) return hipErrorInvalidValue;
             it = plans.emplace(key, pl).first;
         }
         plan = &it->second;

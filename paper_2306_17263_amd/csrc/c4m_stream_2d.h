@@ -449,10 +449,16 @@ __device__ __forceinline__ void strip_tile(const ColArgs& a, const Coef& cf, con
         strip_run<K, MODE, U, LA, true, true, U>(a, cf, L, cs, x0, y0, tr);
 }
 
+// Cost model of the plan: work per step of the three forms, the window
+// fill in steps, and how many resident waves it takes to keep a SIMD busy
+// (the estimated time of a launch is the larger of its longest item and
+// its total work over the SIMDs at that many waves each, per round of the
+// resident wave slots).
 constexpr double STRIP_COST[3] = {1.0, 1.3, 1.9};
 constexpr int STRIP_FILL_STEPS = 6;
+constexpr double STRIP_WAVES_PER_SIMD = 3.0;
 template <class SS, int K, int U>
-inline bool strip_plan(const UGrid& g, const PadeLine& L, int slots, StripPlan& plan)
+inline bool strip_plan(const UGrid& g, const PadeLine& L, int slots, int simds, StripPlan& plan)
 {
     const int strips = strip_tiles_x<SS>(g);
     plan.strips = strips;
@@ -472,13 +478,14 @@ inline bool strip_plan(const UGrid& g, const PadeLine& L, int slots, StripPlan& 
         return STRIP_COST[strip_variant<SS, K>(g, L, x0_of(rep[t]), y0, tr)] * (tr + STRIP_FILL_STEPS);
     };
     // segments of a strip of type t for a target cost; -1 if too many
-    auto layout = [&](int t, double target, bool store, double& worst) -> int {
+    auto layout = [&](int t, double target, bool store, double& worst, double& total) -> int {
         int n = 0;
         for (int y0 = g.lo[1]; y0 < g.hi[1];) {
             int tr = tr_min;
             while (tr + U - 2 * K <= span + 2 * U && cost(t, y0, tr + U) <= target) tr += U;
             const double c = cost(t, y0, tr);
             worst = c > worst ? c : worst;
+            total += c * nstr[t];
             if (n == STRIP_MAXSEG) return -1;
             if (store) {
                 plan.y0[t][n] = (short)y0;
@@ -491,17 +498,19 @@ inline bool strip_plan(const UGrid& g, const PadeLine& L, int slots, StripPlan& 
     };
     double best_t = 0.0, best_make = 0.0;
     for (double t = STRIP_COST[0] * (tr_min + STRIP_FILL_STEPS); t < 1e7; t *= 1.03) {
-        double worst = 0.0;
+        double worst = 0.0, total = 0.0;
         int items = 0;
         bool ok = true;
         for (int k = 0; k < 2; ++k) {
             if (!nstr[k]) continue;
-            const int n = layout(k, t, false, worst);
+            const int n = layout(k, t, false, worst, total);
             if (n < 0) ok = false;
             items += n * nstr[k];
         }
         if (!ok) continue;
-        const double make = (double)((items + slots - 1) / slots) * worst;
+        const int rounds = (items + slots - 1) / slots;
+        const double per_round = total / rounds / (simds * STRIP_WAVES_PER_SIMD);
+        const double make = rounds * (worst > per_round ? worst : per_round);
         if (best_t == 0.0 || make < best_make) {
             best_t = t;
             best_make = make;
@@ -510,8 +519,8 @@ inline bool strip_plan(const UGrid& g, const PadeLine& L, int slots, StripPlan& 
     }
     if (best_t == 0.0) return false;
     for (int k = 0; k < 2; ++k) {
-        double worst = 0.0;
-        plan.nseg[k] = nstr[k] ? layout(k, best_t, true, worst) : 0;
+        double worst = 0.0, total = 0.0;
+        plan.nseg[k] = nstr[k] ? layout(k, best_t, true, worst, total) : 0;
     }
     return true;
 }
