@@ -58,9 +58,16 @@ COPY_PROBE_BYTES = 256 << 20
 # kernel-class -> kernel-name pattern of the 2D path (rocprofv3 names)
 CLASS_PATTERNS = {
     "rhs_e": r"k_xlines<[01]>",
-    "solve_e": r"k_col<\d+, [01],",
+    "solve_e": r"k_(?:strip|col)<\d+, [01],",
     "rhs_h": r"k_xlines<[23]>",
-    "solve_h": r"k_col<\d+, [234],",
+    "solve_h": r"k_(?:strip|col)<\d+, [234],",
+}
+# kernels of each class in the default single-problem form
+CLASS_KERNELS = {
+    "rhs_e": "k_xlines<0|1> (Step 1 x-lines and the band table of the Hx y-lines)",
+    "solve_e": "k_strip<K, 0|1> (Step 1 y-lines, Chebyshev solve, Ez and G_E update)",
+    "rhs_h": "k_xlines<2|3> (Step 2 x-lines and the band table of the G_E y-lines)",
+    "solve_h": "k_strip<K, 2|3> + k_strip<K, 4> (Step 2 Hx and Hy solves and updates)",
 }
 
 
@@ -271,6 +278,7 @@ def main():
     traffic = measured_traffic(dom, workload_key)
     roofline = {"bound": "hbm", "achieved": round(dom_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom_ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "kernels": CLASS_KERNELS.get(dom) if args.solver == "chebyshev" else None,
                 "avg_us": round(per[dom]["avg_us"], 3),
                 "step_alg_bytes_per_cell": sum(per[c]["alg_bytes"] for c in per) / cells,
                 "per_kernel_avg_us": {c: round(v["avg_us"], 3) for c, v in per.items()}}
