@@ -15,14 +15,23 @@
 #include <string>
 #include <vector>
 
-#include "c4m_tiles_2d.h"
+#include "c4m_stream_2d.h"
 
 namespace c4m {
+
+bool strip_form_2d(int shape, bool mixed, int sweeps);
+
+// Strip shape of the batched form: the single-problem default (8 steps per
+// unrolled block, one step of prefetch), so members equal problems run
+// alone bit for bit.
+constexpr int BS_U = 8, BS_LA = 1, BS_WPE = 3;
 
 struct BatchProb {
     XArgs xe, xh;            // x-line arguments of Step 1 and Step 2
     ColArgs ce, chx, chy;    // column arguments of the three solves
     int tiles_x[5];          // tiles along x per phase
+    int xtiles[5];           // x-line phases: tiles before the band-table items
+    StripPlan plan[3];       // strip form: plans of the E, Hx and Hy solves
 };
 
 enum { PH_XE = 0, PH_CE = 1, PH_XH = 2, PH_CHX = 3, PH_CHY = 4, NPH = 5 };
@@ -96,6 +105,18 @@ __global__ __launch_bounds__(256) void k_batch_x(const BatchProb* __restrict__ b
         const int local = it - q.prefix[p];
         const int tx = bp[p].tiles_x[phase];
         const XArgs& xa = phase == PH_XE ? bp[p].xe : bp[p].xh;
+        if (local >= bp[p].xtiles[phase]) {
+            // band-table item of the following strip solve
+            const int id = local - bp[p].xtiles[phase];
+            const ColArgs& ca = phase == PH_XE ? bp[p].ce : bp[p].chx;
+            const int nbx = (xa.N + 1 + 255) / 256, nbr = band_rows(xa.L);
+            const int gx = (id % nbx) * 256 + (int)threadIdx.x, r = (id / nbx) % nbr, e = id / (nbx * nbr);
+            if (MODE == XL_H_TRACKED)
+                yband_entry<false>(ca.src, ca.yb, xa.N, xa.P, xa.L, gx, r, e);
+            else
+                yband_entry<true>(ca.src, ca.yb, xa.N, xa.P, xa.L, gx, r, e);
+            continue;
+        }
         if constexpr (MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE)
             xlines_e_tile<MODE == XL_E_TRACKED>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, local % tx, local / tx);
         else
@@ -120,6 +141,57 @@ __global__ __launch_bounds__(S::NTC) __attribute__((amdgpu_waves_per_eu(S::NL ==
         const ColArgs& ca = phase == PH_CE ? bp[p].ce : (phase == PH_CHX ? bp[p].chx : bp[p].chy);
         const PadeLine& L = phase == PH_CE ? bp[p].xe.L : bp[p].xh.L;
         col_tile<K, MODE, S, FORM>(ca, cf, taps, L, cs, local / ty, local % ty);   // y fastest
+    }
+    finish(q);
+}
+
+// Strip form: a workgroup claims four consecutive items, one per wave.
+__device__ __forceinline__ int claim4(const PhaseQueue& q, int total, int* slot)
+{
+    __syncthreads();                         // every wave has read the previous items
+    if (threadIdx.x == 0) {
+        const int per = (total + NXCD - 1) / NXCD;
+        const int home = (int)(blockIdx.x % NXCD);
+        int item = -1, cnt = 0;
+        for (int j = 0; j < NXCD && item < 0; ++j) {
+            const int c = (home + j) % NXCD;
+            const int len = min(per, total - c * per);
+            if (len <= 0) continue;
+            const int k = atomicAdd(q.ctr + c, SW_WAVES);
+            if (k < len) {
+                item = c * per + k;
+                cnt = min(SW_WAVES, len - k);
+            }
+        }
+        slot[0] = item;
+        slot[1] = cnt;
+    }
+    __syncthreads();
+    const int w = (int)(threadIdx.x / SW_COLS);
+    const int base = slot[0], cnt = slot[1];
+    if (base < 0) return -1;
+    return w < cnt ? base + w : -2;         // -2: this wave idles this round
+}
+
+template <int K, int MODE>
+__global__ __launch_bounds__(SW_COLS * SW_WAVES) __attribute__((amdgpu_waves_per_eu(BS_WPE))) void k_batch_strip(
+    const BatchProb* __restrict__ bp, PhaseQueue q, int total, int phase, Coef cf, ChebSchedule cs)
+{
+    using SS = StripShape<K, MODE, BS_U, BS_LA>;
+    __shared__ int slot[2];
+    const int k = phase == PH_CE ? 0 : (phase == PH_CHX ? 1 : 2);
+    for (;;) {
+        const int got = claim4(q, total, slot);
+        if (got == -1) break;
+        if (got < 0) continue;
+        const int it = __builtin_amdgcn_readfirstlane(got);
+        const int p = find_problem(q, it);
+        const int local = it - q.prefix[p];
+        const ColArgs& ca = k == 0 ? bp[p].ce : (k == 1 ? bp[p].chx : bp[p].chy);
+        const PadeLine& L = k == 0 ? bp[p].xe.L : bp[p].xh.L;
+        int strip, y0, tr;
+        bp[p].plan[k].item(local, strip, y0, tr);
+        strip_tile<K, MODE, BS_U, BS_LA>(ca, cf, L, cs, ca.g.lo[0] + strip * SS::OW, y0, tr);
     }
     finish(q);
 }
@@ -160,6 +232,53 @@ static int blocks_col(int K, int shape, bool mixed)
     if (mixed)
         return with_k_mixed(K, [&]<int KK, class S>() { return resident_blocks(k_batch_col<KK, MODE, S, FORM_MIXED>, S::NTC); });
     return with_k_shape(K, shape, [&]<int KK, class S>() { return resident_blocks(k_batch_col<KK, MODE, S, FORM_FP64>, S::NTC); });
+}
+
+// K (2 .. 8) as a template argument for the strip form
+template <class F>
+static auto with_k_bstrip(int K, F&& f)
+{
+    switch (K) {
+        case 2: return f.template operator()<2>();
+        case 3: return f.template operator()<3>();
+        case 4: return f.template operator()<4>();
+        case 5: return f.template operator()<5>();
+        case 6: return f.template operator()<6>();
+        case 7: return f.template operator()<7>();
+        default: return f.template operator()<8>();
+    }
+}
+
+template <int MODE>
+static int blocks_strip(int K)
+{
+    return with_k_bstrip(K, [&]<int KK>() { return resident_blocks(k_batch_strip<KK, MODE>, SW_COLS * SW_WAVES); });
+}
+
+// plan of one strip solve of a batch member (device wave slots as for a
+// problem run alone)
+template <int MODE>
+static bool batch_plan(int K, const UGrid& g, const PadeLine& L, StripPlan& plan)
+{
+    return with_k_bstrip(K, [&]<int KK>() {
+        using SS = StripShape<KK, MODE, BS_U, BS_LA>;
+        const int blocks = resident_blocks(k_batch_strip<KK, MODE>, SW_COLS * SW_WAVES);
+        int dev = 0, cus = 256;
+        if (hipGetDevice(&dev) == hipSuccess) (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        return strip_plan<SS, KK, BS_U>(g, L, blocks * SW_WAVES, cus * 4, plan);
+    });
+}
+
+template <int MODE>
+static hipError_t launch_bs(int K, hipStream_t st, int blocks, const BatchProb* bp, const PhaseQueue& q, int total,
+                            int phase, const Coef& cf, const ChebSchedule& cs)
+{
+    const int g = std::max(1, std::min(blocks, (total + SW_WAVES - 1) / SW_WAVES));
+    return with_k_bstrip(K, [&]<int KK>() {
+        hipLaunchKernelGGL((k_batch_strip<KK, MODE>), dim3(g), dim3(SW_COLS * SW_WAVES), 0, st, bp, q, total, phase, cf,
+                           cs);
+        return hipGetLastError();
+    });
 }
 
 template <int MODE>
@@ -220,6 +339,7 @@ struct c4m_batch {
     ChebSchedule cheb{};
     int blocks[NPH] = {};           // workgroups of each persistent launch
     bool owns = true;               // problems created by (and destroyed with) the batch
+    bool strips = false;            // solves in the strip form
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -271,6 +391,11 @@ c4m_status launch_step(c4m_batch* b)
                             : launch_bx<XL_E_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe);
                 break;
             case PH_CE:
+                if (b->strips) {
+                    e = tracked ? launch_bs<COL_E_TRACKED>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->cheb)
+                                : launch_bs<COL_E_DISCRETE>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->cheb);
+                    break;
+                }
                 e = tracked ? launch_bc<COL_E_TRACKED>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb)
                             : launch_bc<COL_E_DISCRETE>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb);
                 break;
@@ -279,11 +404,18 @@ c4m_status launch_step(c4m_batch* b)
                             : launch_bx<XL_H_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh);
                 break;
             case PH_CHX:
+                if (b->strips) {
+                    e = tracked ? launch_bs<COL_HX_TRACKED>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->cheb)
+                                : launch_bs<COL_HX_DISCRETE>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->cheb);
+                    break;
+                }
                 e = tracked ? launch_bc<COL_HX_TRACKED>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb)
                             : launch_bc<COL_HX_DISCRETE>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
                 break;
             default:
-                e = launch_bc<COL_HY>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->cheb);
+                e = b->strips ? launch_bs<COL_HY>(K, b->stream, nb, bp, q, tot, ph, b->coef, b->cheb)
+                              : launch_bc<COL_HY>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef,
+                                                  b->taps_xh, b->cheb);
                 break;
         }
     }
@@ -326,6 +458,17 @@ c4m_status build_tables(c4m_batch* b, char* cur)
     std::vector<int> prefix((size_t)NPH * (count + 1), 0);
     const int shape = b->base.tile_x;
     const bool mixed = b->base.precision == C4M_FP32_REFINED;
+    {
+        // the strip form when every member's workspace fits one buffer resource
+        ProblemView v0{};
+        problem_view(b->probs[0], &v0);
+        b->strips = strip_form_2d(shape, mixed, v0.cheb.sweeps);
+        for (int i = 0; i < count && b->strips; ++i) {
+            ProblemView v{};
+            problem_view(b->probs[i], &v);
+            if (!v.yband || v.used >= (size_t)0xFFFFF000u) b->strips = false;
+        }
+    }
     for (int i = 0; i < count; ++i) {
         ProblemView v{};
         problem_view(b->probs[i], &v);
@@ -340,12 +483,30 @@ c4m_status build_tables(c4m_batch* b, char* cur)
         const int K = v.cheb.sweeps;
         int tiles[NPH];
         d.tiles_x[PH_XE] = xe_tiles_x(v.line[1].n_out);
-        tiles[PH_XE] = d.tiles_x[PH_XE] * xe_tiles_y(N);
-        tiles[PH_CE] = col_tiles_k(K, shape, mixed, d.ce.g, &d.tiles_x[PH_CE]);
+        d.xtiles[PH_XE] = d.tiles_x[PH_XE] * xe_tiles_y(N);
         d.tiles_x[PH_XH] = xlines_tiles_x(v.line[0].n_out);
-        tiles[PH_XH] = d.tiles_x[PH_XH] * xlines_tiles_y(N);
-        tiles[PH_CHX] = col_tiles_k(K, shape, mixed, d.chx.g, &d.tiles_x[PH_CHX]);
-        tiles[PH_CHY] = col_tiles_k(K, shape, mixed, d.chy.g, &d.tiles_x[PH_CHY]);
+        d.xtiles[PH_XH] = d.tiles_x[PH_XH] * xlines_tiles_y(N);
+        tiles[PH_XE] = d.xtiles[PH_XE];
+        tiles[PH_XH] = d.xtiles[PH_XH];
+        if (b->strips) {
+            d.ce.yb = d.chx.yb = d.chy.yb = v.yband;
+            const int nbx = (N + 1 + 255) / 256;
+            tiles[PH_XE] += nbx * band_rows(v.line[1]) * 2;
+            tiles[PH_XH] += nbx * band_rows(v.line[0]) * 2;
+            bool ok = tracked ? batch_plan<COL_E_TRACKED>(K, d.ce.g, v.line[1], d.plan[0])
+                              : batch_plan<COL_E_DISCRETE>(K, d.ce.g, v.line[1], d.plan[0]);
+            ok = ok && (tracked ? batch_plan<COL_HX_TRACKED>(K, d.chx.g, v.line[0], d.plan[1])
+                                : batch_plan<COL_HX_DISCRETE>(K, d.chx.g, v.line[0], d.plan[1]));
+            ok = ok && batch_plan<COL_HY>(K, d.chy.g, v.line[0], d.plan[2]);
+            if (!ok) return set_error(C4M_EINVAL, "no strip plan for a batch member");
+            tiles[PH_CE] = d.plan[0].items();
+            tiles[PH_CHX] = d.plan[1].items();
+            tiles[PH_CHY] = d.plan[2].items();
+        } else {
+            tiles[PH_CE] = col_tiles_k(K, shape, mixed, d.ce.g, &d.tiles_x[PH_CE]);
+            tiles[PH_CHX] = col_tiles_k(K, shape, mixed, d.chx.g, &d.tiles_x[PH_CHX]);
+            tiles[PH_CHY] = col_tiles_k(K, shape, mixed, d.chy.g, &d.tiles_x[PH_CHY]);
+        }
         for (int ph = 0; ph < NPH; ++ph)
             prefix[(size_t)ph * (count + 1) + i + 1] = prefix[(size_t)ph * (count + 1) + i] + tiles[ph];
         if (i == 0) {
@@ -360,10 +521,16 @@ c4m_status build_tables(c4m_batch* b, char* cur)
         const bool tracked = b->base.lap_mode == C4M_LAP_TRACKED;
         const int K = b->cheb.sweeps;
         b->blocks[PH_XE] = tracked ? blocks_x<XL_E_TRACKED>() : blocks_x<XL_E_DISCRETE>();
-        b->blocks[PH_CE] = tracked ? blocks_col<COL_E_TRACKED>(K, shape, mixed) : blocks_col<COL_E_DISCRETE>(K, shape, mixed);
         b->blocks[PH_XH] = tracked ? blocks_x<XL_H_TRACKED>() : blocks_x<XL_H_DISCRETE>();
-        b->blocks[PH_CHX] = tracked ? blocks_col<COL_HX_TRACKED>(K, shape, mixed) : blocks_col<COL_HX_DISCRETE>(K, shape, mixed);
-        b->blocks[PH_CHY] = blocks_col<COL_HY>(K, shape, mixed);
+        if (b->strips) {
+            b->blocks[PH_CE] = tracked ? blocks_strip<COL_E_TRACKED>(K) : blocks_strip<COL_E_DISCRETE>(K);
+            b->blocks[PH_CHX] = tracked ? blocks_strip<COL_HX_TRACKED>(K) : blocks_strip<COL_HX_DISCRETE>(K);
+            b->blocks[PH_CHY] = blocks_strip<COL_HY>(K);
+        } else {
+            b->blocks[PH_CE] = tracked ? blocks_col<COL_E_TRACKED>(K, shape, mixed) : blocks_col<COL_E_DISCRETE>(K, shape, mixed);
+            b->blocks[PH_CHX] = tracked ? blocks_col<COL_HX_TRACKED>(K, shape, mixed) : blocks_col<COL_HX_DISCRETE>(K, shape, mixed);
+            b->blocks[PH_CHY] = blocks_col<COL_HY>(K, shape, mixed);
+        }
         const int mult = b->base.tile_y > 0 ? b->base.tile_y : 1;   // persistent grid multiplier
         for (int ph = 0; ph < NPH; ++ph) b->blocks[ph] *= mult;
     }

@@ -953,6 +953,8 @@ c4m_status problem_view(c4m_problem* p, ProblemView* v)
     for (int i = 0; i < 6; ++i) v->f[i] = p->f[i];
     for (int i = 0; i < 3; ++i) v->ge[i] = p->ge[i];
     for (int i = 0; i < 5; ++i) v->tmp[i] = p->tmp[i];
+    v->yband = p->yband;
+    v->used = p->used;
     v->N = p->N;
     v->P = p->P;
     for (int k = 0; k < 2; ++k) {

@@ -149,6 +149,8 @@ struct ProblemView {
     double* f[6];
     double* ge[3];
     double* tmp[5];
+    double* yband;        // 2D band table of the strip form
+    size_t used;          // workspace bytes in use (one buffer resource must span them)
     int N, P;
     PadeLine line[2];
     PadeTaps taps[2];

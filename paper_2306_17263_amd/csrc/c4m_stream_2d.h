@@ -456,7 +456,12 @@ __device__ __forceinline__ void strip_tile(const ColArgs& a, const Coef& cf, con
 // resident wave slots).
 constexpr double STRIP_COST[3] = {1.0, 1.3, 1.9};
 constexpr int STRIP_FILL_STEPS = 6;
-constexpr double STRIP_WAVES_PER_SIMD = 3.0;
+// (measured at N = 2048: two waves for the Step 1 strips, three for Step 2)
+template <class SS>
+constexpr double strip_waves_per_simd()
+{
+    return SS::ESTEP ? 2.0 : 3.0;
+}
 template <class SS, int K, int U>
 inline bool strip_plan(const UGrid& g, const PadeLine& L, int slots, int simds, StripPlan& plan)
 {
@@ -509,7 +514,7 @@ inline bool strip_plan(const UGrid& g, const PadeLine& L, int slots, int simds, 
         }
         if (!ok) continue;
         const int rounds = (items + slots - 1) / slots;
-        const double per_round = total / rounds / (simds * STRIP_WAVES_PER_SIMD);
+        const double per_round = total / rounds / (simds * strip_waves_per_simd<SS>());
         const double make = rounds * (worst > per_round ? worst : per_round);
         if (best_t == 0.0 || make < best_make) {
             best_t = t;

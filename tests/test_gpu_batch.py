@@ -36,9 +36,9 @@ def test_batch_equals_alone_and_oracle(lap, closure):
     b.step(5)                                      # the graph is replayed across calls
     names = ["ez", "hx", "hy"]
     for p, s, init in zip(b.problems, specs, inits):
-        # the batched form runs the column-tile kernels: bitwise equal to a
-        # problem run alone with the 128 x 4 column tiles (tile_x 3)
-        alone = Problem(2, s["n"], 0.5, stream=st, closure=closure, lap_mode=lap, tile_x=3)
+        # the batched form runs the single-problem kernels (the strip form by
+        # default): bitwise equal to the problem run alone
+        alone = Problem(2, s["n"], 0.5, stream=st, closure=closure, lap_mode=lap)
         for name in alone.fields():
             alone.set(name, init[name])
         alone.step(steps)
@@ -63,7 +63,7 @@ def test_batch_rejects_mixed_settings():
         Batch([{"n": 16, "cfl": 0.5}, {"n": 20, "cfl": 0.4}])
 
 
-@pytest.mark.parametrize("shape,mult", [(1, 1), (2, 2), (0, 3)])
+@pytest.mark.parametrize("shape,mult", [(1, 1), (2, 2), (0, 3), (3, 1)])
 def test_batch_shapes_and_grid(shape, mult):
     import torch
     from paper_2306_17263_amd import Batch

@@ -19,9 +19,7 @@ def test_served_results_equal_alone():
     assert out["completed"] == len(reqs)
     st = torch.cuda.Stream()
     for r in out["done"]:
-        # 2D members are served through the batched form (column tiles):
-        # bitwise equal to a problem run alone with those tiles (tile_x 3)
-        p = Problem(r.dim, r.n, r.r, stream=st, tile_x=3 if r.dim == 2 else 0)
+        p = Problem(r.dim, r.n, r.r, stream=st)
         h = 1.0 / r.n
         for name, v in mode_fields(r.dim, r.n, r.k, 0.0, r.r * h / 2, amp=r.amp).items():
             if name in p.fields():
