@@ -190,8 +190,9 @@ __global__ __launch_bounds__(SW_COLS * SW_WAVES) __attribute__((amdgpu_waves_per
         const ColArgs& ca = k == 0 ? bp[p].ce : (k == 1 ? bp[p].chx : bp[p].chy);
         const PadeLine& L = k == 0 ? bp[p].xe.L : bp[p].xh.L;
         int strip, y0, tr;
-        bp[p].plan[k].item(local, strip, y0, tr);
-        strip_tile<K, MODE, BS_U, BS_LA>(ca, cf, L, cs, ca.g.lo[0] + strip * SS::OW, y0, tr);
+        bool up;
+        bp[p].plan[k].item(local, strip, y0, tr, up);
+        strip_tile<K, MODE, BS_U, BS_LA>(ca, cf, L, cs, ca.g.lo[0] + strip * SS::OW, y0, tr, up);
     }
     finish(q);
 }

@@ -80,8 +80,9 @@ __global__ __launch_bounds__(SW_COLS * SW_WAVES) __attribute__((amdgpu_waves_per
     const int item = l * SW_WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / SW_COLS));
     if (item >= items) return;
     int strip, y0, tr;
-    plan.item(item, strip, y0, tr);
-    strip_tile<K, MODE, U, LA>(a, cf, L, cs, a.g.lo[0] + strip * SS::OW, y0, tr);
+    bool up;
+    plan.item(item, strip, y0, tr, up);
+    strip_tile<K, MODE, U, LA>(a, cf, L, cs, a.g.lo[0] + strip * SS::OW, y0, tr, up);
 }
 
 // Whether a 2D single-problem solve takes the strip form (the host then

@@ -150,7 +150,7 @@ __host__ __device__ inline StripSpan strip_span(const ColArgs& a)
 // the buffer range check.
 template <int K, int MODE, int U, int LA, bool XB, bool YB, int UU>
 __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, const PadeLine& L,
-                                          const ChebSchedule& cs, int x0, int y0, const int TR)
+                                          const ChebSchedule& cs, int x0, int y0, const int TR, const bool rev)
 {
     using SS = StripShape<K, MODE, U, LA>;
     constexpr bool YPART = SS::YPART, SPLIT = SS::SPLIT, HAS_T0 = SS::HAS_T0, CARRY = SS::CARRY;
@@ -168,10 +168,20 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
     const bool mlo = XB && nx && gx == g.lo[0], mhi = XB && nx && gx == g.hi[0] - 1;
     const bool lane_out = lane >= HX && lane < SW_COLS - HX && col_active;
     const int ylo = g.lo[1], yhi = g.hi[1];
-    const int ry0 = y0 - K;                             // grid row of region row 0
+    const int ry0 = y0 - K;                             // grid row of the region's first row
     const int mofs = SS::ESTEP ? 1 : 0;                 // grid row = Pade output index + mofs
-    const int mbase = ry0 - mofs;                       // Pade output index of region row 0
-    const int gbase = mbase - (SW_WIN / 2 - 1);         // raw row in window slot 0 at region row 0
+    // Walking direction: down (rev false) or up.  Step ry takes region row
+    // ry from the walking start; rows behind in walking order are above
+    // (down) or below (up).  Segments of a strip alternate, so the rows
+    // two neighbouring segments share are read by both at about the same
+    // time (both at their starts or both at their ends).
+    const int dir = rev ? -1 : 1;
+    const int gy0 = rev ? ry0 + TR - 1 : ry0;          // grid row of step 0
+    const int mfirst = gy0 - mofs;                      // its Pade output index
+    // window slot i after the load of step ry holds raw row wbase + dir (ry + i);
+    // the pair form over slots 0..25 is dir P(m + dir), m = mfirst + dir ry
+    const int wbase = rev ? mfirst + (SW_WIN / 2 - 2) : mfirst - (SW_WIN / 2 - 3);
+    const double psg = rev ? -1.0 : 1.0;
     const int n_in = L.n_in, n_out = L.n_out;
 
     // one buffer over every array of the strip (their span stays below
@@ -207,18 +217,19 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
         return (m >= 0 && m < n_out && col_data) ? v : 0.0;
     };
     auto row_in = [&](int gy) -> bool { return !YB || (gy >= ylo && gy < yhi); };
-    auto out_row = [&](int ry) -> bool {   // step ry updates grid row ry0 + ry - K
-        return ry >= 2 * K && ry < TR && (!YB || ry0 + ry - K < yhi);
+    auto grow = [&](int ry) -> int { return gy0 + dir * ry; };   // grid row of step ry
+    auto out_row = [&](int ry) -> bool {   // step ry updates grid row grow(ry) - dir K
+        return ry >= 2 * K && ry < TR && (!YB || grow(ry) - dir * K < yhi);
     };
-    // per-row inputs: t0 of region row ry; field, G_E and t1 of the output
-    // row that leaves the pipeline at step ry (rows clamped into the valid
-    // range: values of other rows are never used)
+    // per-row inputs: t0 of the row of step ry; field, G_E and t1 of the
+    // output row that leaves the pipeline at step ry (rows clamped into the
+    // valid range: values of other rows are never used)
     auto prefetch = [&](int ry, double& t0v, double& fv, double& gv, double& t1v) {
         const int rt = ry < TR ? ry : TR - 1;
-        const int gyt = YB ? clampi(ry0 + rt, ylo, yhi - 1) : ry0 + rt;
+        const int gyt = YB ? clampi(grow(rt), ylo, yhi - 1) : grow(rt);
         t0v = HAS_T0 ? buf_ld_s(rb, laneb, dt0 + (unsigned)gyt * rowb) : 0.0;
         const int ro = rt < 2 * K ? 2 * K : rt;
-        const int gyo = YB ? clampi(ry0 + ro - K, ylo, yhi - 1) : ry0 + ro - K;
+        const int gyo = YB ? clampi(grow(ro) - dir * K, ylo, yhi - 1) : grow(ro) - dir * K;
         const unsigned so = (unsigned)gyo * rowb;
         fv = buf_ld_s(rb, laneb, dfield + so);
         gv = CARRY ? buf_ld_s(rb, laneb, dge + so) : 0.0;
@@ -226,7 +237,7 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
     };
 
     // ---- state
-    double fw[NW];                 // raw window: slot i holds raw row gbase + W0 + ry + i
+    double fw[NW];                 // raw window (see wbase)
     double t0q[NQ], fq[NQ], gq[NQ], t1q[NQ];
     double pd[K + 1];              // raw Pade derivative of the last K + 1 rows
     double dp1[K], dp2[K], rp1[K], xp1[K];
@@ -236,7 +247,7 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
     for (int j = 0; j <= K; ++j) pd[j] = 0.0;
     if (YPART) {
 #pragma unroll
-        for (int i = W0 ? 0 : 1; i < NW; ++i) fw[i] = load_raw(gbase + W0 - 1 + i);
+        for (int i = W0 ? 0 : 1; i < NW; ++i) fw[i] = load_raw(wbase + dir * (i - 1));
     }
 #pragma unroll
     for (int i = 1; i < NQ; ++i) prefetch(i - 1, t0q[i], fq[i], gq[i], t1q[i]);
@@ -253,16 +264,16 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
         }
         return p0 + p1;
     };
-    // raw derivatives of the rows mbase - 1 and mbase before step 0 (fw[i]
-    // holds row mbase - 12 + i)
+    // raw derivatives of the rows mfirst - dir and mfirst before step 0
+    // (fw[i] holds row wbase + dir (i - 1))
     double pm1 = 0.0, pm0 = 0.0;
     if (YPART) {
-        const double extra = load_raw(mbase - PADE_R - 1);
-        pm1 = fir_pair([&](int i) { return i == 0 ? extra : fw[i - 1]; });
-        pm0 = fir_pair([&](int i) { return fw[i]; });
+        const double extra = load_raw(wbase - 2 * dir);
+        pm1 = psg * fir_pair([&](int i) { return i == 0 ? extra : fw[i - 1]; });
+        pm0 = psg * fir_pair([&](int i) { return fw[i]; });
         if (YB) {
-            pm1 = in_band(mbase - 1) ? band(0, mbase - 1) : pm1;
-            pm0 = in_band(mbase) ? band(0, mbase) : pm0;
+            pm1 = in_band(mfirst - dir) ? band(0, mfirst - dir) : pm1;
+            pm0 = in_band(mfirst) ? band(0, mfirst) : pm0;
         }
     }
 
@@ -274,7 +285,7 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
             if (YPART) {
 #pragma unroll
                 for (int i = 0; i < NW - 1; ++i) fw[i] = fw[i + 1];
-                fw[NW - 1] = load_raw(gbase + W0 + ry + NW - 1);
+                fw[NW - 1] = load_raw(wbase + dir * (ry + NW - 1));
             }
 #pragma unroll
             for (int i = 0; i < NQ - 1; ++i) {
@@ -285,15 +296,15 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
             }
             prefetch(ry + LA, t0q[NQ - 1], fq[NQ - 1], gq[NQ - 1], t1q[NQ - 1]);
 
-            // ---- line derivatives of Pade row m = mbase + ry: raw (pr) and of
-            // the conditioned source (cr).  The conditioning along the line
+            // ---- line derivatives of Pade row m = mfirst + dir ry: raw (pr) and
+            // of the conditioned source (cr).  The conditioning along the line
             // commutes with the interior (Toeplitz) rows, so there
             // R(m) = alpha P(m) + (P(m-1) + P(m+1) - 2 P(m)) / 12.
             double pr = 0.0, cr = 0.0;
             if (YPART) {
-                const int m = mbase + ry;
-                double pp1 = fir_pair([&](int i2) { return fw[i2]; });
-                if (YB) pp1 = in_band(m + 1) ? band(0, m + 1) : pp1;
+                const int m = mfirst + dir * ry;
+                double pp1 = psg * fir_pair([&](int i2) { return fw[i2]; });
+                if (YB) pp1 = in_band(m + dir) ? band(0, m + dir) : pp1;
                 pr = pm0;
                 if (SPLIT) {
                     cr = fma(cf.alpha, pm0, (pm1 + pp1 - 2.0 * pm0) * (1.0 / 12.0));
@@ -305,8 +316,8 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
                 pm0 = pp1;
             }
 
-            // ---- right-hand side of region row ry
-            const int gy = ry0 + ry;
+            // ---- right-hand side of the row of step ry
+            const int gy = grow(ry);
             double b;
             {
                 double v = 0.0;
@@ -324,18 +335,20 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
                 pd[K] = pr;
             }
 
-            // ---- Chebyshev pipeline: application j + 1 on row ry - j - 1
+            // ---- Chebyshev pipeline: application j + 1 on the row j + 1 steps behind
             double dn[K + 1], rn[K + 1], xn[K + 1];
             dn[0] = b * cs.inv_theta;
             rn[0] = b;
             xn[0] = 0.0;
 #pragma unroll
             for (int j = 0; j < K; ++j) {
-                const int gq_ = gy - j - 1;
+                const int gq_ = gy - dir * (j + 1);
+                // older row (dp2) and newer row (dn): above and below when
+                // walking down, below and above when walking up
                 double up = dp2[j], cen = dp1[j], dw = dn[j];
                 if (YB) {
-                    up = (ny && gq_ == ylo) ? cen : up;
-                    dw = (ny && gq_ == yhi - 1) ? cen : dw;
+                    up = (ny && gq_ == (rev ? yhi - 1 : ylo)) ? cen : up;
+                    dw = (ny && gq_ == (rev ? ylo : yhi - 1)) ? cen : dw;
                 }
                 const double sown = fma(4.0, cen, up + dw);
                 double sl = from_left(sown), sr = from_right(sown);
@@ -363,10 +376,10 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
                 xp1[j] = xn[j];
             }
 
-            // ---- update of grid row gy - K (other lanes and rows: BUF_NULL)
+            // ---- update of grid row gy - dir K (other lanes and rows: BUF_NULL)
             {
                 const bool ok = out_row(ry) && lane_out;
-                const unsigned row = (unsigned)(gy - K) * rowb + laneb;
+                const unsigned row = (unsigned)(gy - dir * K) * rowb + laneb;
                 const double de = cf.cfl * (xn[K] + dn[K]);
                 buf_st(rb, ok ? dfield + row : BUF_NULL, fq[0] + de);
                 if (CARRY)
@@ -390,8 +403,10 @@ __host__ __device__ inline int strip_variant(const UGrid& g, const PadeLine& L, 
     bool yin = ry0 > g.lo[1] && ry0 + tr < g.hi[1];
     if (SS::YPART) {
         const int m_lo = ry0 - mofs, m_hi = ry0 - mofs + tr - 1;
-        yin = yin && !L.all && m_lo - 2 >= L.b && m_hi + 2 < L.n_out - L.b && m_lo - SW_WIN / 2 >= 0 &&
-              m_hi + SW_WIN / 2 + SS::NW - SW_WIN < L.n_in;
+        // (either walking direction: the window reaches 14 rows plus the
+        // prefetch beyond the region on one side)
+        yin = yin && !L.all && m_lo - 2 >= L.b && m_hi + 2 < L.n_out - L.b &&
+              m_lo - SW_WIN / 2 - (SS::NW - SW_WIN) >= 0 && m_hi + SW_WIN / 2 + SS::NW - SW_WIN < L.n_in;
     }
     return !yin ? 2 : (!xin ? 1 : 0);
 }
@@ -413,8 +428,9 @@ struct StripPlan {
     {
         return (xa + xb) * nseg[0] + (strips - xa - xb) * nseg[1];
     }
-    // strip index, output row and region rows of item it
-    __host__ __device__ void item(int it, int& strip, int& y0v, int& trv) const
+    // strip index, output row, region rows and walking direction (odd
+    // segments walk up) of item it
+    __host__ __device__ void item(int it, int& strip, int& y0v, int& trv, bool& up) const
     {
         const int ix = (xa + xb) * nseg[0];
         int t, k, sg;
@@ -432,21 +448,22 @@ struct StripPlan {
         }
         y0v = y0[t][sg];
         trv = tr[t][sg];
+        up = (sg & 1) != 0;
     }
 };
 
 template <int K, int MODE, int U, int LA>
 __device__ __forceinline__ void strip_tile(const ColArgs& a, const Coef& cf, const PadeLine& L,
-                                           const ChebSchedule& cs, int x0, int y0, int tr)
+                                           const ChebSchedule& cs, int x0, int y0, int tr, bool up)
 {
     using SS = StripShape<K, MODE, U, LA>;
     const int v = strip_variant<SS, K>(a.g, L, x0, y0, tr);
     if (v == 0)
-        strip_run<K, MODE, U, LA, false, false, U>(a, cf, L, cs, x0, y0, tr);
+        strip_run<K, MODE, U, LA, false, false, U>(a, cf, L, cs, x0, y0, tr, up);
     else if (v == 1)
-        strip_run<K, MODE, U, LA, true, false, U>(a, cf, L, cs, x0, y0, tr);
+        strip_run<K, MODE, U, LA, true, false, U>(a, cf, L, cs, x0, y0, tr, up);
     else
-        strip_run<K, MODE, U, LA, true, true, U>(a, cf, L, cs, x0, y0, tr);
+        strip_run<K, MODE, U, LA, true, true, U>(a, cf, L, cs, x0, y0, tr, up);
 }
 
 // Cost model of the plan: work per step of the three forms, the window
