@@ -68,3 +68,47 @@ def test_strip_matches_tiles_large():
     for shape in (0, 4):
         assert rel_l2_all(out[shape], out[3], EH) <= 1e-13, shape
         assert rel_l2(out[shape]["lz"], out[3]["lz"]) <= 1e-10
+
+
+def test_strip_many_rounds_large_grid():
+    # N = 8192: the strip plan needs several rounds of the resident wave
+    # slots; one step against the 128 x 4 column tiles
+    from paper_2306_17263_amd import Problem
+    n = 8192
+    rng = np.random.default_rng(8192)
+    init = None
+    out = {}
+    for shape in (3, 0):
+        p = Problem(2, n, 0.5, tile_x=shape)
+        if init is None:
+            init = {a: rng.normal(size=p.shape(a)) for a in p.fields()}
+        for name in p.fields():
+            p.set(name, init[name])
+        p.step(1)
+        out[shape] = {a: p.get(a) for a in EH}
+        p.close()
+    assert rel_l2_all(out[0], out[3], EH) <= 1e-13
+
+
+def test_batch_random_data_equals_alone():
+    # seeded random fields (every operator mode), strips in the batch
+    # against the same problems alone, bit for bit
+    import torch
+    from paper_2306_17263_amd import Batch, Problem
+    ns = [8, 21, 50, 77, 130, 257]
+    st = torch.cuda.Stream()
+    b = Batch([{"n": n} for n in ns], stream=st, closure="paper", lap_mode="tracked")
+    inits = [initial_fields(2, n, 0.5, seed=40 + n) for n in ns]
+    for p, init in zip(b.problems, inits):
+        for name in p.fields():
+            p.set(name, init[name])
+    b.step(5)
+    for p, n, init in zip(b.problems, ns, inits):
+        q = Problem(2, n, 0.5, stream=st, closure="paper", lap_mode="tracked")
+        for name in q.fields():
+            q.set(name, init[name])
+        q.step(5)
+        for a in EH:
+            assert np.array_equal(p.get(a), q.get(a)), (n, a)
+        q.close()
+    b.close()
