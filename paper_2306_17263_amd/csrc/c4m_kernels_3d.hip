@@ -32,33 +32,41 @@ __device__ __forceinline__ const double* pade_row3(const PadeLine& L, int m)
     return L.rows + (size_t)(2 * L.b) * PADE_TAPS;   // the interior taps, stored after the boundary rows
 }
 
-// Source value at stored index q (q[D] may run outside the line: zero).
-// SRC_G: alpha u + (sum of second differences)/12 with even ghosts along
-// half axes (node axes are interior here); SRC_GE_DISCRETE: the same on E,
-// zero on E's node walls.
+// Source value at stored index q (q[D] may run outside the line: zero; ok
+// false: zero).  SRC_G: alpha u + (sum of second differences)/12 with even
+// ghosts along half axes (node axes are interior here); SRC_GE_DISCRETE: the
+// same on E, zero on E's node walls.  Every load takes an index clamped into
+// the stored box and the value is selected at the end, so a caller can have
+// the loads of several values in flight at once.
 template <int MODE>
-__device__ __forceinline__ double src_value(const Term3& t, int i, int j, int k, double alpha)
+__device__ __forceinline__ double src_value(const Term3& t, int i, int j, int k, double alpha, bool ok)
 {
     const Box& b = t.sb;
-    if (i < 0 || j < 0 || k < 0 || i >= b.n[0] || j >= b.n[1] || k >= b.n[2]) return 0.0;
-    const double* p = t.src + k * t.plane + (size_t)j * t.P + i;
-    if (MODE == SRC_RAW || MODE == SRC_GE_STORED) return p[0];
     const int q[3] = {i, j, k};
-    const size_t st[3] = {1, (size_t)t.P, t.plane};
+    int c[3];
+    bool in = ok;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        in = in && q[d] >= 0 && q[d] < b.n[d];
+        c[d] = q[d] < 0 ? 0 : (q[d] >= b.n[d] ? b.n[d] - 1 : q[d]);
+    }
+    const double* p = t.src + c[2] * t.plane + (size_t)c[1] * t.P + c[0];
+    const double u0 = p[0];
+    if (MODE == SRC_RAW || MODE == SRC_GE_STORED) return in ? u0 : 0.0;
+    const long st[3] = {1, (long)t.P, (long)t.plane};
     if (MODE == SRC_GE_DISCRETE) {
 #pragma unroll
         for (int d = 0; d < 3; ++d)
-            if (!b.half[d] && (q[d] == 0 || q[d] == b.n[d] - 1)) return 0.0;
+            if (!b.half[d]) in = in && c[d] != 0 && c[d] != b.n[d] - 1;
     }
-    const double u0 = p[0];
     double lap = 0.0;
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
-        const double um = q[d] == 0 ? u0 : p[-(long)st[d]];          // even ghost (half axis)
-        const double up = q[d] == b.n[d] - 1 ? u0 : p[st[d]];
+        const double um = p[c[d] == 0 ? 0 : -st[d]];                 // even ghost (half axis)
+        const double up = p[c[d] == b.n[d] - 1 ? 0 : st[d]];
         lap += um + up - 2.0 * u0;
     }
-    return fma(alpha, u0, lap * (1.0 / 12.0));
+    return in ? fma(alpha, u0, lap * (1.0 / 12.0)) : 0.0;
 }
 
 constexpr int T3_SEG = 8;
@@ -80,21 +88,35 @@ __global__ __launch_bounds__(256) void k_term3(Term3 t, double alpha, PadeTaps t
     const int s = t.tg.lo[SX] + blockIdx.z;               // slab index
     const int tid = threadIdx.x;
     const int n_in = L.n_in;
-    for (int e = tid; e < A * BW; e += 256) {
-        int a, q;
-        if (D == 0) { a = e / BW; q = e - a * BW; }       // consecutive threads along the line (x)
-        else { q = e / A; a = e - q * A; }                // consecutive threads across lines (x)
-        const int wi = w0 + a;
-        const int g = m0 - PADE_R + q;
-        double v = 0.0;
-        if (wi < t.tg.hi[W] && g >= 0 && g < n_in) {
+    // staging in chunks of CH elements per thread, the loads of a chunk all
+    // in flight before its LDS stores
+    constexpr int NS = (A * BW + 255) / 256;
+    constexpr int CH = (MODE == SRC_RAW || MODE == SRC_GE_STORED) ? NS : 4;
+    for (int i0 = 0; i0 < NS; i0 += CH) {
+        double v[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int e = tid + (i0 + c) * 256;
+            int a, q;
+            if (D == 0) { a = e / BW; q = e - a * BW; }   // consecutive threads along the line (x)
+            else { q = e / A; a = e - q * A; }            // consecutive threads across lines (x)
+            const int wi = w0 + a;
+            const int g = m0 - PADE_R + q;
+            const bool ok = i0 + c < NS && e < A * BW && wi < t.tg.hi[W] && g >= 0 && g < n_in;
             int idx[3];
             idx[D] = g;
             idx[W] = wi;
             idx[SX] = s;
-            v = src_value<MODE>(t, idx[0], idx[1], idx[2], alpha);
+            v[c] = src_value<MODE>(t, idx[0], idx[1], idx[2], alpha, ok);
         }
-        sv[a * BS + q] = v;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int e = tid + (i0 + c) * 256;
+            int a, q;
+            if (D == 0) { a = e / BW; q = e - a * BW; }
+            else { q = e / A; a = e - q * A; }
+            if (i0 + c < NS && e < A * BW) sv[a * BS + q] = v[c];
+        }
     }
     __syncthreads();
     // thread -> (line a, segment): lanes of a half-wave take consecutive lines
@@ -232,23 +254,55 @@ __global__ __launch_bounds__(256) void k_cheb3t(Cheb3T<TX, TB> a)
     const int z1 = min(z0 + C3_CZ, a.g.hi[2]);
     const bool own = i < a.g.hi[0] && j < a.g.hi[1];
     const TC scale = FIRST ? TC(a.inv_theta) : TC(1);
-    auto load = [&](int z) {
-        TC* buf = ring[z & 3];
-        for (int e = tid; e < C3_PL; e += 256) {
+    // Planes of the iterate (with the halo) pass through registers into the
+    // LDS ring: the loads of plane z + 2 are issued in the iteration of plane
+    // z and stored to the ring in the next one.  Loads take clamped (valid)
+    // indices and the value is selected after.
+    constexpr int NL = (C3_PL + 255) / 256;
+    auto fetch = [&](int z, TC (&r)[NL]) {
+#pragma unroll
+        for (int c = 0; c < NL; ++c) {
+            const int e = tid + c * 256;
             const int ly = e / C3_LX, lx = e - ly * C3_LX;
-            const long q = rule_index(a.g, a.P, a.plane, bx + lx - 1, by + ly - 1, z);
-            TC v = TC(0);
-            if (q >= 0) v = FIRST ? TC(a.b[q]) * scale : TC(a.xk[q]);
-            buf[e] = v;
+            const long q = e < C3_PL ? rule_index(a.g, a.P, a.plane, bx + lx - 1, by + ly - 1, z) : -1;
+            const long qc = q < 0 ? 0 : q;
+            const TC v = FIRST ? TC(a.b[qc]) * scale : TC(a.xk[qc]);
+            r[c] = q >= 0 ? v : TC(0);
         }
     };
-    load(z0 - 1);
-    load(z0);
+    auto put = [&](int z, const TC (&r)[NL]) {
+        TC* buf = ring[z & 3];
+#pragma unroll
+        for (int c = 0; c < NL; ++c) {
+            const int e = tid + c * 256;
+            if (e < C3_PL) buf[e] = r[c];
+        }
+    };
+    TC ra[NL], rb[NL];
+    fetch(z0 - 1, ra);
+    fetch(z0, rb);
+    put(z0 - 1, ra);
+    put(z0, rb);
+    fetch(z0 + 1, ra);
     const TC alpha = TC(a.cf.alpha), b6 = TC(a.cf.beta * (1.0 / 6.0));
     const TC c1 = TC(a.c1), c2 = TC(a.c2);
     const int c0 = (ty + 1) * C3_LX + tx + 1;
     for (int z = z0; z < z1; ++z) {
-        load(z + 1);
+        // the thread's own operands of plane z (index 0 for lanes outside)
+        const size_t o = own ? (size_t)z * a.plane + (size_t)j * a.P + i : 0;
+        const TC bv = TC(a.b[o]);
+        // x_{k-1}: zero in the first pass, b / theta in the second
+        const TC xp = (FIRST || OUT == C3_RESID) ? TC(0) : (a.xkm1 ? TC(a.xkm1[o]) : bv * TC(a.inv_theta));
+        double fv = 0.0, gv = 0.0, cv = 0.0, av = 0.0;
+        if (OUT == C3_FIELD) {
+            fv = a.field[o];
+            gv = a.ge ? a.ge[o] : 0.0;
+            cv = a.ge ? a.cur[o] : 0.0;
+            av = a.xadd ? (double)a.xadd[o] : 0.0;
+        }
+        // ring slot (z + 1) & 3 was last read in the iteration of plane z - 2
+        put(z + 1, ra);
+        if (z + 2 <= z1) fetch(z + 2, ra);
         __syncthreads();
         if (own) {
             const TC* pm = ring[(z - 1) & 3];
@@ -262,19 +316,15 @@ __global__ __launch_bounds__(256) void k_cheb3t(Cheb3T<TX, TB> a)
                              pm[c0 - 1] + pm[c0 + 1] + pm[c0 - C3_LX] + pm[c0 + C3_LX] + pp[c0 - 1] + pp[c0 + 1] +
                              pp[c0 - C3_LX] + pp[c0 + C3_LX];
             const TC mx = fma(alpha, xc, -b6 * (TC(2) * faces + edges - TC(24) * xc));
-            const size_t o = (size_t)z * a.plane + (size_t)j * a.P + i;
             if (OUT == C3_RESID) {
-                a.rout[o] = (float)(TC(a.b[o]) - mx);
+                a.rout[o] = (float)(bv - mx);
             } else {
-                const TC bv = TC(a.b[o]);
-                // x_{k-1}: zero in the first pass, b / theta in the second
-                const TC xp = FIRST ? TC(0) : (a.xkm1 ? TC(a.xkm1[o]) : TC(a.b[o]) * TC(a.inv_theta));
                 const TC xn = xc + fma(c1, xc - xp, c2 * (bv - mx));
                 if (OUT == C3_FIELD) {
-                    const double phi = (double)xn + (a.xadd ? (double)a.xadd[o] : 0.0);
+                    const double phi = (double)xn + av;
                     const double de = a.cf.cfl * phi;
-                    a.field[o] += de;
-                    if (a.ge) a.ge[o] += fma(a.cf.ge_gain, de, -a.cf.ge_curl * a.cur[o]);
+                    a.field[o] = fv + de;
+                    if (a.ge) a.ge[o] = gv + fma(a.cf.ge_gain, de, -a.cf.ge_curl * cv);
                 } else {
                     a.xout[o] = (TX)xn;
                 }

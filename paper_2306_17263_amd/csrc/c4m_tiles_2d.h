@@ -91,35 +91,53 @@ __device__ __forceinline__ void xlines_tile(const double* __restrict__ src, doub
     const int m0 = bxi * XT_OUT;                    // first output of the tile
     const int j0 = 1 + byi * XT_ROWS;               // first row (interior rows 1..N-1)
     const int n_in = L.n_in;
-    // ---- stage the conditioned line input (and the raw one)
-    for (int e = tid; e < XT_ROWS * XT_IN; e += 256) {
-        const int rr = e / XT_IN, q = e - rr * XT_IN;
-        const int j = j0 + rr, g = m0 - PADE_R + q;
-        double vg = 0.0, vr = 0.0;
-        if (j <= N - 1 && g >= 0 && g < n_in) {
-            const double* row = src + (size_t)j * P;
+    // ---- stage the conditioned line input (and the raw one).  Chunks of CH
+    // elements per thread: the loads of a chunk take clamped (valid)
+    // addresses and are all issued before its LDS stores.
+    constexpr int NS = (XT_ROWS * XT_IN + 255) / 256;
+    constexpr int CH = MODE == XL_H_TRACKED ? NS : 4;
+    for (int i0 = 0; i0 < NS; i0 += CH) {
+        double vg[CH], vr[CH];
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int e = tid + (i0 + c) * 256;
+            const int rr = e / XT_IN, q = e - rr * XT_IN;
+            const int j = j0 + rr, g = m0 - PADE_R + q;
+            const bool ok = i0 + c < NS && e < XT_ROWS * XT_IN && j <= N - 1 && g >= 0 && g < n_in;
+            const int jc = ok ? j : 1, gc = ok ? g : 0;
+            const double* row = src + (size_t)jc * P;
+            double a = 0.0, b = 0.0;
             if (E) {
                 // Hy at half points along x: even ghosts at both ends
-                const double h0 = row[g];
-                const double hl = row[g > 0 ? g - 1 : 0];
-                const double hr = row[g < n_in - 1 ? g + 1 : n_in - 1];
-                const double hs = row[g - P];
-                const double hn = row[g + P];
-                vr = h0;
-                vg = fma(cf.alpha, h0, (hl + hr + hs + hn - 4.0 * h0) * (1.0 / 12.0));
+                const double h0 = row[gc];
+                const double hl = row[gc > 0 ? gc - 1 : 0];
+                const double hr = row[gc < n_in - 1 ? gc + 1 : n_in - 1];
+                const double hs = row[gc - P];
+                const double hn = row[gc + P];
+                b = h0;
+                a = fma(cf.alpha, h0, (hl + hr + hs + hn - 4.0 * h0) * (1.0 / 12.0));
             } else if (MODE == XL_H_TRACKED) {
-                vg = row[g];                                       // stored G_E
+                a = row[gc];                                       // stored G_E
             } else {
                 // alpha E + L5 E / 12, zero on the walls (nodes 0 and N)
-                if (g > 0 && g < n_in - 1) {
-                    const double e0 = row[g];
-                    vg = fma(cf.alpha, e0, (row[g - 1] + row[g + 1] + row[g - P] + row[g + P] - 4.0 * e0) *
-                                               (1.0 / 12.0));
-                }
+                const int gi = gc < 1 ? 1 : (gc > n_in - 2 ? n_in - 2 : gc);
+                const double e0 = row[gi];
+                const double w = fma(cf.alpha, e0, (row[gi - 1] + row[gi + 1] + row[gi - P] + row[gi + P] - 4.0 * e0) *
+                                                       (1.0 / 12.0));
+                a = (gc > 0 && gc < n_in - 1) ? w : 0.0;
+            }
+            vg[c] = ok ? a : 0.0;
+            vr[c] = ok ? b : 0.0;
+        }
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+            const int e = tid + (i0 + c) * 256;
+            const int rr = e / XT_IN, q = e - rr * XT_IN;
+            if (i0 + c < NS && e < XT_ROWS * XT_IN) {
+                sg[rr * XT_STRIDE + q] = vg[c];
+                if (TWO) sr[rr * XT_STRIDE + q] = vr[c];
             }
         }
-        sg[rr * XT_STRIDE + q] = vg;
-        if (TWO) sr[rr * XT_STRIDE + q] = vr;
     }
     __syncthreads();
     const int row = tid % XT_ROWS;
@@ -229,13 +247,27 @@ __device__ __forceinline__ void xlines_e_tile(const double* __restrict__ src, do
     const int j0 = 1 + byi * XE_OROWS;                 // first T0 row
     const int n_in = L.n_in, n_out = L.n_out;
     const int g0 = m0 - 1 - PADE_R;                    // line position of staged column 0
-    // ---- stage the raw rows j0 - 1 .. j0 + 30 (zero off the grid and line)
-    for (int e = tid; e < XE_PROWS * XE_IN; e += 256) {
-        const int rr = e / XE_IN, q = e - rr * XE_IN;
-        const int j = j0 - 1 + rr, g = g0 + q;
-        double v = 0.0;
-        if (j <= N && g >= 0 && g < n_in) v = src[(size_t)j * P + g];
-        sh[rr * XE_STRIDE + q] = v;
+    // ---- stage the raw rows j0 - 1 .. j0 + 30 (zero off the grid and line).
+    // Every load of the thread is issued before the first LDS store: the
+    // loads take clamped (valid) addresses and the value is selected after.
+    {
+        constexpr int NS = (XE_PROWS * XE_IN + 255) / 256;
+        double v[NS];
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            const int e = tid + i * 256;
+            const int rr = e / XE_IN, q = e - rr * XE_IN;
+            const int j = j0 - 1 + rr, g = g0 + q;
+            const bool ok = e < XE_PROWS * XE_IN && j <= N && g >= 0 && g < n_in;
+            const double x = src[ok ? (size_t)j * P + g : 0];
+            v[i] = ok ? x : 0.0;
+        }
+#pragma unroll
+        for (int i = 0; i < NS; ++i) {
+            const int e = tid + i * 256;
+            const int rr = e / XE_IN, q = e - rr * XE_IN;
+            if (e < XE_PROWS * XE_IN) sh[rr * XE_STRIDE + q] = v[i];
+        }
     }
     __syncthreads();
     // ---- P on the 32 x 64 outputs; 8 per thread
