@@ -93,7 +93,8 @@ __device__ __forceinline__ void finish(const PhaseQueue& q)
     }
 }
 
-template <int MODE>
+// PF: Step 1 x-lines of the strip form (see k_xlines).
+template <int MODE, bool PF>
 __global__ __launch_bounds__(256) void k_batch_x(const BatchProb* __restrict__ bp, PhaseQueue q, int total,
                                                  int phase, Coef cf, PadeTaps taps)
 {
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(256) void k_batch_x(const BatchProb* __restrict__ b
             continue;
         }
         if constexpr (MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE)
-            xlines_e_tile<MODE == XL_E_TRACKED>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, local % tx, local / tx);
+            xlines_e_tile<MODE == XL_E_TRACKED, PF>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, local % tx, local / tx);
         else
             xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, local % tx, local / tx);
     }
@@ -222,9 +223,10 @@ static int resident_blocks(Kern kern, int threads)
 }
 
 template <int MODE>
-static int blocks_x()
+static int blocks_x(bool strips)
 {
-    return resident_blocks(k_batch_x<MODE>, 256);
+    constexpr bool E = MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE;
+    return (E && strips) ? resident_blocks(k_batch_x<MODE, E>, 256) : resident_blocks(k_batch_x<MODE, false>, 256);
 }
 
 template <int MODE>
@@ -284,10 +286,14 @@ static hipError_t launch_bs(int K, hipStream_t st, int blocks, const BatchProb* 
 
 template <int MODE>
 static hipError_t launch_bx(hipStream_t st, int blocks, const BatchProb* bp, const PhaseQueue& q, int total,
-                            int phase, const Coef& cf, const PadeTaps& taps)
+                            int phase, const Coef& cf, const PadeTaps& taps, bool strips)
 {
     const int g = std::max(1, std::min(blocks, total));
-    hipLaunchKernelGGL(k_batch_x<MODE>, dim3(g), dim3(256), 0, st, bp, q, total, phase, cf, taps);
+    constexpr bool E = MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE;
+    if (E && strips)
+        hipLaunchKernelGGL((k_batch_x<MODE, E>), dim3(g), dim3(256), 0, st, bp, q, total, phase, cf, taps);
+    else
+        hipLaunchKernelGGL((k_batch_x<MODE, false>), dim3(g), dim3(256), 0, st, bp, q, total, phase, cf, taps);
     return hipGetLastError();
 }
 
@@ -388,8 +394,8 @@ c4m_status launch_step(c4m_batch* b)
         const int tot = b->total[ph];
         switch (ph) {
             case PH_XE:
-                e = tracked ? launch_bx<XL_E_TRACKED>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe)
-                            : launch_bx<XL_E_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe);
+                e = tracked ? launch_bx<XL_E_TRACKED>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->strips)
+                            : launch_bx<XL_E_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->strips);
                 break;
             case PH_CE:
                 if (b->strips) {
@@ -401,8 +407,8 @@ c4m_status launch_step(c4m_batch* b)
                             : launch_bc<COL_E_DISCRETE>(K, b->base.tile_x, mixed, b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xe, b->cheb);
                 break;
             case PH_XH:
-                e = tracked ? launch_bx<XL_H_TRACKED>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh)
-                            : launch_bx<XL_H_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh);
+                e = tracked ? launch_bx<XL_H_TRACKED>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->strips)
+                            : launch_bx<XL_H_DISCRETE>(b->stream, nb, bp, q, tot, ph, b->coef, b->taps_xh, b->strips);
                 break;
             case PH_CHX:
                 if (b->strips) {
@@ -521,8 +527,8 @@ c4m_status build_tables(c4m_batch* b, char* cur)
     {
         const bool tracked = b->base.lap_mode == C4M_LAP_TRACKED;
         const int K = b->cheb.sweeps;
-        b->blocks[PH_XE] = tracked ? blocks_x<XL_E_TRACKED>() : blocks_x<XL_E_DISCRETE>();
-        b->blocks[PH_XH] = tracked ? blocks_x<XL_H_TRACKED>() : blocks_x<XL_H_DISCRETE>();
+        b->blocks[PH_XE] = tracked ? blocks_x<XL_E_TRACKED>(b->strips) : blocks_x<XL_E_DISCRETE>(b->strips);
+        b->blocks[PH_XH] = tracked ? blocks_x<XL_H_TRACKED>(b->strips) : blocks_x<XL_H_DISCRETE>(b->strips);
         if (b->strips) {
             b->blocks[PH_CE] = tracked ? blocks_strip<COL_E_TRACKED>(K) : blocks_strip<COL_E_DISCRETE>(K);
             b->blocks[PH_CHX] = tracked ? blocks_strip<COL_HX_TRACKED>(K) : blocks_strip<COL_HX_DISCRETE>(K);

@@ -34,7 +34,9 @@ __host__ __device__ inline int xl_tiles_y(int N)
     return (MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE) ? xe_tiles_y(N) : xlines_tiles_y(N);
 }
 
-template <int MODE>
+// PF: Step 1 x-lines of the strip form (raw derivative on every row, T0 on
+// the band columns only; the strips form the rest of T0).
+template <int MODE, bool PF = false>
 __global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps, YbandArgs yba)
 {
     const int ntx = xl_tiles_x<MODE>(xa.L.n_out), nty = xl_tiles_y<MODE>(xa.N);
@@ -52,7 +54,7 @@ __global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps
     int l;
     if (!xcd_tile(ntx * nty, l)) return;
     if constexpr (MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE)
-        xlines_e_tile<MODE == XL_E_TRACKED>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, l % ntx, l / ntx);
+        xlines_e_tile<MODE == XL_E_TRACKED, PF>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, l % ntx, l / ntx);
     else
         xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, l % ntx, l / ntx);
 }
@@ -186,7 +188,11 @@ hipError_t launch_rhs_e_2d(hipStream_t st, bool tracked, const double* hx, const
     const YbandArgs yba{hx, yb, line_h2n, 1};
     const dim3 grid(xcd_grid(xe_tiles_x(line_h2n.n_out) * xe_tiles_y(N)) + yband_blocks(yba, N));
     const XArgs xa{hy, t0, t1, N, P, line_h2n};
-    if (tracked)
+    if (yb && tracked)
+        hipLaunchKernelGGL((k_xlines<XL_E_TRACKED, true>), grid, dim3(256), 0, st, xa, cf, taps, yba);
+    else if (yb)
+        hipLaunchKernelGGL((k_xlines<XL_E_DISCRETE, true>), grid, dim3(256), 0, st, xa, cf, taps, yba);
+    else if (tracked)
         hipLaunchKernelGGL(k_xlines<XL_E_TRACKED>, grid, dim3(256), 0, st, xa, cf, taps, yba);
     else
         hipLaunchKernelGGL(k_xlines<XL_E_DISCRETE>, grid, dim3(256), 0, st, xa, cf, taps, yba);

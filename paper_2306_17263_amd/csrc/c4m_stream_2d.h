@@ -8,7 +8,11 @@
 //     rows near the line ends from the table);
 //   * the right-hand side b of the row is formed from it, the part across
 //     the line of the source conditioning G (a second difference between
-//     neighbouring columns) and the precomputed x-line part;
+//     neighbouring columns) and the x-line part: in Step 1 formed here from
+//     the raw x-line derivative P of the row and its neighbours (the
+//     conditioning commutes with the interior rows of the x-lines too; the
+//     columns near the x ends read it from the x-line pass), in Step 2
+//     precomputed;
 //   * the K Chebyshev applications of M = alpha I - beta L9 run as a
 //     pipeline: application k works on the row k rows above the newest b
 //     row, so it sees the rows above and below it from the previous
@@ -52,13 +56,17 @@ struct StripShape {
     static constexpr bool YPART = MODE != COL_HY;
     static constexpr bool SPLIT = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE || MODE == COL_HX_DISCRETE;
     static constexpr bool ESTEP = MODE == COL_E_TRACKED || MODE == COL_E_DISCRETE;
-    static constexpr bool HAS_T0 = ESTEP || MODE == COL_HY;
+    // Step 1: the x-line part T0 is formed from the raw x-derivative P (t1)
+    // of the row and its neighbours, and read from t0 on the band columns
+    static constexpr bool PSRC = ESTEP;
+    static constexpr bool HAS_T0 = MODE == COL_HY;
     static constexpr bool CARRY = MODE == COL_E_TRACKED;
     static constexpr int HX = K + (SPLIT ? 1 : 0);   // halo columns on each side
     static constexpr int OW = SW_COLS - 2 * HX;     // output columns
     static constexpr int NW = YPART ? SW_WIN + LA : 1;
     static constexpr int NQ = LA + 1;               // per-row prefetch queue
     static_assert(OW > 0, "strip too narrow for K");
+    static_assert(!CARRY || PSRC, "the carried update takes P from the Step 1 stream");
     static_assert(U % 4 == 0, "the boundary form runs 4 steps per block");
 };
 
@@ -154,6 +162,7 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
 {
     using SS = StripShape<K, MODE, U, LA>;
     constexpr bool YPART = SS::YPART, SPLIT = SS::SPLIT, HAS_T0 = SS::HAS_T0, CARRY = SS::CARRY;
+    constexpr bool PSRC = SS::PSRC;
     constexpr int HX = SS::HX, NQ = SS::NQ;
     // the raw derivative of row m + 1 needs rows m - 11 .. m + 14 only
     constexpr int W0 = YPART ? 2 : 0;
@@ -183,6 +192,11 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
     const int wbase = rev ? mfirst + (SW_WIN / 2 - 2) : mfirst - (SW_WIN / 2 - 3);
     const double psg = rev ? -1.0 : 1.0;
     const int n_in = L.n_in, n_out = L.n_out;
+    // Step 1: columns whose x-line output (m = gx - 1; the grid is square, so
+    // the x-lines share the y-lines' line) lies in an end band take T0 from
+    // the x-line pass
+    const int mx = gx - 1;
+    const bool xband = PSRC && XB && col_active && (L.all || mx <= L.b || mx >= n_out - 1 - L.b);
 
     // one buffer over every array of the strip (their span stays below
     // BUF_NULL: the caller takes the strip form only then); each array is a
@@ -221,30 +235,44 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
     auto out_row = [&](int ry) -> bool {   // step ry updates grid row grow(ry) - dir K
         return ry >= 2 * K && ry < TR && (!YB || grow(ry) - dir * K < yhi);
     };
-    // per-row inputs: t0 of the row of step ry; field, G_E and t1 of the
-    // output row that leaves the pipeline at step ry (rows clamped into the
-    // valid range: values of other rows are never used)
+    // Step 1: raw x-line derivative P of the row of step r (rows clamped
+    // into 0..N, where the x-line pass stores it)
+    auto load_p = [&](int r) -> double {
+        const int gg = YB ? clampi(grow(r), ylo - 1, yhi) : grow(r);
+        const double v = buf_ld_s(rb, laneb, dt1 + (unsigned)gg * rowb);
+        return col_data ? v : 0.0;
+    };
+    // per-row inputs: t0 of the row of step ry (Step 1: P of the row of step
+    // ry + 1, and in t1v T0 of the band columns of the row of step ry);
+    // field and G_E of the output row that leaves the pipeline at step ry
+    // (rows clamped into the valid range: values of other rows are never
+    // used)
     auto prefetch = [&](int ry, double& t0v, double& fv, double& gv, double& t1v) {
         const int rt = ry < TR ? ry : TR - 1;
         const int gyt = YB ? clampi(grow(rt), ylo, yhi - 1) : grow(rt);
         t0v = HAS_T0 ? buf_ld_s(rb, laneb, dt0 + (unsigned)gyt * rowb) : 0.0;
+        if (PSRC) t0v = load_p(ry + 1 < TR ? ry + 1 : TR);
         const int ro = rt < 2 * K ? 2 * K : rt;
         const int gyo = YB ? clampi(grow(ro) - dir * K, ylo, yhi - 1) : grow(ro) - dir * K;
         const unsigned so = (unsigned)gyo * rowb;
         fv = buf_ld_s(rb, laneb, dfield + so);
         gv = CARRY ? buf_ld_s(rb, laneb, dge + so) : 0.0;
-        t1v = CARRY ? buf_ld_s(rb, laneb, dt1 + so) : 0.0;
+        t1v = (PSRC && XB) ? buf_ld(rb, xband ? dt0 + (unsigned)gyt * rowb + laneb : BUF_NULL) : 0.0;
     };
 
     // ---- state
     double fw[NW];                 // raw window (see wbase)
     double t0q[NQ], fq[NQ], gq[NQ], t1q[NQ];
-    double pd[K + 1];              // raw Pade derivative of the last K + 1 rows
+    // carried Laplacian: raw curl of the last K + 1 rows (x-line minus y-line
+    // raw derivative)
+    double pd[K + 1];
     double dp1[K], dp2[K], rp1[K], xp1[K];
 #pragma unroll
     for (int j = 0; j < K; ++j) dp1[j] = dp2[j] = rp1[j] = xp1[j] = 0.0;
 #pragma unroll
     for (int j = 0; j <= K; ++j) pd[j] = 0.0;
+    // Step 1: P of the rows of the previous and the current step
+    double pprev = PSRC ? load_p(-1) : 0.0, pcur = PSRC ? load_p(0) : 0.0;
     if (YPART) {
 #pragma unroll
         for (int i = W0 ? 0 : 1; i < NW; ++i) fw[i] = load_raw(wbase + dir * (i - 1));
@@ -327,12 +355,26 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
                     v = ysign * sum;
                 }
                 if (HAS_T0) v += t0q[0];
+                if (PSRC) {
+                    // T0 = Z (alpha P + (P(m-1) + P(m+1) - 2 P) / 12 + (P_s + P_n - 2 P) / 12)
+                    const double pn = t0q[0];
+                    const double pc = pcur;
+                    const double along = fma(cf.alpha, pc, (from_left(pc) + from_right(pc) - 2.0 * pc) * (1.0 / 12.0));
+                    const double across = (pprev + pn - 2.0 * pc) * (1.0 / 12.0);
+                    double tv = cf.z * (along + across);
+                    if (XB) tv = xband ? t1q[0] : tv;
+                    v += tv;
+                }
                 b = (row_in(gy) && col_active) ? v : 0.0;
             }
             if (CARRY) {
 #pragma unroll
                 for (int j = 0; j < K; ++j) pd[j] = pd[j + 1];
-                pd[K] = pr;
+                pd[K] = pcur - pr;
+            }
+            if (PSRC) {
+                pprev = pcur;
+                pcur = t0q[0];
             }
 
             // ---- Chebyshev pipeline: application j + 1 on the row j + 1 steps behind
@@ -384,10 +426,21 @@ __device__ __forceinline__ void strip_run(const ColArgs& a, const Coef& cf, cons
                 buf_st(rb, ok ? dfield + row : BUF_NULL, fq[0] + de);
                 if (CARRY)
                     buf_st(rb, ok ? dge + row : BUF_NULL,
-                           gq[0] + fma(cf.ge_gain, de, -cf.ge_curl * (t1q[0] - pd[0])));
+                           gq[0] + fma(cf.ge_gain, de, -cf.ge_curl * pd[0]));
             }
         }
     }
+}
+
+// Whether every lane of a strip with first region column rx0 lies strictly
+// inside the unknowns (no mirror, no mask) and, in Step 1, outside the
+// x-line end bands.
+template <class SS>
+__host__ __device__ inline bool strip_xin(const UGrid& g, const PadeLine& L, int rx0)
+{
+    bool in = rx0 > g.lo[0] && rx0 + SW_COLS < g.hi[0];
+    if (SS::PSRC) in = in && !L.all && rx0 - 1 > L.b && rx0 + SW_COLS - 2 < L.n_out - 1 - L.b;
+    return in;
 }
 
 // Which form a strip takes: 0 interior, 1 x ends (XB), 2 y ends (XB and YB).
@@ -396,8 +449,7 @@ __host__ __device__ inline int strip_variant(const UGrid& g, const PadeLine& L, 
 {
     const int rx0 = x0 - SS::HX, ry0 = y0 - K;
     const int mofs = SS::ESTEP ? 1 : 0;
-    // x: every lane strictly inside the unknowns (no mirror, no mask)
-    const bool xin = rx0 > g.lo[0] && rx0 + SW_COLS < g.hi[0];
+    const bool xin = strip_xin<SS>(g, L, rx0);
     // y: every region row strictly inside; the Pade rows of the region and
     // two beyond each end stay out of the bands, and the window in the line
     bool yin = ry0 > g.lo[1] && ry0 + tr < g.hi[1];
@@ -486,10 +538,7 @@ inline bool strip_plan(const UGrid& g, const PadeLine& L, int slots, int simds, 
     plan.strips = strips;
     plan.xa = plan.xb = 0;
     auto x0_of = [&](int i) { return g.lo[0] + i * SS::OW; };
-    auto xin = [&](int i) {
-        const int rx0 = x0_of(i) - SS::HX;
-        return rx0 > g.lo[0] && rx0 + SW_COLS < g.hi[0];
-    };
+    auto xin = [&](int i) { return strip_xin<SS>(g, L, x0_of(i) - SS::HX); };
     while (plan.xa < strips && !xin(plan.xa)) ++plan.xa;
     while (plan.xa + plan.xb < strips && !xin(strips - 1 - plan.xb)) ++plan.xb;
     const int nstr[2] = {plan.xa + plan.xb, strips - plan.xa - plan.xb};

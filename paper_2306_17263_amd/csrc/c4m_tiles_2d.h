@@ -235,7 +235,10 @@ constexpr int XE_WIN = XE_SEG + PADE_TAPS - 1;
 __host__ __device__ inline int xe_tiles_x(int n_out) { return (n_out + XE_OUT - 1) / XE_OUT; }
 __host__ __device__ inline int xe_tiles_y(int N) { return (N - 1 + XE_OROWS - 1) / XE_OROWS; }
 
-template <bool TWO>
+// PF (strip form): the tile writes P itself to t1 on rows 0..N (the strips
+// form T0 from it) and T0 only on the band columns of the line ends (where
+// the along-line part needs the conditioned table rows) to t0.
+template <bool TWO, bool PF>
 __device__ __forceinline__ void xlines_e_tile(const double* __restrict__ src, double* __restrict__ t0,
                                               double* __restrict__ t1, int N, int P, const PadeLine& L,
                                               const Coef& cf, int bxi, int byi)
@@ -305,6 +308,31 @@ __device__ __forceinline__ void xlines_e_tile(const double* __restrict__ src, do
 #pragma unroll
     for (int k = 0; k < XE_SEG; ++k) sp[row * XE_PSTRIDE + seg * XE_SEG + k] = pv[k];
     __syncthreads();
+    if (PF) {
+        // P on the inner rows, and on rows 0 and N (first and last tile)
+        for (int e = tid; e < XE_PROWS * XE_OUT; e += 256) {
+            const int rp = e / XE_OUT, c = e - rp * XE_OUT;
+            const int jj = j0 - 1 + rp, m = m0 + c;
+            const bool keep = (rp >= 1 && rp <= XE_OROWS && jj <= N - 1) || jj == 0 || jj == N;
+            if (keep && jj <= N && m < n_out) t1[(size_t)jj * P + m + 1] = sp[rp * XE_PSTRIDE + c + 1];
+        }
+        if (!(L.all || m0 <= L.b || m0 + XE_OUT - 1 >= n_out - 1 - L.b)) return;
+        // T0 on the band columns: conditioned table rows along the line
+        for (int e = tid; e < XE_OROWS * XE_OUT; e += 256) {
+            const int rr = e / XE_OUT, c = e - rr * XE_OUT;
+            const int jj = j0 + rr, m = m0 + c;
+            if (jj > N - 1 || m >= n_out || !(L.all || m <= L.b || m >= n_out - 1 - L.b)) continue;
+            const double* q = sp + (rr + 1) * XE_PSTRIDE + c + 1;
+            const double pc = q[0];
+            const double across = (q[-XE_PSTRIDE] + q[XE_PSTRIDE] - 2.0 * pc) * (1.0 / 12.0);
+            CDouble* cr = as_const(L.crows + (size_t)pade_row_index(L, m) * COND_TAPS);
+            const double* wr = sh + (rr + 1) * XE_STRIDE + c;   // staged f[m - 13]
+            double along = 0.0;
+            for (int u = 0; u < COND_TAPS; ++u) along = fma(cr[u], wr[u], along);
+            t0[(size_t)jj * P + m + 1] = cf.z * (along + across);
+        }
+        return;
+    }
     // ---- T0 on the inner rows and outputs, through the LDS for row stores
     double t0v[XE_SEG];
     const bool out_row = row >= 1 && row <= XE_OROWS;
