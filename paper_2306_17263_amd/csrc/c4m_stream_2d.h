@@ -525,11 +525,12 @@ __device__ __forceinline__ void strip_tile(const ColArgs& a, const Coef& cf, con
 // resident wave slots).
 constexpr double STRIP_COST[3] = {1.0, 1.3, 1.9};
 constexpr int STRIP_FILL_STEPS = 6;
-// (measured at N = 2048: two waves for the Step 1 strips, three for Step 2)
+// (measured at N = 2048: three waves for the strips of both steps; two
+// waves were better for Step 1 while its strips read both x-line terms)
 template <class SS>
 constexpr double strip_waves_per_simd()
 {
-    return SS::ESTEP ? 2.0 : 3.0;
+    return 3.0;
 }
 template <class SS, int K, int U>
 inline bool strip_plan(const UGrid& g, const PadeLine& L, int slots, int simds, StripPlan& plan)
