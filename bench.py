@@ -60,14 +60,14 @@ CLASS_PATTERNS = {
     "rhs_e": r"k_xlines<[01][,>]",
     "solve_e": r"k_(?:strip|col)<\d+, [01],",
     "rhs_h": r"k_xlines<[23][,>]",
-    "solve_h": r"k_(?:strip|col)<\d+, [234],",
+    "solve_h": r"k_(?:strip_h|strip|col)<\d+, [234],",
 }
 # kernels of each class in the default single-problem form
 CLASS_KERNELS = {
     "rhs_e": "k_xlines<0|1, true> (Step 1 raw x-line derivatives, T0 on the end-band columns, and the band table of the Hx y-lines)",
     "solve_e": "k_strip<K, 0|1> (Step 1 y-lines, T0 from the raw x-line derivatives, Chebyshev solve, Ez and G_E update)",
     "rhs_h": "k_xlines<2|3, false> (Step 2 x-lines and the band table of the G_E y-lines)",
-    "solve_h": "k_strip<K, 2|3> + k_strip<K, 4> (Step 2 Hx and Hy solves and updates)",
+    "solve_h": "k_strip_h<K, 2|3> (Step 2 Hx and Hy solves and updates, one launch)",
 }
 
 

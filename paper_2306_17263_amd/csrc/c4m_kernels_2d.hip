@@ -87,6 +87,38 @@ __global__ __launch_bounds__(SW_COLS * SW_WAVES) __attribute__((amdgpu_waves_per
     strip_tile<K, MODE, U, LA>(a, cf, L, cs, a.g.lo[0] + strip * SS::OW, y0, tr, up);
 }
 
+// Step 2 in the strip form: the Hx strips (mode MA) and the Hy strips of a
+// step in one launch.  The Hx items come first; each part keeps the
+// XCD-aware order over its own items (the part sizes are whole rounds of
+// the XCD count), so the Hy items fill the device as the Hx items drain.
+template <int K, int MA, int U, int LA, int WPE>
+__global__ __launch_bounds__(SW_COLS * SW_WAVES) __attribute__((amdgpu_waves_per_eu(WPE))) void k_strip_h(
+    ColArgs a, ColArgs b, Coef cf, PadeLine L, ChebSchedule cs, StripPlan pa, StripPlan pb)
+{
+    using SA = StripShape<K, MA, U, LA>;
+    using SB = StripShape<K, COL_HY, U, LA>;
+    const int na = pa.items(), nb = pb.items();
+    const int ga = xcd_grid((na + SW_WAVES - 1) / SW_WAVES);
+    const bool first = (int)blockIdx.x < ga;
+    const int tiles = first ? (na + SW_WAVES - 1) / SW_WAVES : (nb + SW_WAVES - 1) / SW_WAVES;
+    const int per = (tiles + NXCD - 1) / NXCD;
+    const int g = (int)blockIdx.x - (first ? 0 : ga);
+    const int l = (g % NXCD) * per + g / NXCD;
+    if (l >= tiles) return;
+    const int item = l * SW_WAVES + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / SW_COLS));
+    int strip, y0, tr;
+    bool up;
+    if (first) {
+        if (item >= na) return;
+        pa.item(item, strip, y0, tr, up);
+        strip_tile<K, MA, U, LA>(a, cf, L, cs, a.g.lo[0] + strip * SA::OW, y0, tr, up);
+    } else {
+        if (item >= nb) return;
+        pb.item(item, strip, y0, tr, up);
+        strip_tile<K, COL_HY, U, LA>(b, cf, L, cs, b.g.lo[0] + strip * SB::OW, y0, tr, up);
+    }
+}
+
 // Whether a 2D single-problem solve takes the strip form (the host then
 // provides the band table, in a workspace whose span fits one buffer).
 bool strip_form_2d(int shape, bool mixed, int sweeps)
@@ -137,6 +169,45 @@ static hipError_t launch_strip(hipStream_t st, const ColArgs& a, const Coef& cf,
     }
     const dim3 grid(xcd_grid((plan->items() + SW_WAVES - 1) / SW_WAVES));
     hipLaunchKernelGGL(kern, grid, dim3(SW_COLS * SW_WAVES), 0, st, a, cf, L, cs, *plan);
+    return hipGetLastError();
+}
+
+// Step 2 strips in one launch (k_strip_h); each part is planned for
+// 1 / STRIP_H_DIV of the resident wave slots.
+constexpr int STRIP_H_DIV = 2;
+template <int K, int MA, int U, int LA, int WPE>
+static hipError_t launch_strip_h(hipStream_t st, const ColArgs& a, const ColArgs& b, const Coef& cf,
+                                 const PadeLine& L, const ChebSchedule& cs)
+{
+    using SA = StripShape<K, MA, U, LA>;
+    using SB = StripShape<K, COL_HY, U, LA>;
+    auto kern = k_strip_h<K, MA, U, LA, WPE>;
+    static std::mutex mu;
+    static std::map<std::tuple<int, int, int>, std::pair<StripPlan, StripPlan>> plans;
+    const std::pair<StripPlan, StripPlan>* pl = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        int dev = 0;
+        (void)hipGetDevice(&dev);
+        const auto key = std::make_tuple(dev, a.N, L.n_in);
+        auto it = plans.find(key);
+        if (it == plans.end()) {
+            int cus = 0, blocks = 0;
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kern, SW_COLS * SW_WAVES, 0);
+            cus = cus > 0 ? cus : 256;
+            const int slots = cus * (blocks > 0 ? blocks : 1) * SW_WAVES;
+            std::pair<StripPlan, StripPlan> pp{};
+            if (!strip_plan<SA, K, U>(a.g, L, slots / STRIP_H_DIV, cus * 4, pp.first) ||
+                !strip_plan<SB, K, U>(b.g, L, slots / STRIP_H_DIV, cus * 4, pp.second))
+                return hipErrorInvalidValue;
+            it = plans.emplace(key, pp).first;
+        }
+        pl = &it->second;
+    }
+    const int ga = xcd_grid((pl->first.items() + SW_WAVES - 1) / SW_WAVES);
+    const int gb = xcd_grid((pl->second.items() + SW_WAVES - 1) / SW_WAVES);
+    hipLaunchKernelGGL(kern, dim3(ga + gb), dim3(SW_COLS * SW_WAVES), 0, st, a, b, cf, L, cs, pl->first, pl->second);
     return hipGetLastError();
 }
 
@@ -233,12 +304,17 @@ hipError_t launch_solve_h_2d(hipStream_t st, int shape, bool mixed, bool tracked
     // right-hand side -(1/Z) delta_y G_E along columns
     ColArgs ax{src, nullptr, nullptr, hx, nullptr, ugrid_hx(N), N, P};
     ax.yb = yb;
-    hipError_t e = tracked ? launch_col<COL_HX_TRACKED>(shape, mixed, st, ax, cf, taps, line_n2h, cs)
-                           : launch_col<COL_HX_DISCRETE>(shape, mixed, st, ax, cf, taps, line_n2h, cs);
-    if (e != hipSuccess) return e;
     // Hy: Neumann in x, Dirichlet in y; right-hand side T1 from the x-lines
     ColArgs ay{nullptr, t1, nullptr, hy, nullptr, ugrid_hy(N), N, P};
     ay.yb = yb;
+    if (shape == 0 && strip_form_2d(shape, mixed, cs.sweeps) && yb)
+        return with_k_strip(cs.sweeps, [&]<int K>() {
+            return tracked ? launch_strip_h<K, COL_HX_TRACKED, 8, 1, 3>(st, ax, ay, cf, line_n2h, cs)
+                           : launch_strip_h<K, COL_HX_DISCRETE, 8, 1, 3>(st, ax, ay, cf, line_n2h, cs);
+        });
+    hipError_t e = tracked ? launch_col<COL_HX_TRACKED>(shape, mixed, st, ax, cf, taps, line_n2h, cs)
+                           : launch_col<COL_HX_DISCRETE>(shape, mixed, st, ax, cf, taps, line_n2h, cs);
+    if (e != hipSuccess) return e;
     return launch_col<COL_HY>(shape, mixed, st, ay, cf, taps, line_n2h, cs);
 }
 
