@@ -154,15 +154,38 @@ c4m_status c4m_create(const c4m_config* cfg, void* d_workspace, size_t bytes,
 c4m_status c4m_field_shape(const c4m_problem* p, c4m_field f, int64_t shape[3]);
 
 /* Copy a whole field in (E at tau = 0, H at tau = h_tau/2, l at tau = 0).
- * `src` is a device pointer when src_on_device != 0, else host memory (the
- * call then synchronises the stream).  Tangential E and l are forced to zero
- * on the walls.  If l is never set after E, the library uses l = L5 E. */
+ * `src` is a device pointer when src_on_device != 0, else host memory.
+ * E and l components synchronise the stream (their wall values are checked
+ * first); H from host memory too.  Tangential E and l vanish on PEC walls
+ * (eq:bc_E=0 and, for l = h^2 Delta E, d^2 E_tan / dt^2 = 0 there): EINVAL,
+ * and nothing changed, when a wall value exceeds 1e-13 of the array's
+ * largest magnitude; smaller ones (rounding of sampled data) are stored as
+ * 0.  The whole array of an H component is taken, walls included: the
+ * values on the walls normal to its axis are the constant normal H of
+ * eq:BC_H.  If l is never set after E, the library uses l = L5 E. */
 c4m_status c4m_set_field(c4m_problem* p, c4m_field f, const double* src, int src_on_device);
+
+/* Wall values of one component on one face (face = 2 axis + side, axis
+ * 0..dim-1 for x, y, z, side 0 the wall at coordinate 0, 1 the wall at 1).
+ * `vals` is the component's wall plane: its (nz, ny, nx) extent without
+ * `axis`, remaining axes in that order, x fastest (host memory, or device
+ * memory when vals_on_device != 0; host data synchronise the stream).
+ * H_s: only the two faces normal to axis s (the points H_s has on walls);
+ * the values are its normal component there, constant in time on a PEC
+ * wall (eq:BC_H, Table tab:bc), and enter the source conditioning of
+ * Step 1 as the wall values of the node-direction stencil.
+ * E_s and l_s: only faces normal to the other axes, and every value must be
+ * 0 (tangential E vanishes, eq:bc_E=0): EINVAL otherwise, nothing changed.
+ * EINVAL for any other face. */
+c4m_status c4m_set_boundary(c4m_problem* p, c4m_field f, int32_t face, const double* vals, int vals_on_device);
 
 /* Copy a whole field out; a host destination synchronises the stream. */
 c4m_status c4m_get_field(c4m_problem* p, c4m_field f, double* dst, int dst_on_device);
 
-/* Enqueue nsteps whole steps on the problem's stream (asynchronous). */
+/* Enqueue nsteps whole steps on the problem's stream (asynchronous);
+ * nsteps = 0 does nothing.  With C4M_FLAG_CHECK_FINITE the call scans the
+ * fields afterwards, waits, and returns ENONFINITE (sticky in c4m_info)
+ * when a NaN or Inf is found. */
 c4m_status c4m_step(c4m_problem* p, int64_t nsteps);
 
 /* Counters and sticky flags; synchronises the stream when PCG statistics

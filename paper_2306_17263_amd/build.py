@@ -19,7 +19,11 @@ def sources():
 def build(verbose: bool = True, jobs: int = 8) -> str:
     objdir = os.path.join(ROOT, "_build")
     os.makedirs(objdir, exist_ok=True)
-    flags = ["-O3", "-std=c++20", f"--offload-arch={ARCH}", "-fPIC",
+    # -ffp-contract=on: a multiply-add is fused or not by its source
+    # expression, never across statements, so a device function gives the
+    # same bits in every kernel it is inlined into (batch members equal the
+    # problem run alone)
+    flags = ["-O3", "-std=c++20", f"--offload-arch={ARCH}", "-fPIC", "-ffp-contract=on",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
              "-munsafe-fp-atomics", "-Wall",
              "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]

@@ -45,6 +45,10 @@ hipError_t launch_lap_convert(hipStream_t st, double* a, const double* e, double
                               int P, size_t plane, double alpha, int mode);
 hipError_t launch_count_nonfinite(hipStream_t st, const double* a, const Box& bx, int P,
                                   size_t plane, int* count);
+hipError_t launch_wall_max(hipStream_t st, const double* a, const Box& bx, int P, size_t plane,
+                           unsigned long long* out);
+hipError_t launch_put_plane(hipStream_t st, double* a, const double* vals, const Box& bx, int axis, int at,
+                            int P, size_t plane);
 
 namespace {
 
@@ -273,6 +277,11 @@ using namespace c4m;
 // Problem handle.
 // ---------------------------------------------------------------------------
 enum { LAP_UNSET = 0, LAP_RAW = 1, LAP_GE = 2 };
+
+// Tangential E (and l) wall values accepted by c4m_set_field: at most this
+// fraction of the array's largest magnitude (rounding of sampled data such
+// as sin(pi k) at x = 1), stored as exact zeros.
+constexpr double C4M_WALL_RTOL = 1e-13;
 
 struct c4m_problem {
     c4m_config cfg{};
@@ -825,22 +834,98 @@ c4m_status c4m_set_field(c4m_problem* p, c4m_field f, const double* src, int src
     const int c = field_comp(f);
     const bool is_lap = f >= C4M_LX;
     if (is_lap && p->cfg.lap_mode != C4M_LAP_TRACKED) return C4M_OK;   // recomputed each step
+    const Box& bx = p->box[c];
+    if (c < 3) {
+        // Tangential E and l vanish on the PEC walls (eq:bc_E=0): reject
+        // wall values above rounding of the array's scale, before anything
+        // changes.  Host data are checked here, device data in a staging
+        // copy in the first temporary.
+        double all = 0.0, wall = 0.0;
+        if (!src_on_device) {
+            const size_t nx = bx.n[0], ny = bx.n[1], nz = bx.n[2];
+            for (size_t k = 0; k < nz; ++k)
+                for (size_t j = 0; j < ny; ++j)
+                    for (size_t i = 0; i < nx; ++i) {
+                        double v = fabs(src[(k * ny + j) * nx + i]);
+                        if (v != v) v = INFINITY;
+                        all = v > all ? v : all;
+                        const size_t q[3] = {i, j, k};
+                        bool w = false;
+                        for (int d = 0; d < 3; ++d)
+                            w = w || (bx.active[d] && !bx.half[d] && (q[d] == 0 || q[d] == (size_t)bx.n[d] - 1));
+                        if (w) wall = v > wall ? v : wall;
+                    }
+        } else {
+            c4m_status s = copy_field(p, p->tmp[0], bx, src, true, true);
+            if (s != C4M_OK) return s;
+            unsigned long long* mx = (unsigned long long*)((char*)p->counter + 64);
+            unsigned long long h[2] = {0, 0};
+            hipError_t e = hipMemsetAsync(mx, 0, 2 * sizeof(unsigned long long), p->stream);
+            if (e == hipSuccess) e = launch_wall_max(p->stream, p->tmp[0], bx, p->P, p->plane, mx);
+            if (e == hipSuccess) e = hipMemcpyAsync(h, mx, sizeof(h), hipMemcpyDeviceToHost, p->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+            if (e != hipSuccess) return hip_fail(e, "wall check");
+            memcpy(&all, &h[0], sizeof(double));
+            memcpy(&wall, &h[1], sizeof(double));
+        }
+        if (!(wall <= C4M_WALL_RTOL * all))
+            return fail(C4M_EINVAL, "tangential E (and l) must vanish on the PEC walls");
+    }
     if (!is_lap && c < 3 && p->cfg.lap_mode == C4M_LAP_TRACKED && p->lap_state[c] == LAP_GE) {
         // keep l: convert G_E back to l with the old E before E changes
-        hipError_t e = launch_lap_convert(p->stream, p->ge[c], p->f[c], p->ge[c], p->box[c], p->P,
+        hipError_t e = launch_lap_convert(p->stream, p->ge[c], p->f[c], p->ge[c], bx, p->P,
                                           p->plane, p->coef.alpha, 1);
         if (e != hipSuccess) return hip_fail(e, "lap_convert");
         p->lap_state[c] = LAP_RAW;
     }
     double* dst = is_lap ? p->ge[c] : p->f[c];
-    c4m_status s = copy_field(p, dst, p->box[c], src, true, src_on_device != 0);
+    c4m_status s = copy_field(p, dst, bx, src, true, src_on_device != 0);
     if (s != C4M_OK) return s;
     if (c < 3) {
-        hipError_t e = launch_zero_walls(p->stream, dst, p->box[c], p->P, p->plane);
+        // values at rounding level become exact zeros
+        hipError_t e = launch_zero_walls(p->stream, dst, bx, p->P, p->plane);
         if (e != hipSuccess) return hip_fail(e, "zero_walls");
     }
     if (is_lap) p->lap_state[c] = LAP_RAW;
     return C4M_OK;
+}
+
+c4m_status c4m_set_boundary(c4m_problem* p, c4m_field f, int32_t face, const double* vals, int vals_on_device)
+{
+    if (!p || !vals || !has_field(p->dim, f)) return fail(C4M_EINVAL, "bad field");
+    if (face < 0 || face >= 2 * p->dim) return fail(C4M_EINVAL, "face must be 2 axis + side with axis < dim");
+    const int axis = face / 2, side = face % 2;
+    const int c = field_comp(f);
+    const Box& bx = p->box[c];
+    const size_t count = (size_t)bx.n[0] * bx.n[1] * bx.n[2] / bx.n[axis];
+    if (c < 3) {
+        // E_s and l_s: points on the walls normal to the other axes only,
+        // where they must vanish (eq:bc_E=0)
+        if (axis == c) return fail(C4M_EINVAL, "E_s has no points on the walls normal to axis s");
+        std::vector<double> h(count);
+        const double* hv = vals;
+        if (vals_on_device) {
+            hipError_t e = hipMemcpyAsync(h.data(), vals, count * sizeof(double), hipMemcpyDeviceToHost, p->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+            if (e != hipSuccess) return hip_fail(e, "boundary copy");
+            hv = h.data();
+        }
+        for (size_t i = 0; i < count; ++i)
+            if (hv[i] != 0.0) return fail(C4M_EINVAL, "tangential E (and l) must vanish on the PEC walls");
+        return C4M_OK;
+    }
+    // H_s: points on the two walls normal to axis s, where it keeps its
+    // value for all time (eq:BC_H)
+    if (axis != c - 3) return fail(C4M_EINVAL, "H_s has points only on the walls normal to axis s");
+    const double* dv = vals;
+    if (!vals_on_device) {
+        hipError_t e = hipMemcpyAsync(p->tmp[0], vals, count * sizeof(double), hipMemcpyHostToDevice, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "boundary copy");
+        dv = p->tmp[0];
+    }
+    hipError_t e = launch_put_plane(p->stream, p->f[c], dv, bx, axis, side ? bx.n[axis] - 1 : 0, p->P, p->plane);
+    if (e == hipSuccess && !vals_on_device) e = hipStreamSynchronize(p->stream);
+    return e == hipSuccess ? C4M_OK : hip_fail(e, "set_boundary");
 }
 
 c4m_status c4m_get_field(c4m_problem* p, c4m_field f, double* dst, int dst_on_device)
@@ -874,6 +959,7 @@ c4m_status c4m_get_field(c4m_problem* p, c4m_field f, double* dst, int dst_on_de
 c4m_status c4m_step(c4m_problem* p, int64_t nsteps)
 {
     if (!p || nsteps < 0) return fail(C4M_EINVAL, "bad step count");
+    if (nsteps == 0) return C4M_OK;
     c4m_status s = ensure_ge(p);
     if (s != C4M_OK) return s;
     for (int64_t t = 0; t < nsteps; ++t) {

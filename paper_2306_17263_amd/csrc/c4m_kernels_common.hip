@@ -69,6 +69,46 @@ __global__ void k_count_nonfinite(const double* a, Box bx, int P, size_t plane, 
     if ((threadIdx.x & 63) == 0 && m) atomicAdd(count, __popcll(m));
 }
 
+// Largest magnitude over the array (out[0]) and over its node walls
+// (out[1]), as bit patterns of non-negative doubles (which order like the
+// values) combined with atomicMax; NaN counts as infinity.
+__global__ void k_wall_max(const double* a, Box bx, int P, size_t plane, unsigned long long* out)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int k = blockIdx.z;
+    double v = 0.0, w = 0.0;
+    if (i < bx.n[0]) {
+        v = fabs(a[k * plane + (size_t)j * P + i]);
+        v = isnan(v) ? INFINITY : v;
+        w = on_node_wall(bx, i, j, k) ? v : 0.0;
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        v = fmax(v, __shfl_xor(v, off));
+        w = fmax(w, __shfl_xor(w, off));
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(out, (unsigned long long)__double_as_longlong(v));
+        atomicMax(out + 1, (unsigned long long)__double_as_longlong(w));
+    }
+}
+
+// Scatter a contiguous wall plane (the box without `axis`, remaining axes
+// in (z, y, x) order, x fastest) into index `at` along `axis`.
+__global__ void k_put_plane(double* a, const double* vals, Box bx, int axis, int at, int P, size_t plane)
+{
+    const int u = axis == 0 ? 1 : 0;          // faster remaining axis
+    const int v = axis == 2 ? 1 : 2;          // slower remaining axis
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= bx.n[u] * bx.n[v]) return;
+    int q[3];
+    q[axis] = at;
+    q[u] = e % bx.n[u];
+    q[v] = e / bx.n[u];
+    a[q[2] * plane + (size_t)q[1] * P + q[0]] = vals[e];
+}
+
 static dim3 box_grid(const Box& bx) { return dim3((bx.n[0] + 255) / 256, bx.n[1], bx.n[2]); }
 
 hipError_t launch_zero_walls(hipStream_t st, double* a, const Box& bx, int P, size_t plane)
@@ -82,6 +122,21 @@ hipError_t launch_lap_convert(hipStream_t st, double* a, const double* e, double
 {
     hipLaunchKernelGGL(k_lap_convert, box_grid(bx), dim3(256), 0, st, a, e, out, bx, P, plane, alpha,
                        mode);
+    return hipGetLastError();
+}
+
+hipError_t launch_wall_max(hipStream_t st, const double* a, const Box& bx, int P, size_t plane,
+                           unsigned long long* out)
+{
+    hipLaunchKernelGGL(k_wall_max, box_grid(bx), dim3(256), 0, st, a, bx, P, plane, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_put_plane(hipStream_t st, double* a, const double* vals, const Box& bx, int axis, int at,
+                            int P, size_t plane)
+{
+    const int cnt = bx.n[0] * bx.n[1] * bx.n[2] / bx.n[axis];
+    hipLaunchKernelGGL(k_put_plane, dim3((cnt + 255) / 256), dim3(256), 0, st, a, vals, bx, axis, at, P, plane);
     return hipGetLastError();
 }
 

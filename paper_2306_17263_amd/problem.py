@@ -94,6 +94,21 @@ class Problem:
         L.check(self._lib.c4m_set_field(self._h, L.FIELD[name], a.ctypes.data_as(ctypes.c_void_p), 0),
                 f"c4m_set_field({name})")
 
+    def set_boundary(self, name: str, face: int, values):
+        """Wall plane of one component on face 2 axis + side (c4m_set_boundary)."""
+        shp = list(self.shape(name))
+        axis = face // 2
+        del shp[2 - axis]
+        if isinstance(values, torch.Tensor) and values.is_cuda:
+            t = values.to(torch.float64).contiguous().reshape(shp)
+            self._keep = t
+            L.check(self._lib.c4m_set_boundary(self._h, L.FIELD[name], int(face), ctypes.c_void_p(t.data_ptr()), 1),
+                    f"c4m_set_boundary({name}, {face})")
+            return
+        a = np.ascontiguousarray(np.asarray(values, dtype=np.float64).reshape(shp))
+        L.check(self._lib.c4m_set_boundary(self._h, L.FIELD[name], int(face), a.ctypes.data_as(ctypes.c_void_p), 0),
+                f"c4m_set_boundary({name}, {face})")
+
     def get(self, name: str, device: bool = False):
         shp = self.shape(name)
         if device:

@@ -5,10 +5,48 @@ from __future__ import annotations
 import numpy as np
 
 import oracle
-from workloads import mode_fields
+from workloads import component_half_axes, mode_fields
 
 CLOSURES = {"paper": oracle.CLOSURE_PAPER, "reflect": oracle.CLOSURE_REFLECT}
 LAPS = {"tracked": oracle.LAP_TRACKED, "discrete": oracle.LAP_DISCRETE}
+
+
+def zero_node_walls(name, dim, a):
+    """Zero the wall planes along the node axes of an E (or l) component:
+    tangential E and the carried Laplacian vanish on PEC walls."""
+    half = component_half_axes(name, dim)
+    a = np.array(a, dtype=np.float64, copy=True)
+    for ax in range(dim):
+        if half[ax]:
+            continue
+        sl = [slice(None)] * 3
+        for idx in (0, -1):
+            sl[2 - ax] = idx
+            a[tuple(sl)] = 0.0
+    return a
+
+
+def random_fields(dim, n, seed, h_walls=False):
+    """Seeded normal fields with PEC walls: tangential E and l zero on the
+    walls; normal H zero on its walls unless h_walls (then seeded values,
+    held constant in time by the scheme)."""
+    from workloads import component_names, field_shape
+    rng = np.random.default_rng(seed)
+    out = {}
+    for name in component_names(dim):
+        a = rng.normal(size=field_shape(name, dim, n))
+        if name[0] == "h" and not h_walls:
+            ax = "xyz".index(name[1])
+            sl = [slice(None)] * 3
+            for idx in (0, -1):
+                sl[2 - ax] = idx
+                a[tuple(sl)] = 0.0
+        out[name] = zero_node_walls(name, dim, a) if name[0] == "e" else a
+    for name in list(out):
+        if name[0] == "e":
+            lname = "l" + name[1]
+            out[lname] = zero_node_walls(lname, dim, 0.1 * rng.normal(size=out[name].shape))
+    return out
 
 
 def initial_fields(dim, n, cfl, k=None, seed=None, amp=1.0, z=1.0):
@@ -16,29 +54,15 @@ def initial_fields(dim, n, cfl, k=None, seed=None, amp=1.0, z=1.0):
     h = 1.0 / n
     if k is not None:
         return mode_fields(dim, n, k, 0.0, cfl * h / 2, amp=amp, z=z)
-    from workloads import component_names, field_shape
-    rng = np.random.default_rng(seed)
-    out = {}
-    for name in component_names(dim):
-        a = rng.normal(size=field_shape(name, dim, n))
-        if name[0] == "h":                       # normal H on its walls: zero
-            ax = "xyz".index(name[1])
-            sl = [slice(None)] * 3
-            sl[2 - ax] = 0
-            a[tuple(sl)] = 0.0
-            sl[2 - ax] = -1
-            a[tuple(sl)] = 0.0
-        out[name] = a
-    for name in list(out):
-        if name[0] == "e":
-            out["l" + name[1]] = 0.1 * rng.normal(size=out[name].shape)
-    return out
+    return random_fields(dim, n, seed)
 
 
-def run_pair(dim, n, cfl, steps, closure="paper", lap="tracked", k=(1, 1), seed=None, z=1.0, **kw):
+def run_pair(dim, n, cfl, steps, closure="paper", lap="tracked", k=(1, 1), seed=None, z=1.0,
+             init=None, **kw):
     """Returns (gpu_fields, oracle_fields) after `steps` steps."""
     from paper_2306_17263_amd import Problem
-    init = initial_fields(dim, n, cfl, k=k if seed is None else None, seed=seed, z=z)
+    if init is None:
+        init = initial_fields(dim, n, cfl, k=k if seed is None else None, seed=seed, z=z)
     g = Problem(dim, n, cfl, z=z, closure=closure, lap_mode=lap, **kw)
     o = oracle.OracleProblem(dim, n, cfl, z, closure=CLOSURES[closure], lap_mode=LAPS[lap])
     for name in g.fields():
@@ -61,3 +85,26 @@ def rel_l2_all(gf, of, names):
     num = sum(np.sum((gf[a] - of[a]) ** 2) for a in names)
     den = sum(np.sum(of[a] ** 2) for a in names)
     return float(np.sqrt(num / den))
+
+
+def eh_names(gf):
+    return [a for a in ("ex", "ey", "ez", "hx", "hy", "hz") if a in gf]
+
+
+def check_fields(gf, of, tol=1e-12, lap_tol=1e-9, names=None):
+    """Parity bar: relative L2 over all E and H arrays <= tol, and every
+    element within 10 tol of the largest oracle magnitude (so a local error
+    cannot hide in a global norm).  The carried Laplacian is compared at
+    lap_tol: the device holds G_E = alpha E + l/12 and recovers l as
+    12 (G_E - alpha E), which cancels about three digits."""
+    names = names or eh_names(of)
+    err = rel_l2_all(gf, of, names)
+    assert err <= tol, (err, {a: rel_l2(gf[a], of[a]) for a in names})
+    scale = max(float(np.max(np.abs(of[a]))) for a in names)
+    for a in names:
+        d = float(np.max(np.abs(gf[a] - of[a])))
+        assert d <= 10 * tol * scale, (a, d, scale)
+    for a in ("lx", "ly", "lz"):
+        if a in gf and a in of and lap_tol is not None:
+            assert rel_l2(gf[a], of[a]) <= lap_tol, a
+    return err

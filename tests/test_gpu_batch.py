@@ -1,11 +1,18 @@
-"""Batched form: every problem advanced inside the batch (persistent launches,
-one HIP graph per step) equals the same problem advanced alone through the
-single-problem path bit for bit, and the oracle to 1e-12."""
+"""Batched form: every problem advanced inside the batch equals the same
+problem advanced alone through the single-problem path bit for bit, and the
+oracle to the FP64 bar (1e-12 relative L2, every element within 1e-11 of the
+field scale).
+
+Bitwise equality holds because the batch and the single-problem kernels run
+the same device functions on the same data and the library is built with
+floating-point contraction fixed per source expression (-ffp-contract=on),
+so a multiply-add is fused or not by the source, not by the kernel it is
+inlined into."""
 import numpy as np
 import pytest
 
 import oracle
-from gpu_util import CLOSURES, LAPS, initial_fields, rel_l2_all
+from gpu_util import CLOSURES, LAPS, check_fields, initial_fields, rel_l2_all
 
 pytestmark = pytest.mark.gpu
 
@@ -51,9 +58,42 @@ def test_batch_equals_alone_and_oracle(lap, closure):
         of = {a: o.get(a) for a in names}
         for a in names:
             assert np.array_equal(gb[a], ga[a]), (s["n"], a)
-        assert rel_l2_all(gb, of, names) <= 1e-12, s["n"]
+        check_fields(gb, of)
         assert p.info()["steps"] == steps
         alone.close()
+    b.close()
+
+
+@pytest.mark.parametrize("lap", ["tracked", "discrete"])
+def test_batch_large_members_equal_alone(lap):
+    # members at the top of the batch workload's size range (N up to 768)
+    # equal the problem run alone bit for bit, and the oracle
+    import torch
+    from paper_2306_17263_amd import Batch, Problem
+    ns = [768, 64, 701, 400]
+    steps = 6
+    st = torch.cuda.Stream()
+    b = Batch([{"n": n} for n in ns], stream=st, lap_mode=lap)
+    inits = [initial_fields(2, n, 0.5, seed=500 + n) for n in ns]
+    for p, init in zip(b.problems, inits):
+        for name in p.fields():
+            p.set(name, init[name])
+    b.step(steps)
+    names = ["ez", "hx", "hy"]
+    for p, n, init in zip(b.problems, ns, inits):
+        alone = Problem(2, n, 0.5, stream=st, lap_mode=lap)
+        for name in alone.fields():
+            alone.set(name, init[name])
+        alone.step(steps)
+        for a in names:
+            assert np.array_equal(p.get(a), alone.get(a)), (n, a)
+        alone.close()
+        if n in (768, 64):
+            o = oracle.OracleProblem(2, n, 0.5, 1.0, lap_mode=LAPS[lap])
+            for name in alone.fields():
+                o.set(name, init[name])
+            o.step(steps)
+            check_fields({a: p.get(a) for a in names}, {a: o.get(a) for a in names})
     b.close()
 
 
@@ -83,7 +123,7 @@ def test_batch_shapes_and_grid(shape, mult):
             o.set(name, init[name])
         o.step(6)
         names = ["ez", "hx", "hy"]
-        assert rel_l2_all({a: p.get(a) for a in names}, {a: o.get(a) for a in names}, names) <= 1e-12
+        check_fields({a: p.get(a) for a in names}, {a: o.get(a) for a in names})
     b.close()
 
 

@@ -5,7 +5,7 @@ determinism of the reductions."""
 import numpy as np
 import pytest
 
-from gpu_util import initial_fields, rel_l2_all, run_pair
+from gpu_util import check_fields, initial_fields, rel_l2_all, run_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -18,19 +18,19 @@ EH3 = ["ex", "ey", "ez", "hx", "hy", "hz"]
 @pytest.mark.parametrize("n", [33, 130])
 def test_pcg_parity_2d(closure, lap, n):
     gf, of = run_pair(2, n, 0.5, 12, closure=closure, lap=lap, k=(3, 2), solver="pcg")
-    assert rel_l2_all(gf, of, EH2) <= 1e-12
+    check_fields(gf, of)
 
 
 def test_pcg_random_data_2d():
     gf, of = run_pair(2, 77, 0.45, 6, seed=1234, solver="pcg")
-    assert rel_l2_all(gf, of, EH2) <= 1e-12
+    check_fields(gf, of)
 
 
 @pytest.mark.parametrize("lap", ["tracked", "discrete"])
 @pytest.mark.parametrize("n", [8, 13])
 def test_pcg_parity_3d(lap, n):
     gf, of = run_pair(3, n, 0.4, 4, lap=lap, k=(2, 3, 4), solver="pcg")
-    assert rel_l2_all(gf, of, EH3) <= 1e-12
+    check_fields(gf, of)
 
 
 def _problem(n=64, steps=4, **kw):

@@ -11,7 +11,7 @@ form is built for.
 import numpy as np
 import pytest
 
-from gpu_util import initial_fields, rel_l2, rel_l2_all, run_pair
+from gpu_util import check_fields, initial_fields, rel_l2, rel_l2_all, run_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -22,9 +22,7 @@ EH = ["ez", "hx", "hy"]
 @pytest.mark.parametrize("lap", ["tracked", "discrete"])
 def test_strip_oracle_parity(n, lap):
     gf, of = run_pair(2, n, 0.5, 6, closure="paper" if n % 2 else "reflect", lap=lap, seed=100 + n)
-    assert rel_l2_all(gf, of, EH) <= 1e-12
-    if "lz" in gf:
-        assert rel_l2(gf["lz"], of["lz"]) <= 1e-9
+    check_fields(gf, of)
 
 
 @pytest.mark.parametrize("sweeps", [2, 3, 4, 6, 7, 8])
@@ -48,45 +46,57 @@ def test_strip_sweep_counts(sweeps):
 @pytest.mark.parametrize("cfl", [0.2, 0.35, 0.58])
 def test_strip_cfl(cfl):
     gf, of = run_pair(2, 120, cfl, 5, seed=7)
-    assert rel_l2_all(gf, of, EH) <= 1e-12
+    check_fields(gf, of)
 
 
-def test_strip_matches_tiles_large():
-    # N = 2048 (many strips and segments): strips (0, 4) against the
-    # 128 x 4 column tiles (3), random data, a few steps
+def test_strip_matches_tiles_and_oracle_large():
+    # N = 2048 (many strips and segments): strips (0, 4) against the oracle
+    # element by element and against the 128 x 4 column tiles (3), random
+    # data, a few steps
+    import oracle
     from paper_2306_17263_amd import Problem
-    n = 2048
+    n, steps = 2048, 3
     init = initial_fields(2, n, 0.5, seed=21)
     out = {}
     for shape in (3, 0, 4):
         p = Problem(2, n, 0.5, tile_x=shape)
         for name in p.fields():
             p.set(name, init[name])
-        p.step(3)
+        p.step(steps)
         out[shape] = {a: p.get(a) for a in p.fields()}
         p.close()
+    o = oracle.OracleProblem(2, n, 0.5)
+    for name in init:
+        o.set(name, init[name])
+    o.step(steps)
+    of = {a: o.get(a) for a in out[0]}
     for shape in (0, 4):
+        check_fields(out[shape], of)
         assert rel_l2_all(out[shape], out[3], EH) <= 1e-13, shape
         assert rel_l2(out[shape]["lz"], out[3]["lz"]) <= 1e-10
 
 
 def test_strip_many_rounds_large_grid():
     # N = 8192: the strip plan needs several rounds of the resident wave
-    # slots; one step against the 128 x 4 column tiles
+    # slots; one step against the oracle (element by element) and the
+    # 128 x 4 column tiles
+    import oracle
     from paper_2306_17263_amd import Problem
     n = 8192
-    rng = np.random.default_rng(8192)
-    init = None
+    init = initial_fields(2, n, 0.5, seed=8192)
     out = {}
     for shape in (3, 0):
         p = Problem(2, n, 0.5, tile_x=shape)
-        if init is None:
-            init = {a: rng.normal(size=p.shape(a)) for a in p.fields()}
         for name in p.fields():
             p.set(name, init[name])
         p.step(1)
         out[shape] = {a: p.get(a) for a in EH}
         p.close()
+    o = oracle.OracleProblem(2, n, 0.5)
+    for name in init:
+        o.set(name, init[name])
+    o.step(1)
+    check_fields(out[0], {a: o.get(a) for a in EH})
     assert rel_l2_all(out[0], out[3], EH) <= 1e-13
 
 
