@@ -220,6 +220,25 @@ c4m_status c4m_batch_tables_bytes(int32_t count, size_t* bytes);
 c4m_status c4m_batch_create_from(c4m_problem* const* probs, int32_t count, void* d_tables,
                                  size_t bytes, void* hip_stream, c4m_batch** out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): advance
+ * the fields `fields[f]` (device pointers indexed by c4m_field, in the
+ * layout of c4m_set_field; every field the configuration carries must be
+ * given, the others are ignored; with the carried Laplacian the l arrays
+ * too) by nsteps steps in place.  The problem's workspace (padded fields,
+ * G_E, temporaries, tables, counters) is a 64 MiB static device array, one
+ * per device, held until the process ends; the call allocates no device
+ * memory, runs the same kernels as c4m_create / c4m_set_field / c4m_step /
+ * c4m_get_field on a caller workspace (same results, bit for bit), and
+ * returns when the fields are written.  ENOMEM for a configuration whose
+ * c4m_workspace_bytes exceeds 64 MiB (2D up to n = 1150 or so, 3D up to
+ * n = 76), EINVAL with C4M_FLAG_PROFILE, errors of c4m_set_field otherwise.
+ * Calls on one device share the array: the library serialises calls of one
+ * process on a device; the array keeps the last call's contents, and each
+ * call clears what must start at zero. */
+c4m_status c4m_step_fields_noalloc(const c4m_config* cfg, double* const* fields, int64_t nsteps,
+                                   void* hip_stream);
+
 const char* c4m_status_string(c4m_status s);
 const char* c4m_last_error(void);
 

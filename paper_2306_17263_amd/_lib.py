@@ -24,7 +24,7 @@ EXPORTS = [
     "c4m_set_field", "c4m_set_boundary", "c4m_get_field", "c4m_step", "c4m_get_info", "c4m_destroy",
     "c4m_batch_workspace_bytes", "c4m_batch_create", "c4m_batch_problem", "c4m_batch_step",
     "c4m_batch_destroy", "c4m_batch_tables_bytes", "c4m_batch_create_from",
-    "c4m_status_string", "c4m_last_error",
+    "c4m_step_fields_noalloc", "c4m_status_string", "c4m_last_error",
 ]
 
 
@@ -85,6 +85,7 @@ def load():
     lib.c4m_batch_destroy.argtypes = [vp]
     lib.c4m_batch_tables_bytes.argtypes = [i32, ctypes.POINTER(sz)]
     lib.c4m_batch_create_from.argtypes = [ctypes.POINTER(vp), i32, vp, sz, vp, ctypes.POINTER(vp)]
+    lib.c4m_step_fields_noalloc.argtypes = [cfgp, ctypes.POINTER(vp), i64, vp]
     for name in EXPORTS:
         if name in ("c4m_status_string", "c4m_last_error"):
             continue
