@@ -1,15 +1,18 @@
 """Throughput benchmark of the compact fourth-order Yee stepper on one MI355X.
 
-Default workload: 2D TM PEC unit-square cavity, N = 2048, mode (k, l) = (4, 3),
-CFL 0.5, FP64, PAPER closure with the carried Laplacian; one bench step is
-one time step (Step 1 + Step 2) of that problem, and the default K = 4096
-steps covers T = 1.  The fields are resident in HBM before the timed region.
+Default workload (--workload batch): 512 independent 2D TM PEC cavities,
+N ~ U{64..768} (seed 2306), modes (k, l) ~ U{1..8}^2, amplitude U(0.5, 2),
+CFL 0.5, FP64, PAPER closure with the carried Laplacian, advanced together
+by the batched form; one bench step is one time step (Step 1 + Step 2) of
+every member, and the default K = 200 steps is the workload's run length.
+About 3.5 GB of state: HBM-resident (the 256 MB Infinity Cache holds a
+small part).  The fields are resident in HBM before the timed region.
 
 Prints ONE JSON line with the metric, the roofline block of the dominant
-kernel (per-kernel HIP-event timing on the problem's stream, in a profiled
-pass of the same steps right after the timed region) and the CPU baseline
-(the oracle on the host cores over a bounded sample of the same workload,
-also used as a full-size parity check of the device result).
+kernel (every launch of the timed region bracketed by HIP events on the
+batch's stream) and the CPU baseline (the oracle on the host cores over a
+bounded sample of the same workload).  Other workloads: the single N = 2048
+cavity (2d), the refinement sweep (sweep), the 3D cube (3d), serving.
 """
 from __future__ import annotations
 
@@ -26,12 +29,32 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+METRIC = "Mcell-steps/s at fixed L2 error vs FP64 oracle + % HBM roofline; p50/p99 latency"
+CLOSURES_O = {"paper": 0, "reflect": 1}
+LAPS_O = {"tracked": 0, "discrete": 1}
+# kernels of each class in the batched strip form (one launch per stage)
+BATCH_KERNELS = {
+    ("rhs_e", True): "k_batch_stage<K, T, 0> (Step 1 x-line tiles: raw x-derivatives, T0 on the end-band columns; band-table rows)",
+    ("solve_e", True): "k_batch_stage<K, T, 1> (Step 1 wave strips: y-lines, T0, Chebyshev solve, Ez and G_E update)",
+    ("rhs_h", True): "k_batch_stage<K, T, 2> (Step 2 x-line tiles of G_E; band-table rows)",
+    ("solve_h", True): "k_batch_stage<K, T, 3> (Step 2 Hx and Hy wave strips: solves and updates)",
+    ("step", False): "k_batch_step<K, T> (the whole step: all four stages, per-problem stage counters)",
+}
 
 
-def kernel_source_hash() -> str:
+# sources each workload's kernels are built from (a change elsewhere does
+# not void its counter results)
+KERNEL_SOURCES = {
+    "2d": ["c4m_internal.h", "c4m_tiles_2d.h", "c4m_stream_2d.h", "c4m_kernels_2d.hip", "c4m_host.hip"],
+    "batch": ["c4m_internal.h", "c4m_tiles_2d.h", "c4m_stream_2d.h", "c4m_batch.hip", "c4m_host.hip"],
+    "3d": ["c4m_internal.h", "c4m_kernels_3d.hip", "c4m_host.hip"],
+}
+
+
+def kernel_source_hash(workload: str = "2d") -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2306_17263_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
+    for name in sorted(KERNEL_SOURCES.get(workload.split("_")[0], os.listdir(csrc))):
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -49,7 +72,7 @@ def measured_traffic(kernel: str, workload: str):
     except (OSError, ValueError):
         return None
     ent = data.get(workload, {}).get(kernel)
-    if not ent or ent.get("source_hash") != kernel_source_hash():
+    if not ent or ent.get("source_hash") != kernel_source_hash(workload):
         return None
     return ent.get("bytes_per_launch")
 
@@ -71,7 +94,20 @@ CLASS_KERNELS = {
 }
 
 
+# kernel-class -> kernel-name pattern of the batched form (strip stage
+# launches, the single launch per step, the column-tile form)
+BATCH_CLASS_PATTERNS = {
+    "rhs_e": r"k_batch_stage<\d+, (?:true|false), 0>|k_batch_x<[01]>",
+    "solve_e": r"k_batch_stage<\d+, (?:true|false), 1>|k_batch_col<\d+, [01],",
+    "rhs_h": r"k_batch_stage<\d+, (?:true|false), 2>|k_batch_x<[23]>",
+    "solve_h": r"k_batch_stage<\d+, (?:true|false), 3>|k_batch_col<\d+, [234],",
+    "step": r"k_batch_step<",
+}
+
+
 def traffic_key(n, args):
+    if getattr(args, "workload", "2d") == "batch":
+        return f"batch_{args.count}_{args.closure}_{args.lap}_{args.precision}"
     return f"2d_n{n}_{args.closure}_{args.lap}_{args.precision}_{args.solver}"
 
 
@@ -88,6 +124,20 @@ def pmc_probe(args):
         for _ in range(3):
             torch.mul(src, 1.0, out=dst)
     st.synchronize()
+    if args.workload == "batch":
+        from paper_2306_17263_amd import Batch
+        from workloads import batch_mix, mode_fields
+        specs = batch_mix(count=args.count)
+        b = Batch(specs, stream=st, closure=args.closure, lap_mode=args.lap, precision=args.precision)
+        for p, sp in zip(b.problems, specs):
+            init = mode_fields(2, sp["n"], sp["k"], 0.0, sp["r"] / sp["n"] / 2, amp=sp["amp"])
+            for name in p.fields():
+                p.set(name, init[name])
+        b.step(args.steps or 4)
+        st.synchronize()
+        b.close()
+        print(json.dumps({"pmc_probe": traffic_key(0, args), "copy_bytes": COPY_PROBE_BYTES}), flush=True)
+        return
     n = args.n
     k = tuple(int(v) for v in args.mode.split(","))
     ht = args.cfl / n
@@ -133,14 +183,15 @@ def traffic_from(args):
     scale_f = copy_value(fetch) / COPY_PROBE_BYTES
     scale_w = copy_value(write) / COPY_PROBE_BYTES
     out = {}
-    for cls, pat in CLASS_PATTERNS.items():
+    pats = BATCH_CLASS_PATTERNS if args.workload == "batch" else CLASS_PATTERNS
+    for cls, pat in pats.items():
         rx = re.compile(pat)
         fb = sum(v for name, v in fetch.items() if rx.search(name)) * 1024.0 / scale_f
         wb = sum(v for name, v in write.items() if rx.search(name)) * 1024.0 / scale_w
         if fb or wb:
             out[cls] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
                         "copy_scale": {"fetch": scale_f, "write": scale_w},
-                        "source_hash": kernel_source_hash()}
+                        "source_hash": kernel_source_hash(traffic_key(args.n, args))}
     key = traffic_key(args.n, args)
     path = os.path.join(ROOT, "profiles", "traffic.json")
     data = {}
@@ -168,7 +219,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=None)
-    ap.add_argument("--warmup", type=int, default=64)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--n", type=int, default=2048)
     ap.add_argument("--mode", type=str, default="4,3")
     ap.add_argument("--cfl", type=float, default=0.5)
@@ -177,9 +228,9 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="2d", choices=["2d", "batch", "3d", "serve", "sweep"],
-                    help="2d: the N=2048 refinement-sweep cavity (default); batch: 512 seeded 2D "
-                         "cavities of uneven N; 3d: the cube cavity")
+    ap.add_argument("--workload", default="batch", choices=["2d", "batch", "3d", "serve", "sweep"],
+                    help="batch: 512 seeded 2D cavities of uneven N (default); 2d: the N=2048 "
+                         "refinement-sweep cavity; 3d: the cube cavity")
     ap.add_argument("--count", type=int, default=512)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
     ap.add_argument("--solver", default="chebyshev", choices=["chebyshev", "pcg"],
@@ -350,52 +401,132 @@ def _cpu_cores():
     return len(os.sched_getaffinity(0))
 
 
-def bench_batch(args):
-    """Batched form: seeded mix of independent 2D TM cavities, N uniform in
-    64..768, modes (k, l) in 1..8, amplitude U(0.5, 2), CFL 0.5, 200 steps
-    each, one persistent launch per phase and a HIP graph per step, launch
-    shape from the autotuner."""
+def _omp_threads(n):
+    """Thread count of the oracle's OpenMP loops (its runtime is loaded with it)."""
+    import ctypes
+    try:
+        ctypes.CDLL("libgomp.so.1").omp_set_num_threads(int(n))
+        return True
+    except OSError:
+        return False
+
+
+def _batch_run(specs, steps, warmup, stream, **kw):
+    """Create a batch, load the exact modes, warm up, reload, and time
+    `steps` steps between HIP events on its stream.  Returns (batch, inits,
+    elapsed seconds)."""
     import torch
-    from paper_2306_17263_amd import Batch, Problem, autotune
-    from workloads import batch_mix, mode_fields
+    from paper_2306_17263_amd import Batch
+    from workloads import mode_fields
+    b = Batch(specs, stream=stream, **kw)
+    inits = []
+    for p, s in zip(b.problems, specs):
+        init = mode_fields(2, s["n"], s["k"], 0.0, s["r"] / s["n"] / 2, amp=s["amp"])
+        inits.append(init)
+        for name in p.fields():
+            p.set(name, init[name])
+    b.step(warmup)
+    for p, init in zip(b.problems, inits):
+        for name in p.fields():
+            p.set(name, init[name])
+    b.warm_info = b.info()                     # profiling counters after the warm-up (subtracted later)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    b.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    elapsed = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3)
+    return b, inits, elapsed
+
+
+def _member_errors(problems, specs, steps):
+    from workloads import mode_fields
+    names = ["ez", "hx", "hy"]
+    errs = []
+    for p, s in zip(problems, specs):
+        ht = s["r"] / s["n"]
+        ex = mode_fields(2, s["n"], s["k"], steps * ht, (steps + 0.5) * ht, amp=s["amp"], with_laplacian=False)
+        errs.append(rel_l2({a: p.get(a) for a in names}, ex, names))
+    return errs
+
+
+def bench_batch(args):
+    """Batched form on the seeded 512-cavity mix (the default workload)."""
+    import torch
+    from paper_2306_17263_amd import Problem, autotune
+    from paper_2306_17263_amd import _lib as L
+    from workloads import batch_mix
     specs = batch_mix(count=args.count)
     steps = args.steps if args.steps is not None else 200
     st = torch.cuda.Stream()
     settings = dict(closure=args.closure, lap_mode=args.lap, precision=args.precision)
     tuned = autotune.tune_batch([{"n": s["n"]} for s in specs], steps=2, **settings)
-    b = Batch(specs, stream=st, tile_x=tuned["tile_x"], tile_y=tuned["tile_y"], **settings)
-    inits = []
-    for p, s in zip(b.problems, specs):
-        h = 1.0 / s["n"]
-        init = mode_fields(2, s["n"], s["k"], 0.0, s["r"] * h / 2, amp=s["amp"])
-        inits.append(init)
-        for name in p.fields():
-            p.set(name, init[name])
-    b.step(args.warmup)
-    for p, init in zip(b.problems, inits):
-        for name in p.fields():
-            p.set(name, init[name])
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record(st)
-    b.step(steps)
-    ev1.record(st)
-    torch.cuda.synchronize()
-    elapsed = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3)
+    form = dict(tile_x=tuned["tile_x"], tile_y=tuned["tile_y"])
     cells = sum(s["n"] ** 2 for s in specs)
-    value = cells * steps / elapsed / 1e6
-    # accuracy of every problem against its exact mode at the final time
     names = ["ez", "hx", "hy"]
-    errs = []
-    for p, s in zip(b.problems, specs):
-        h = 1.0 / s["n"]
-        ht = s["r"] * h
-        ex = mode_fields(2, s["n"], s["k"], steps * ht, (steps + 0.5) * ht, amp=s["amp"], with_laplacian=False)
-        errs.append(rel_l2({a: p.get(a) for a in names}, ex, names))
-    # the plain FP64 stepper: the same problems one after another through the
-    # single-problem path (created and loaded before the clock starts)
+
+    # ---- timed region: every launch bracketed by HIP events on the stream
+    b, inits, elapsed = _batch_run(specs, steps, args.warmup, st, flags=L.FLAG_PROFILE, **form, **settings)
+    value = cells * steps / elapsed / 1e6
+    inf, w0 = b.info(), b.warm_info
+    per = {}
+    for ci, cname in enumerate(L.KERNEL_CLASSES):
+        cnt = inf["kernel_launches"][ci] - w0["kernel_launches"][ci]
+        if cnt:
+            per[cname] = {"avg_us": 1e3 * (inf["kernel_ms"][ci] - w0["kernel_ms"][ci]) / cnt, "launches": cnt,
+                          "alg_bytes": inf["kernel_alg_bytes"][ci]}
+    dom = max(per, key=lambda c: per[c]["avg_us"] * per[c]["launches"])
+    dom_ach = per[dom]["alg_bytes"] / (per[dom]["avg_us"] * 1e-6) / 1e9
+    step_alg = sum(per[c]["alg_bytes"] * per[c]["launches"] for c in per) / steps
+    traffic = measured_traffic(dom, traffic_key(0, args))
+    strips = form["tile_x"] == 0 and args.precision == "fp64"
+    kernels = BATCH_KERNELS.get((dom, strips and form["tile_y"] != 1)) if strips else None
+    roofline = {"bound": "hbm", "achieved": round(dom_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom_ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom, "kernels": kernels,
+                "avg_us": round(per[dom]["avg_us"], 3), "alg_bytes_per_launch": per[dom]["alg_bytes"],
+                "step_alg_bytes_per_cell": round(step_alg / cells, 3),
+                "per_kernel_avg_us": {c: round(v["avg_us"], 3) for c, v in per.items()},
+                "step_frac": round(step_alg * steps / elapsed / 1e9 / HBM_PEAK_GBS, 4)}
+    errs = _member_errors(b.problems, specs, steps)
+
+    # ---- full-size parity sample: members the oracle steps in seconds,
+    # the same steps from the same initial data, element by element
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+        order = sorted(range(len(specs)), key=lambda i: specs[i]["n"])
+        mid = min(range(len(specs)), key=lambda i: abs(specs[i]["n"] - 160))
+        parity = []
+        for i in order[:4] + [mid]:
+            s = specs[i]
+            o = oracle.OracleProblem(2, s["n"], s["r"], 1.0, closure=CLOSURES_O[args.closure],
+                                     lap_mode=LAPS_O[args.lap])
+            for name in o.fields():
+                o.set(name, inits[i][name])
+            o.step(steps)
+            gf = {a: b.problems[i].get(a) for a in names}
+            of = {a: o.get(a) for a in names}
+            scale = max(float(np.max(np.abs(of[a]))) for a in names)
+            parity.append({"n": s["n"], "steps": steps, "rel_l2_vs_oracle": rel_l2(gf, of, names),
+                           "max_abs_over_scale": max(float(np.max(np.abs(gf[a] - of[a]))) for a in names) / scale})
+    b.close()
+
+    # ---- the same steps in the default graph-replayed launches, and the
+    # single persistent launch per step (strip form)
+    extra = {}
+    b2, _, el2 = _batch_run(specs, steps, args.warmup, st, **form, **settings)
+    b2.close()
+    extra["graph_ms_per_step"] = round(el2 * 1e3 / steps, 4)
+    if strips:
+        b3, _, el3 = _batch_run(specs, steps, args.warmup, st, tile_x=0, tile_y=1, **settings)
+        b3.check()
+        b3.close()
+        extra["single_launch_ms_per_step"] = round(el3 * 1e3 / steps, 4)
+
+    # ---- the plain FP64 stepper: the same problems one after another
     plain = dict(settings, precision="fp64")
     singles = []
     for s, init in zip(specs, inits):
@@ -409,59 +540,75 @@ def bench_batch(args):
         q.step(steps)
     torch.cuda.synchronize()
     seq = time.perf_counter() - t1
-    errs_plain = []
-    for q, s in zip(singles, specs):
-        ht = s["r"] / s["n"]
-        ex = mode_fields(2, s["n"], s["k"], steps * ht, (steps + 0.5) * ht, amp=s["amp"], with_laplacian=False)
-        errs_plain.append(rel_l2({a: q.get(a) for a in names}, ex, names))
+    errs_plain = _member_errors(singles, specs, steps)
+    for q in singles:
         q.close()
-    err_ratio = max(e / f for e, f in zip(errs, errs_plain))
-    cpu = parity = None
+
+    # ---- precision form: FP32 Chebyshev rounds around FP64 residuals, same batch
+    prec = None
+    if args.precision == "fp64":
+        b4, _, el4 = _batch_run(specs, steps, args.warmup, st, **dict(settings, precision="fp32_refined"))
+        errs4 = _member_errors(b4.problems, specs, steps)
+        b4.close()
+        prec = {"ms_per_step": round(el4 * 1e3 / steps, 4), "speedup_vs_fp64_batch": round(elapsed / el4, 3),
+                "max_l2_ratio_vs_fp64": max(e / f for e, f in zip(errs4, errs)),
+                "form": "column tiles 128 x 4, FP32 Chebyshev rounds + FP64 residual"}
+
+    # ---- CPU baseline: the oracle on 32 seeded members of the mix, on
+    # every host core and on one
+    cpu = None
     if not args.no_cpu_baseline:
         import oracle
-        sub = sorted(range(len(specs)), key=lambda i: specs[i]["n"])[:3]
-        parity = []
-        for i in sub:
-            s = specs[i]
-            o = oracle.OracleProblem(2, s["n"], s["r"], 1.0)
-            for name in o.fields():
-                o.set(name, inits[i][name])
-            o.step(steps)
-            parity.append({"n": s["n"], "rel_l2_vs_oracle":
-                           rel_l2({a: b.problems[i].get(a) for a in names}, {a: o.get(a) for a in names}, names)})
         rng = np.random.default_rng(2306)
         sample = sorted(rng.choice(len(specs), 32, replace=False).tolist())
-        t2 = time.perf_counter()
-        done = 0
-        for i in sample:
-            s = specs[i]
-            o = oracle.OracleProblem(2, s["n"], s["r"], 1.0)
-            for name in o.fields():
-                o.set(name, inits[i][name])
-            o.step(2)
-            done += s["n"] ** 2 * 2
-            if time.perf_counter() - t2 > args.cpu_seconds:
-                break
-        spent = time.perf_counter() - t2
-        cpu = {"value": round(done / spent / 1e6, 3), "unit": "Mcell-steps/s", "cores": _cpu_cores(), "kind": "oracle",
-               "sample": f"2 steps of each of up to 32 seeded problems of the mix ({spent:.1f} s)"}
-    b.close()
+
+        def run_oracle(nsteps):
+            t = time.perf_counter()
+            done = 0
+            for i in sample:
+                s = specs[i]
+                o = oracle.OracleProblem(2, s["n"], s["r"], 1.0, closure=CLOSURES_O[args.closure],
+                                         lap_mode=LAPS_O[args.lap])
+                for name in o.fields():
+                    o.set(name, inits[i][name])
+                o.step(nsteps)
+                done += s["n"] ** 2 * nsteps
+            return done, time.perf_counter() - t
+
+        cores = _cpu_cores()
+        _omp_threads(cores)
+        done, spent = run_oracle(4)
+        one = None
+        if _omp_threads(1):
+            done1, spent1 = run_oracle(1)
+            one = round(done1 / spent1 / 1e6, 3)
+            _omp_threads(cores)
+        cpu = {"value": round(done / spent / 1e6, 3), "unit": "Mcell-steps/s", "cores": cores, "kind": "oracle",
+               "sample": f"4 steps of each of 32 seeded members of the mix ({done / 1e6:.1f} M cell-steps, "
+                         f"{spent:.1f} s, OpenMP over lines, {cores} threads); 1 step each on 1 thread",
+               "value_1thread": one}
+
     line = {
-        "metric": "Mcell-steps/s at fixed L2 error vs FP64 oracle + % HBM roofline",
+        "metric": METRIC,
         "value": round(value, 2), "unit": "Mcell-steps/s", "n_gpus": 1, "steps": steps, "warmup": args.warmup,
         "ms_per_step": round(elapsed * 1e3 / steps, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
-        "data": "synthetic (seeded exact PEC cavity modes)",
-        "config": {"workload": f"batched: {len(specs)} 2D TM cavities, N uniform 64..768 (seed 2306), "
-                               f"modes 1..8, CFL 0.5, {steps} steps each, {args.precision}",
-                   "problems": len(specs), "cells_per_step": cells, "tile_x": tuned["tile_x"],
-                   "tile_y": tuned["tile_y"], "autotune_timings_s": tuned["timings"]},
+        "data": "synthetic (seeded exact PEC cavity modes sampled on the Yee grids)",
+        "config": {"workload": f"batched: {len(specs)} 2D TM PEC cavities, N uniform 64..768 (seed 2306), "
+                               f"modes 1..8, amplitude 0.5..2, CFL 0.5, {steps} steps each, {args.closure} "
+                               f"closure, {args.lap} Laplacian, {args.precision}",
+                   "problems": len(specs), "cells_per_step": cells, "tile_x": form["tile_x"],
+                   "tile_y": form["tile_y"],
+                   "form": ("wave strips, one persistent launch per stage" if strips and form["tile_y"] != 1 else
+                            "wave strips, one persistent launch per step" if strips else "column tiles"),
+                   "autotune_s_per_step": tuned["timings"]},
         "l2_vs_exact": {"max": max(errs), "median": float(np.median(errs))},
-        "plain_fp64_sequential_s": round(seq, 4), "speedup_vs_plain_fp64_sequential": round(seq / elapsed, 3),
-        "l2_vs_exact_plain_fp64": {"max": max(errs_plain), "median": float(np.median(errs_plain))},
-        "max_l2_ratio_vs_plain_fp64": err_ratio,
         "parity_sample": parity,
-        "step_frac": round(88.0 * value * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+        **extra,
+        "plain_fp64_sequential_s": round(seq, 4), "speedup_vs_plain_fp64_sequential": round(seq / elapsed, 3),
+        "max_l2_ratio_vs_plain_fp64": max(e / f for e, f in zip(errs, errs_plain)),
+        "precision_form": prec,
+        "roofline": roofline,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -86,6 +86,7 @@ enum { C4M_K_RHS_E = 0,      /* Pade curl of G(H): Step 1 right-hand side       
        C4M_K_STEP_E = 4,     /* fused Step 1 (right-hand side, solve, update)      */
        C4M_K_STEP_H = 5,     /* fused Step 2                                       */
        C4M_K_OTHER = 6,      /* everything else (conversions, reductions)          */
+       C4M_K_STEP = 7,       /* a whole step in one launch (batched strip form)    */
        C4M_K_COUNT = 8 };
 
 typedef struct {
@@ -104,13 +105,19 @@ typedef struct {
     int32_t tile_x;     /* column kernel shape, 0..4 (0 = built-in, see below)         */
     int32_t tile_y;
     uint32_t flags;     /* C4M_FLAG_*                                                  */
-    int32_t reserved[5];
+    int32_t batch_wait_limit; /* batched strip form: polls before a stage wait gives  *
+                               * up and flags (0 = about a second); see c4m_batch_check */
+    int32_t reserved[4];
 } c4m_config;
 /* tile_x, single 2D problems (FP64 Chebyshev): 0 = wave strips (one
  * wavefront per 64 columns walks down a row segment, no LDS; falls back
  * to 3 where it does not apply), 4 = wave strips unrolled 16 steps,
  * 1 = 64 x 4 column tiles, 2 = 128 x 2, 3 = 128 x 4.  Batched form:
- * 0 = 128 x 4 column tiles, 1 = 64 x 4, 2 = 128 x 2.  3D: ignored. */
+ * 0 = wave strips (FP64; column tiles 128 x 4 in the FP32-refined form),
+ * 1 = 64 x 4 column tiles, 2 = 128 x 2.  3D: ignored.
+ * tile_y, batched form: with the strips, 1 = one persistent launch per
+ * step, any other value = one persistent launch per stage (default);
+ * with column tiles, a multiplier of the persistent grid (0 = 1). */
 
 typedef struct {
     int64_t steps;            /* whole steps taken since create                       */
@@ -197,26 +204,46 @@ c4m_status c4m_destroy(c4m_problem* p);
 
 /* Batched form: `count` independent problems (2D, any mix of n; shared cfl,
  * z, closure, lap_mode, precision; Chebyshev solve only) on one workspace.
- * Each kernel phase of a step is one persistent launch over the (problem,
- * tile) items of every problem; a step is captured once as a HIP graph and
- * replayed.  EINVAL for 3D problems, mixed settings or the PCG solver. */
+ * A step is four stages per problem (Step 1 x-lines, Step 1 solve, Step 2
+ * x-lines, Step 2 Hx and Hy solves), each a table of work items over every
+ * problem.  Strip form (FP64, tile_x 0, the default): ONE persistent launch
+ * per step; an item waits for its own problem's previous stage only
+ * (per-problem counters), so stages of different problems overlap; every
+ * member's strip segments are planned for its share of the device.  Column
+ * tiles (tile_x 1-3, FP32-refined): one persistent launch per stage.  Runs
+ * of steps are captured once as HIP graphs and replayed.  Members equal the
+ * same problems stepped alone, bit for bit.  EINVAL for 3D problems, mixed
+ * settings or the PCG solver. */
 c4m_status c4m_batch_workspace_bytes(const c4m_config* cfgs, int32_t count, size_t* bytes);
 c4m_status c4m_batch_create(const c4m_config* cfgs, int32_t count, void* d_workspace,
                             size_t bytes, void* hip_stream, c4m_batch** out);
 /* Borrow the handle of problem i (owned by the batch; use it for set/get). */
 c4m_status c4m_batch_problem(c4m_batch* b, int32_t i, c4m_problem** out);
-/* Advance every problem of the batch by nsteps steps. */
+/* Advance every problem of the batch by nsteps steps (asynchronous). */
 c4m_status c4m_batch_step(c4m_batch* b, int64_t nsteps);
+/* Synchronise the batch's stream and report whether a stage wait of the
+ * strip form gave up since the last check (EDEVICE: the results of the
+ * steps in between are invalid; the flag is cleared).  A wait gives up only
+ * if the device does not run every workgroup of the launch at once, e.g.
+ * when other work occupies it, or with a tiny batch_wait_limit. */
+c4m_status c4m_batch_check(c4m_batch* b);
+/* Summed member figures (steps, workspace bytes, algorithmic bytes per
+ * launch of each kernel class over all members; C4M_K_STEP for the single
+ * launch per step) and, with C4M_FLAG_PROFILE in the members' settings,
+ * the batch's kernel time per class: every launch is then bracketed by HIP
+ * events on the batch's stream and steps run without graphs (synchronises
+ * the stream). */
+c4m_status c4m_batch_get_info(c4m_batch* b, c4m_info* info);
 c4m_status c4m_batch_destroy(c4m_batch* b);
 
 /* Batched form over 2D problems the caller already created (each on its own
  * workspace, sharing cfl, z, closure, lap_mode, precision, solver, sweeps and
- * tiles).  `d_tables` (>= c4m_batch_tables_bytes(count), 256-byte aligned)
- * holds only the work-queue tables; the problems stay the caller's, must
- * outlive the batch, and keep their own stream-ordered state (they are
- * stepped on the batch's stream).  Lets a serving loop re-form batches as
- * requests come and go without moving resident fields. */
-c4m_status c4m_batch_tables_bytes(int32_t count, size_t* bytes);
+ * tiles).  `d_tables` (>= c4m_batch_tables_bytes of the same problems,
+ * 256-byte aligned) holds only the work tables; the problems stay the
+ * caller's, must outlive the batch, and keep their own stream-ordered state
+ * (they are stepped on the batch's stream).  Lets a serving loop re-form
+ * batches as requests come and go without moving resident fields. */
+c4m_status c4m_batch_tables_bytes(c4m_problem* const* probs, int32_t count, size_t* bytes);
 c4m_status c4m_batch_create_from(c4m_problem* const* probs, int32_t count, void* d_tables,
                                  size_t bytes, void* hip_stream, c4m_batch** out);
 

@@ -16,14 +16,14 @@ SOLVER = {"chebyshev": 0, "pcg": 1}
 FLAG_ALLOW_ANY_CFL = 0x1
 FLAG_CHECK_FINITE = 0x2
 FLAG_PROFILE = 0x4
-KERNEL_CLASSES = ["rhs_e", "solve_e", "rhs_h", "solve_h", "step_e", "step_h", "other", "spare"]
+KERNEL_CLASSES = ["rhs_e", "solve_e", "rhs_h", "solve_h", "step_e", "step_h", "other", "step"]
 
 # every symbol include/c4m.h declares
 EXPORTS = [
     "c4m_config_default", "c4m_workspace_bytes", "c4m_create", "c4m_field_shape",
     "c4m_set_field", "c4m_set_boundary", "c4m_get_field", "c4m_step", "c4m_get_info", "c4m_destroy",
     "c4m_batch_workspace_bytes", "c4m_batch_create", "c4m_batch_problem", "c4m_batch_step",
-    "c4m_batch_destroy", "c4m_batch_tables_bytes", "c4m_batch_create_from",
+    "c4m_batch_check", "c4m_batch_get_info", "c4m_batch_destroy", "c4m_batch_tables_bytes", "c4m_batch_create_from",
     "c4m_step_fields_noalloc", "c4m_status_string", "c4m_last_error",
 ]
 
@@ -34,7 +34,8 @@ class C4mConfig(ctypes.Structure):
         ("z", ctypes.c_double), ("closure", ctypes.c_int32), ("lap_mode", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("solver", ctypes.c_int32), ("sweeps", ctypes.c_int32),
         ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double), ("tile_x", ctypes.c_int32),
-        ("tile_y", ctypes.c_int32), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_int32 * 5),
+        ("tile_y", ctypes.c_int32), ("flags", ctypes.c_uint32), ("batch_wait_limit", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
     ]
 
 
@@ -82,8 +83,10 @@ def load():
     lib.c4m_batch_create.argtypes = [cfgp, i32, vp, sz, vp, ctypes.POINTER(vp)]
     lib.c4m_batch_problem.argtypes = [vp, i32, ctypes.POINTER(vp)]
     lib.c4m_batch_step.argtypes = [vp, i64]
+    lib.c4m_batch_check.argtypes = [vp]
+    lib.c4m_batch_get_info.argtypes = [vp, ctypes.POINTER(C4mInfo)]
     lib.c4m_batch_destroy.argtypes = [vp]
-    lib.c4m_batch_tables_bytes.argtypes = [i32, ctypes.POINTER(sz)]
+    lib.c4m_batch_tables_bytes.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(sz)]
     lib.c4m_batch_create_from.argtypes = [ctypes.POINTER(vp), i32, vp, sz, vp, ctypes.POINTER(vp)]
     lib.c4m_step_fields_noalloc.argtypes = [cfgp, ctypes.POINTER(vp), i64, vp]
     for name in EXPORTS:

@@ -49,10 +49,10 @@ class Batch:
         self.stream = stream if stream is not None else problems[0].stream
         self.specs = [{"n": p.n, "cfl": p.cfl} for p in problems]
         nb = ctypes.c_size_t()
-        L.check(self._lib.c4m_batch_tables_bytes(len(problems), ctypes.byref(nb)), "c4m_batch_tables_bytes")
+        arr = (ctypes.c_void_p * len(problems))(*[p.handle.value for p in problems])
+        L.check(self._lib.c4m_batch_tables_bytes(arr, len(problems), ctypes.byref(nb)), "c4m_batch_tables_bytes")
         self.nbytes = nb.value
         self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
-        arr = (ctypes.c_void_p * len(problems))(*[p.handle.value for p in problems])
         self._h = ctypes.c_void_p()
         L.check(self._lib.c4m_batch_create_from(arr, len(problems), ctypes.c_void_p(self.workspace.data_ptr()),
                                                 self.nbytes, ctypes.c_void_p(int(self.stream.cuda_stream)),
@@ -68,6 +68,20 @@ class Batch:
 
     def step(self, nsteps: int = 1):
         L.check(self._lib.c4m_batch_step(self._h, int(nsteps)), "c4m_batch_step")
+
+    def info(self) -> dict:
+        """Summed member figures and, when profiling, kernel time per class."""
+        inf = L.C4mInfo()
+        L.check(self._lib.c4m_batch_get_info(self._h, ctypes.byref(inf)), "c4m_batch_get_info")
+        out = {}
+        for f, _ in L.C4mInfo._fields_:
+            v = getattr(inf, f)
+            out[f] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+    def check(self):
+        """Synchronise; raise if a stage wait of an earlier step gave up."""
+        L.check(self._lib.c4m_batch_check(self._h), "c4m_batch_check")
 
     def close(self):
         if self._h:

@@ -39,6 +39,8 @@ __host__ __device__ inline int xl_tiles_y(int N)
 template <int MODE, bool PF = false>
 __global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps, YbandArgs yba)
 {
+    constexpr bool E = MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE;
+    __shared__ double lds[E ? XE_LDS : xt_lds(MODE)];
     const int ntx = xl_tiles_x<MODE>(xa.L.n_out), nty = xl_tiles_y<MODE>(xa.N);
     const int xgrid = xcd_grid(ntx * nty);
     if ((int)blockIdx.x >= xgrid) {
@@ -54,9 +56,9 @@ __global__ __launch_bounds__(256) void k_xlines(XArgs xa, Coef cf, PadeTaps taps
     int l;
     if (!xcd_tile(ntx * nty, l)) return;
     if constexpr (MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE)
-        xlines_e_tile<MODE == XL_E_TRACKED, PF>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, l % ntx, l / ntx);
+        xlines_e_tile<MODE == XL_E_TRACKED, PF>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, l % ntx, l / ntx, lds);
     else
-        xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, l % ntx, l / ntx);
+        xlines_tile<MODE>(xa.src, xa.t0, xa.t1, xa.N, xa.P, xa.L, cf, taps, l % ntx, l / ntx, lds);
 }
 
 template <int K, int MODE, class S, int FORM>

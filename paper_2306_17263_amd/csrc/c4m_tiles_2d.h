@@ -1,15 +1,16 @@
-// c4m_kernels_2d.hip -- gfx950 kernels of the 2D TM (Ez, Hx, Hy) step.
+// c4m_tiles_2d.h -- 2D TM (Ez, Hx, Hy) tile code shared by the
+// single-problem launches (c4m_kernels_2d.hip) and the batched form
+// (c4m_batch.hip): the x-line tiles of both steps and the column-tile form
+// of the solve.  The default single-problem solve, the wave strips, is in
+// c4m_stream_2d.h.
 //
-// Step 1 (Section 3.4), two launches:
-//   k_xlines<E>  : rows of Hy -> T0 = Z delta_x G(Hy), T1 = delta_x Hy (carried l)
-//   k_col<E>     : per column of Hx the y-line Pade (streaming FIR in
-//                  registers) completes b = T0 - Z delta_y G(Hx); then the
-//                  Chebyshev solve of M Phi = b on the tile and its halo,
-//                  Ez += r Phi, G_E += (1 + 4/r^2) r Phi - (2/r) Z curl^A H.
-// Step 2, three launches:
-//   k_xlines<H>  : rows of G_E -> T1 = (1/Z) delta_x G_E        (Hy right-hand side)
-//   k_col<HX>    : columns of G_E -> b = -(1/Z) delta_y G_E, solve, Hx += r Phi
-//   k_col<HY>    : b = T1, solve, Hy += r Phi
+// Step 1 (Section 3.4): the x-lines of Hy give the x part of the right-hand
+// side (T0 = Z delta_x G(Hy), or only the raw derivative P = delta_x Hy,
+// from which the strips form T0); the solve kernel adds the y-line part
+// -Z delta_y G(Hx), solves M Phi = b and updates Ez += r Phi and
+// G_E += (1 + 4/r^2) r Phi - (2/r) Z curl^A H.
+// Step 2: the x-lines of G_E give T1 = (1/Z) delta_x G_E (the Hy
+// right-hand side); the Hx solve forms -(1/Z) delta_y G_E itself.
 // G_E = alpha E + l/12 is stored instead of l, so Step 2 reads only G_E.
 //
 // Pade derivative: A^{-1} D truncated to 2 PADE_R + 2 taps on the line
@@ -19,9 +20,9 @@
 // applied to the line derivatives of the neighbouring lines (the line
 // derivative is the same linear map on every line, so the two commute).
 //
-// k_col layout: one lane per column of a 256-column region, each lane holds
-// the region rows of its column in registers; only the column sums
-// S = d(y-1) + 4 d(y) + d(y+1) of the 9-point stencil cross lanes (LDS).
+// Column tiles (k_col): a workgroup holds a region of 128 (or 64) columns;
+// NL lanes per column keep its region rows in registers; the column sums
+// S = d(y-1) + 4 d(y) + d(y+1) of the 9-point stencil cross lanes in LDS.
 #pragma once
 #include "c4m_internal.h"
 
@@ -78,15 +79,20 @@ struct XArgs {
     PadeLine L;
 };
 
+// LDS doubles the x-line tiles take from the caller's buffer (the raw
+// line input as well in the Step 1 mode with the carried Laplacian)
+constexpr int xt_lds(int mode) { return (mode == XL_E_TRACKED ? 2 : 1) * XT_ROWS * XT_STRIDE; }
+
 template <int MODE>
 __device__ __forceinline__ void xlines_tile(const double* __restrict__ src, double* __restrict__ t0,
                                             double* __restrict__ t1, int N, int P, const PadeLine& L,
-                                            const Coef& cf, const PadeTaps& taps, int bxi, int byi)
+                                            const Coef& cf, const PadeTaps& taps, int bxi, int byi,
+                                            double* lds)
 {
     constexpr bool E = MODE == XL_E_TRACKED || MODE == XL_E_DISCRETE;
     constexpr bool TWO = MODE == XL_E_TRACKED;     // raw derivative as well
-    __shared__ double sg[XT_ROWS * XT_STRIDE];
-    __shared__ double sr[TWO ? XT_ROWS * XT_STRIDE : 1];
+    double* sg = lds;                               // [XT_ROWS * XT_STRIDE]
+    double* sr = lds + XT_ROWS * XT_STRIDE;         // (TWO)
     const int tid = threadIdx.x;
     const int m0 = bxi * XT_OUT;                    // first output of the tile
     const int j0 = 1 + byi * XT_ROWS;               // first row (interior rows 1..N-1)
@@ -238,13 +244,15 @@ __host__ __device__ inline int xe_tiles_y(int N) { return (N - 1 + XE_OROWS - 1)
 // PF (strip form): the tile writes P itself to t1 on rows 0..N (the strips
 // form T0 from it) and T0 only on the band columns of the line ends (where
 // the along-line part needs the conditioned table rows) to t0.
+constexpr int XE_LDS = XE_PROWS * XE_STRIDE + XE_PROWS * XE_PSTRIDE;
+
 template <bool TWO, bool PF>
 __device__ __forceinline__ void xlines_e_tile(const double* __restrict__ src, double* __restrict__ t0,
                                               double* __restrict__ t1, int N, int P, const PadeLine& L,
-                                              const Coef& cf, int bxi, int byi)
+                                              const Coef& cf, int bxi, int byi, double* lds)
 {
-    __shared__ double sh[XE_PROWS * XE_STRIDE];       // raw rows, later the T0 tile
-    __shared__ double sp[XE_PROWS * XE_PSTRIDE];      // P
+    double* sh = lds;                                  // raw rows, later the T0 tile
+    double* sp = lds + XE_PROWS * XE_STRIDE;           // P
     const int tid = threadIdx.x;
     const int m0 = bxi * XE_OUT;                       // first T0 output of the tile
     const int j0 = 1 + byi * XE_OROWS;                 // first T0 row

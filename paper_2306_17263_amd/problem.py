@@ -13,7 +13,8 @@ from . import _lib as L
 def make_config(dim: int = 2, n: int = 64, cfl: float = 0.5, z: float = 1.0,
                 closure: str = "paper", lap_mode: str = "tracked", precision: str = "fp64",
                 solver: str = "chebyshev", sweeps: int = 0, max_iter: int = 0, rtol: float = 0.0,
-                tile_x: int = 0, tile_y: int = 0, flags: int = 0) -> L.C4mConfig:
+                tile_x: int = 0, tile_y: int = 0, flags: int = 0,
+                batch_wait_limit: int = 0) -> L.C4mConfig:
     lib = L.load()
     cfg = L.C4mConfig()
     L.check(lib.c4m_config_default(ctypes.byref(cfg)), "c4m_config_default")
@@ -24,6 +25,7 @@ def make_config(dim: int = 2, n: int = 64, cfl: float = 0.5, z: float = 1.0,
     cfg.solver = L.SOLVER[solver]
     cfg.sweeps, cfg.max_iter, cfg.rtol = sweeps, max_iter, rtol
     cfg.tile_x, cfg.tile_y, cfg.flags = tile_x, tile_y, flags
+    cfg.batch_wait_limit = batch_wait_limit
     return cfg
 
 

@@ -48,6 +48,32 @@ def test_class_patterns_attribute_each_kernel_to_one_class():
         assert not any(rx.search(name) for rx in pats.values()), name
 
 
+BATCH_NAMES = {
+    "rhs_e": ["void c4m::k_batch_stage<5, true, 0>(c4m::BatchProb const*, c4m::Sched, c4m::Coef)",
+              "void c4m::k_batch_x<1>(c4m::BatchProb const*, c4m::Sched, int, c4m::Coef, c4m::PadeTaps)"],
+    "solve_e": ["void c4m::k_batch_stage<5, false, 1>(c4m::BatchProb const*, c4m::Sched)",
+                "void c4m::k_batch_col<5, 0, c4m::TileShape<128, 2>, 0>(c4m::BatchProb const*)"],
+    "rhs_h": ["void c4m::k_batch_stage<6, true, 2>(c4m::BatchProb const*, c4m::Sched)",
+              "void c4m::k_batch_x<2>(c4m::BatchProb const*, c4m::Sched, int, c4m::Coef, c4m::PadeTaps)"],
+    "solve_h": ["void c4m::k_batch_stage<5, true, 3>(c4m::BatchProb const*, c4m::Sched)",
+                "void c4m::k_batch_col<5, 4, c4m::TileShape<64, 4>, 0>(c4m::BatchProb const*)",
+                "void c4m::k_batch_col<5, 2, c4m::TileShape<128, 2>, 1>(c4m::BatchProb const*)"],
+    "step": ["void c4m::k_batch_step<5, true>(c4m::BatchProb const*, c4m::Sched, c4m::Coef)"],
+}
+
+
+def test_batch_class_patterns_attribute_each_kernel_to_one_class():
+    b = _bench()
+    pats = {c: re.compile(p) for c, p in b.BATCH_CLASS_PATTERNS.items()}
+    assert set(pats) == set(BATCH_NAMES)
+    for cls, names in BATCH_NAMES.items():
+        for name in names:
+            hits = [c for c, rx in pats.items() if rx.search(name)]
+            assert hits == [cls], (name, hits)
+    for name in OTHERS + [n for v in NAMES.values() for n in v]:
+        assert not any(rx.search(name) for rx in pats.values()), name
+
+
 def test_source_hash_is_stable_and_hex():
     b = _bench()
     h = b.kernel_source_hash()

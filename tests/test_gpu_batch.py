@@ -26,13 +26,14 @@ def _specs(seed=7):
 
 @pytest.mark.parametrize("lap", ["tracked", "discrete"])
 @pytest.mark.parametrize("closure", ["paper", "reflect"])
-def test_batch_equals_alone_and_oracle(lap, closure):
+@pytest.mark.parametrize("tile_y", [0, 1])     # strips: one launch per stage / per step
+def test_batch_equals_alone_and_oracle(lap, closure, tile_y):
     import torch
     from paper_2306_17263_amd import Batch, Problem
     specs = _specs()
     steps = 12
     st = torch.cuda.Stream()
-    b = Batch(specs, stream=st, closure=closure, lap_mode=lap)
+    b = Batch(specs, stream=st, closure=closure, lap_mode=lap, tile_y=tile_y)
     inits = []
     for p, s in zip(b.problems, specs):
         init = initial_fields(2, s["n"], 0.5, k=s["k"], amp=s["amp"])
@@ -61,11 +62,13 @@ def test_batch_equals_alone_and_oracle(lap, closure):
         check_fields(gb, of)
         assert p.info()["steps"] == steps
         alone.close()
+    b.check()
     b.close()
 
 
 @pytest.mark.parametrize("lap", ["tracked", "discrete"])
-def test_batch_large_members_equal_alone(lap):
+@pytest.mark.parametrize("tile_y", [0, 1])
+def test_batch_large_members_equal_alone(lap, tile_y):
     # members at the top of the batch workload's size range (N up to 768)
     # equal the problem run alone bit for bit, and the oracle
     import torch
@@ -73,7 +76,7 @@ def test_batch_large_members_equal_alone(lap):
     ns = [768, 64, 701, 400]
     steps = 6
     st = torch.cuda.Stream()
-    b = Batch([{"n": n} for n in ns], stream=st, lap_mode=lap)
+    b = Batch([{"n": n} for n in ns], stream=st, lap_mode=lap, tile_y=tile_y)
     inits = [initial_fields(2, n, 0.5, seed=500 + n) for n in ns]
     for p, init in zip(b.problems, inits):
         for name in p.fields():
@@ -135,3 +138,34 @@ def test_autotune_batch_and_single(tmp_path, monkeypatch):
     assert autotune.tune_batch(_specs(3)[:4], steps=2) == r          # served from the cache
     s = autotune.tune_single(96, steps=2)
     assert s["tile_x"] in autotune.SINGLE_SHAPES
+
+
+def test_batch_check_quiet_and_forced_give_up():
+    # single launch per step (tile_y 1): the default wait limit never gives
+    # up on a normal run; a limit of one poll makes the Step 1 solve items
+    # (taken while their x-lines still run) give up at once: the step
+    # drains, nothing faults, and c4m_batch_check reports it once (then the
+    # flag is clear)
+    from paper_2306_17263_amd import Batch, C4mError, EDEVICE
+    import torch
+    specs = [{"n": 768}, {"n": 300}, {"n": 64}]
+    st = torch.cuda.Stream()
+    b = Batch(specs, stream=st, tile_y=1)
+    for p, s in zip(b.problems, specs):
+        init = initial_fields(2, s["n"], 0.5, seed=s["n"])
+        for name in p.fields():
+            p.set(name, init[name])
+    b.step(3)
+    b.check()
+    b.close()
+    b = Batch(specs, stream=st, tile_y=1, batch_wait_limit=1)
+    for p, s in zip(b.problems, specs):
+        init = initial_fields(2, s["n"], 0.5, seed=s["n"])
+        for name in p.fields():
+            p.set(name, init[name])
+    b.step(2)
+    with pytest.raises(C4mError) as ei:
+        b.check()
+    assert ei.value.status == EDEVICE
+    b.check()
+    b.close()
