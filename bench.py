@@ -94,6 +94,21 @@ CLASS_KERNELS = {
 }
 
 
+# 3D kernel classes: the Pade line terms of each half-step and the
+# Chebyshev passes of both (the same kernels), per component launch group
+CLASS_PATTERNS_3D = {
+    "rhs_e": r"k_term3<\d, [01]>",
+    "rhs_h": r"k_term3<\d, [23]>",
+    "solve": r"k_cheb3t<",
+}
+KERNELS_3D = {
+    "rhs": "k_term3<axis, mode> (one Pade line term of a right-hand side; 4 per E component, 2 per H)",
+    "solve": "k_cheb3t<...> (one application of M in the three-term Chebyshev recurrence; K per component, "
+             "the last writes the field and G_E updates)",
+}
+# component launch groups per step of each 3D class
+CALLS_3D = {"rhs_e": 3, "rhs_h": 3, "solve": 6}
+
 # kernel-class -> kernel-name pattern of the batched form (strip stage
 # launches, the single launch per step, the column-tile form)
 BATCH_CLASS_PATTERNS = {
@@ -106,6 +121,9 @@ BATCH_CLASS_PATTERNS = {
 
 
 def traffic_key(n, args):
+    if getattr(args, "workload", "2d") == "3d":
+        n3 = args.n if args.n != 2048 else 256
+        return f"3d_n{n3}_{args.closure}_{args.lap}_{args.precision}_{args.solver}"
     if getattr(args, "workload", "2d") == "batch":
         return f"batch_{args.count}_{args.closure}_{args.lap}_{args.precision}"
     return f"2d_n{n}_{args.closure}_{args.lap}_{args.precision}_{args.solver}"
@@ -124,6 +142,20 @@ def pmc_probe(args):
         for _ in range(3):
             torch.mul(src, 1.0, out=dst)
     st.synchronize()
+    if args.workload == "3d":
+        from workloads import mode_fields
+        n = args.n if args.n != 2048 else 256
+        init = mode_fields(3, n, (2, 3, 4), 0.0, 0.2 / n)
+        prob = Problem(3, n, 0.4, closure=args.closure, lap_mode=args.lap, precision=args.precision,
+                       solver=args.solver, stream=st)
+        for name in prob.fields():
+            prob.set(name, init[name])
+        st.synchronize()
+        prob.step(args.steps or 2)
+        st.synchronize()
+        prob.close()
+        print(json.dumps({"pmc_probe": f"3d_n{n}", "copy_bytes": COPY_PROBE_BYTES}), flush=True)
+        return
     if args.workload == "batch":
         from paper_2306_17263_amd import Batch
         from workloads import batch_mix, mode_fields
@@ -166,6 +198,22 @@ def _counter_means(folder):
     return {k: sum(v) / len(v) for k, v in acc.items()}
 
 
+def _counter_sums(folder):
+    """Sum and count of the counter values per kernel name."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)
+    if not files:
+        raise SystemExit(f"no counter_collection.csv under {folder}")
+    acc = {}
+    with open(files[0]) as f:
+        for row in csv.DictReader(f):
+            key = row.get("Kernel_Name", "")
+            s, c = acc.get(key, (0.0, 0))
+            acc[key] = (s + float(row["Counter_Value"]), c + 1)
+    return acc
+
+
 def traffic_from(args):
     """HBM bytes per launch of each kernel class: FETCH_SIZE and WRITE_SIZE
     (KiB per dispatch) divided by what the same counters read for the copy
@@ -183,6 +231,27 @@ def traffic_from(args):
     scale_f = copy_value(fetch) / COPY_PROBE_BYTES
     scale_w = copy_value(write) / COPY_PROBE_BYTES
     out = {}
+    if args.workload == "3d":
+        # every dispatch of a class, per component launch group
+        import re as _re
+        fs, ws = _counter_sums(args.traffic_from[0]), _counter_sums(args.traffic_from[1])
+        steps = args.steps or 2
+        for cls, pat in CLASS_PATTERNS_3D.items():
+            rx = _re.compile(pat)
+            groups = CALLS_3D[cls] * steps
+            fb = sum(v[0] for name, v in fs.items() if rx.search(name)) * 1024.0 / scale_f / groups
+            wb = sum(v[0] for name, v in ws.items() if rx.search(name)) * 1024.0 / scale_w / groups
+            out[cls] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                        "copy_scale": {"fetch": scale_f, "write": scale_w},
+                        "source_hash": kernel_source_hash("3d")}
+        key = traffic_key(args.n, args)
+        path = os.path.join(ROOT, "profiles", "traffic.json")
+        data = json.load(open(path)) if os.path.exists(path) else {}
+        data[key] = out
+        with open(path, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        print(json.dumps({key: out}, indent=1))
+        return
     pats = BATCH_CLASS_PATTERNS if args.workload == "batch" else CLASS_PATTERNS
     for cls, pat in pats.items():
         rx = re.compile(pat)
@@ -577,15 +646,16 @@ def bench_batch(args):
 
         cores = _cpu_cores()
         _omp_threads(cores)
-        done, spent = run_oracle(4)
+        done, spent = run_oracle(16)
         one = None
         if _omp_threads(1):
-            done1, spent1 = run_oracle(1)
+            done1, spent1 = run_oracle(2)
             one = round(done1 / spent1 / 1e6, 3)
             _omp_threads(cores)
         cpu = {"value": round(done / spent / 1e6, 3), "unit": "Mcell-steps/s", "cores": cores, "kind": "oracle",
-               "sample": f"4 steps of each of 32 seeded members of the mix ({done / 1e6:.1f} M cell-steps, "
-                         f"{spent:.1f} s, OpenMP over lines, {cores} threads); 1 step each on 1 thread",
+               "sample": f"16 steps of each of 32 seeded members of the mix ({done / 1e6:.1f} M cell-steps, "
+                         f"{spent:.1f} s, OpenMP over lines, {cores} threads); 2 steps each on 1 thread "
+                         f"({spent1:.1f} s)" if one else f"16 steps of each of 32 seeded members ({spent:.1f} s)",
                "value_1thread": one}
 
     line = {
@@ -615,7 +685,9 @@ def bench_batch(args):
 
 
 def bench_3d(args):
-    """3D PEC cube cavity, mode (2,3,4), CFL 0.4, T = 0.5."""
+    """3D PEC cube cavity, mode (2,3,4), e = (-1,2,-1)/sqrt 6, CFL 0.4,
+    T = 0.5 (1.25 N steps); every kernel-class launch group of the timed
+    region bracketed by HIP events on the problem's stream."""
     import torch
     from paper_2306_17263_amd import Problem
     from paper_2306_17263_amd import _lib as L
@@ -628,12 +700,13 @@ def bench_3d(args):
     st = torch.cuda.Stream()
     settings = dict(closure=args.closure, lap_mode=args.lap, precision=args.precision, solver=args.solver)
     init = mode_fields(3, n, (2, 3, 4), 0.0, ht / 2)
-    p = Problem(3, n, r, stream=st, **settings)
+    p = Problem(3, n, r, stream=st, flags=L.FLAG_PROFILE, **settings)
     for name in p.fields():
         p.set(name, init[name])
     p.step(min(args.warmup, 4))
     for name in p.fields():
         p.set(name, init[name])
+    w0 = p.info()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -648,26 +721,37 @@ def bench_3d(args):
     names = ["ex", "ey", "ez", "hx", "hy", "hz"]
     ex = mode_fields(3, n, (2, 3, 4), steps * ht, (steps + 0.5) * ht, with_laplacian=False)
     l2 = rel_l2({a: p.get(a) for a in names}, ex, names)
+    inf = p.info()
     p.close()
-    pp = Problem(3, n, r, stream=st, flags=L.FLAG_PROFILE, **settings)
-    for name in pp.fields():
-        pp.set(name, init[name])
-    pp.step(2)
-    inf = pp.info()
-    pp.close()
-    per = {c: 1e3 * inf["kernel_ms"][i] / inf["kernel_launches"][i] for i, c in enumerate(L.KERNEL_CLASSES)
-           if inf["kernel_launches"][i]}
+    per = {}
+    for ci, cname in enumerate(L.KERNEL_CLASSES):
+        cnt = inf["kernel_launches"][ci] - w0["kernel_launches"][ci]
+        if cnt:
+            per[cname] = {"avg_us": 1e3 * (inf["kernel_ms"][ci] - w0["kernel_ms"][ci]) / cnt, "launches": cnt,
+                          "alg_bytes": inf["kernel_alg_bytes"][ci]}
+    dom = max(per, key=lambda c: per[c]["avg_us"] * per[c]["launches"])
+    dom_ach = per[dom]["alg_bytes"] / (per[dom]["avg_us"] * 1e-6) / 1e9
+    step_alg = sum(per[c]["alg_bytes"] * per[c]["launches"] for c in per) / steps
+    key = f"3d_n{n}_{args.closure}_{args.lap}_{args.precision}_{args.solver}"
+    traffic = measured_traffic("solve" if dom.startswith("solve") else dom, key)
+    roofline = {"bound": "hbm", "achieved": round(dom_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(dom_ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "kernels": KERNELS_3D.get(dom.split("_")[0]), "avg_us": round(per[dom]["avg_us"], 3),
+                "alg_bytes_per_launch": per[dom]["alg_bytes"],
+                "launch": "one component's launch group of the class (3 per step and half-step class)",
+                "step_alg_bytes_per_cell": round(step_alg / cells, 3),
+                "per_kernel_avg_us": {c: round(v["avg_us"], 3) for c, v in per.items()},
+                "step_frac": round(step_alg * steps / elapsed / 1e9 / HBM_PEAK_GBS, 4)}
     line = {
-        "metric": "Mcell-steps/s at fixed L2 error vs FP64 oracle + % HBM roofline",
+        "metric": METRIC,
         "value": round(value, 2), "unit": "Mcell-steps/s", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 4),
         "ms_per_step": round(elapsed * 1e3 / steps, 4), "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic (exact PEC cube-cavity mode)",
-        "config": {"workload": f"3D PEC cube cavity N={n}, mode (2,3,4), CFL 0.4, T=0.5 ({steps} steps), "
+        "config": {"workload": f"3D PEC cube cavity N={n}, mode (2,3,4), CFL 0.4, T={steps * ht:g} ({steps} steps), "
                                f"{args.closure} closure, {args.lap} Laplacian, {args.precision}", "n": n},
         "l2_vs_exact": l2,
-        "per_class_avg_us": {c: round(v, 1) for c, v in per.items()},
-        "step_frac": round(192.0 * value * 1e6 / 1e9 / HBM_PEAK_GBS, 4),
+        "roofline": roofline,
     }
     print(json.dumps(line), flush=True)
 

@@ -74,9 +74,9 @@ enum { C4M_SOLVER_CHEBYSHEV = 0, /* reduction-free Chebyshev on the closed-form 
 
 #define C4M_FLAG_ALLOW_ANY_CFL 0x1u   /* skip the CFL guard of create               */
 #define C4M_FLAG_CHECK_FINITE  0x2u   /* scan the fields for NaN/Inf after each call */
-#define C4M_FLAG_PROFILE       0x4u   /* time every kernel launch with HIP events on  *
-                                       * the problem's stream, waiting for each launch *
-                                       * before queuing the next (see c4m_info)        */
+#define C4M_FLAG_PROFILE       0x4u   /* time every launch (group) of a kernel class *
+                                       * with HIP events on the problem's stream (no   *
+                                       * host waits; c4m_get_info reads them)          */
 
 /* Kernel classes reported by the profiling counters of c4m_info. */
 enum { C4M_K_RHS_E = 0,      /* Pade curl of G(H): Step 1 right-hand side          */
@@ -190,7 +190,10 @@ c4m_status c4m_set_boundary(c4m_problem* p, c4m_field f, int32_t face, const dou
 c4m_status c4m_get_field(c4m_problem* p, c4m_field f, double* dst, int dst_on_device);
 
 /* Enqueue nsteps whole steps on the problem's stream (asynchronous);
- * nsteps = 0 does nothing.  With C4M_FLAG_CHECK_FINITE the call scans the
+ * nsteps = 0 does nothing.  Runs of up to 32 steps are captured once each
+ * as a HIP graph and replayed (the launch sequence of a step, Section 3.4
+ * Step 1 then Step 2); on the null stream, with C4M_FLAG_PROFILE, or while
+ * the caller captures the stream, the launches go to the stream directly.  With C4M_FLAG_CHECK_FINITE the call scans the
  * fields afterwards, waits, and returns ENONFINITE (sticky in c4m_info)
  * when a NaN or Inf is found. */
 c4m_status c4m_step(c4m_problem* p, int64_t nsteps);

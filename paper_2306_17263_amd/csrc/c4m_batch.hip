@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 #include <string.h>
 
+#include <math.h>
+
 #include <algorithm>
 #include <map>
 #include <string>
@@ -263,8 +265,13 @@ __device__ __forceinline__ void stage_finish(const Sched& sc, int stage)
 // A run of up to `take` items for the workgroup: [slot[0], slot[0] + slot[1]).
 // The same stages as separate launches (STAGE fixed): the launch boundary
 // orders the stages, so there are no waits or counts.
+// waves per SIMD each stage launch is compiled for: the strips need the
+// registers of three; the Step 1 x-line tiles fit four workgroups in the
+// LDS (the Step 2 tiles spill registers at five and run slower)
+constexpr int stage_wpe(int st) { return st == ST_XE ? 4 : BS_WPE; }
+
 template <int K, bool TRACKED, int STAGE>
-__global__ __launch_bounds__(SW_COLS * SW_WAVES) __attribute__((amdgpu_waves_per_eu(BS_WPE))) void k_batch_stage(
+__global__ __launch_bounds__(SW_COLS * SW_WAVES) __attribute__((amdgpu_waves_per_eu(stage_wpe(STAGE)))) void k_batch_stage(
     const BatchProb* __restrict__ bp, Sched sc, Coef cf, PadeTaps taps_xh, ChebSchedule cs)
 {
     constexpr bool XL = STAGE == ST_XE || STAGE == ST_XH;
@@ -657,14 +664,32 @@ c4m_status plan_layout(const c4m_config* cfgs, int count, bool strips_ok, Layout
         // the table holds a similar mix
         for (int k = 0; k < 2; ++k) {
             const int st = k == 0 ? ST_CE : ST_CH;
+            // cost bins of about 15 %, longest first; inside a bin the
+            // items of one problem, by segment, then strip, so the four
+            // waves of a workgroup walk neighbouring strips of one segment
+            // and share their halo columns in L1/L2
             struct C {
-                double c;
+                int bin, seg, strip;
                 Item it;
             };
             std::vector<C> all;
             for (int i = 0; i < count; ++i)
-                for (int l = 0; l < (int)ccost[k][i].size(); ++l) all.push_back(C{ccost[k][i][l], Item{i, l}});
-            std::stable_sort(all.begin(), all.end(), [](const C& a, const C& b) { return a.c > b.c; });
+                for (int l = 0; l < (int)ccost[k][i].size(); ++l) {
+                    const BatchProb& d = lay.probs[i];
+                    const int hy = k == 1 && l >= d.n_chx;           // Step 2: Hy strips after the Hx strips
+                    const StripPlan& pl = k == 0 ? d.plan[0] : d.plan[hy ? 2 : 1];
+                    int strip, y0, tr;
+                    bool up;
+                    pl.item(hy ? l - d.n_chx : l, strip, y0, tr, up);
+                    const int bin = (int)floor(log(std::max(ccost[k][i][l], 1.0)) / log(1.15));
+                    all.push_back(C{bin, y0 + hy * 65536, strip, Item{i, l}});
+                }
+            std::stable_sort(all.begin(), all.end(), [](const C& a, const C& b) {
+                if (a.bin != b.bin) return a.bin > b.bin;
+                if (a.it.p != b.it.p) return a.it.p < b.it.p;
+                if (a.seg != b.seg) return a.seg < b.seg;
+                return a.strip < b.strip;
+            });
             const int total = (int)all.size();
             const int per = (total + NXCD - 1) / NXCD;
             std::vector<Item>& out = lay.items[st];
@@ -1076,8 +1101,12 @@ c4m_status c4m_batch_step(c4m_batch* b, int64_t nsteps)
         c4m_status s = problem_prepare(p);
         if (s != C4M_OK) return s;
     }
-    if (b->base.flags & C4M_FLAG_PROFILE) {
-        // every launch timed by events on the stream, no graph
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    bool direct = (b->base.flags & C4M_FLAG_PROFILE) || !b->stream;
+    if (!direct && hipStreamIsCapturing(b->stream, &cap) != hipSuccess) direct = true;
+    if (direct || cap != hipStreamCaptureStatusNone) {
+        // profiled (every launch timed by events on the stream), the null
+        // stream (no capture), or captured by the caller: no graph
         for (int64_t t = 0; t < nsteps; ++t) {
             c4m_status s = launch_step(b);
             if (s != C4M_OK) return s;

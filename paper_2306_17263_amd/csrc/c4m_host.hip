@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -317,6 +318,8 @@ struct c4m_problem {
     double kernel_ms[C4M_K_COUNT] = {};
     int64_t kernel_launches[C4M_K_COUNT] = {};
     double alg_bytes[C4M_K_COUNT] = {};
+    std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;   // captured runs of steps
+    bool direct = false;                // launch steps without graphs (no-allocation call)
 };
 
 namespace {
@@ -492,10 +495,9 @@ c4m_status timed(c4m_problem* p, int cls, const char* what, F&& launch)
     hipError_t e = launch();
     if (e != hipSuccess) return hip_fail(e, what);
     if (prof) {
-        // Wait for the launch to finish before the next one is queued, so
-        // the event pair brackets this kernel alone.
+        // the stream runs the event, the launches and the event in order:
+        // the pair brackets these launches alone; nothing waits here
         if (hipEventRecord(r.b, p->stream) != hipSuccess) return fail(C4M_EDEVICE, "hipEventRecord");
-        if (hipEventSynchronize(r.b) != hipSuccess) return fail(C4M_EDEVICE, "hipEventSynchronize");
         p->pending.push_back(r);
     }
     return C4M_OK;
@@ -674,6 +676,66 @@ void set_alg_bytes(c4m_problem* p)
     }
     p->alg_bytes[C4M_K_STEP_E] = p->alg_bytes[C4M_K_RHS_E] + p->alg_bytes[C4M_K_SOLVE_E];
     p->alg_bytes[C4M_K_STEP_H] = p->alg_bytes[C4M_K_RHS_H] + p->alg_bytes[C4M_K_SOLVE_H];
+}
+
+// nsteps steps: runs of up to GRAPH_STEPS steps are captured once each as a
+// HIP graph and replayed; launches go to the stream directly when the
+// launches are profiled, the stream is the null stream (which cannot be
+// captured) or the caller is capturing the stream already.
+constexpr int64_t GRAPH_STEPS = 32;
+
+c4m_status run_steps(c4m_problem* p, int64_t nsteps)
+{
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    bool direct = (p->cfg.flags & C4M_FLAG_PROFILE) || !p->stream || p->direct;
+    if (!direct && hipStreamIsCapturing(p->stream, &cap) != hipSuccess) direct = true;
+    if (direct || cap != hipStreamCaptureStatusNone) {
+        for (int64_t t = 0; t < nsteps; ++t) {
+            c4m_status s = step_once(p);
+            if (s != C4M_OK) return s;
+            ++p->steps;
+        }
+        return C4M_OK;
+    }
+    int64_t left = nsteps;
+    while (left > 0) {
+        const int64_t len = std::min(left, GRAPH_STEPS);
+        auto it = p->graphs.find(len);
+        if (it == p->graphs.end()) {
+            hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+            c4m_status s = C4M_OK;
+            for (int64_t t = 0; t < len && s == C4M_OK; ++t) s = step_once(p);
+            hipGraph_t g = nullptr;
+            e = hipStreamEndCapture(p->stream, &g);
+            if (s != C4M_OK) {
+                if (g) (void)hipGraphDestroy(g);
+                return s;
+            }
+            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+            hipGraphExec_t x = nullptr;
+            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                (void)hipGraphDestroy(g);
+                return hip_fail(e, "hipGraphInstantiate");
+            }
+            it = p->graphs.emplace(len, std::make_pair(g, x)).first;
+        }
+        hipError_t e = hipGraphLaunch(it->second.second, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+        left -= len;
+        p->steps += len;
+    }
+    return C4M_OK;
+}
+
+void drop_graphs(c4m_problem* p)
+{
+    for (auto& kv : p->graphs) {
+        (void)hipGraphExecDestroy(kv.second.second);
+        (void)hipGraphDestroy(kv.second.first);
+    }
+    p->graphs.clear();
 }
 
 }  // namespace
@@ -962,11 +1024,8 @@ c4m_status c4m_step(c4m_problem* p, int64_t nsteps)
     if (nsteps == 0) return C4M_OK;
     c4m_status s = ensure_ge(p);
     if (s != C4M_OK) return s;
-    for (int64_t t = 0; t < nsteps; ++t) {
-        s = step_once(p);
-        if (s != C4M_OK) return s;
-        ++p->steps;
-    }
+    s = run_steps(p, nsteps);
+    if (s != C4M_OK) return s;
     if (p->cfg.flags & C4M_FLAG_CHECK_FINITE) {
         hipError_t e = hipMemsetAsync(p->counter, 0, sizeof(int), p->stream);
         for (int c = 0; c < 6 && e == hipSuccess; ++c)
@@ -1021,6 +1080,7 @@ c4m_status c4m_destroy(c4m_problem* p)
     if (!p) return fail(C4M_EINVAL, "null problem");
     if (p->owned_by_batch) return fail(C4M_ESTATE, "problem belongs to a batch");
     (void)flush_profile(p);
+    drop_graphs(p);
     delete p;
     return C4M_OK;
 }
@@ -1064,11 +1124,15 @@ c4m_status problem_create_owned(const c4m_config* cfg, void* ws, size_t bytes, h
 
 void problem_add_steps(c4m_problem* p, int64_t n) { p->steps += n; }
 
+// steps go to the stream directly (graph instantiation may allocate)
+void problem_set_direct(c4m_problem* p) { p->direct = true; }
+
 const c4m_config* problem_config(const c4m_problem* p) { return &p->cfg; }
 
 void problem_destroy_owned(c4m_problem* p)
 {
     (void)flush_profile(p);
+    drop_graphs(p);
     delete p;
 }
 }  // namespace c4m

@@ -16,6 +16,7 @@ constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
 static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
 c4m_status set_error(c4m_status s, const char* msg);   // c4m_host.hip
+void problem_set_direct(c4m_problem* p);                // c4m_host.hip
 
 namespace {
 
@@ -62,6 +63,7 @@ extern "C" c4m_status c4m_step_fields_noalloc(const c4m_config* cfg, double* con
     c4m_problem* p = nullptr;
     s = c4m_create(cfg, g_scratch[dev], NOALLOC_SCRATCH_BYTES, hip_stream, &p);
     if (s != C4M_OK) return s;
+    problem_set_direct(p);
     for (int i = 0; i < nf && s == C4M_OK; ++i) s = c4m_set_field(p, (c4m_field)ids[i], fields[ids[i]], 1);
     if (s == C4M_OK) s = c4m_step(p, nsteps);
     for (int i = 0; i < nf && s == C4M_OK; ++i) s = c4m_get_field(p, (c4m_field)ids[i], fields[ids[i]], 1);
