@@ -395,7 +395,7 @@ static int solve_m(const oc_problem* p, const comp_t* c, const double* b, double
 /* ------------------------------------------------------------------------ */
 /* Sources of the curl.                                                     */
 /* ------------------------------------------------------------------------ */
-enum { SRC_RAW = 0, SRC_G = 1 };
+enum { SRC_RAW = 0, SRC_G = 1, SRC_E_RAW = 2 };
 
 /* G u = alpha u + (h^2 Delta_h u)/12 at a point interior along node axes. */
 static double g_at(const oc_problem* p, const comp_t* c, const double* u, int i, int j, int k)
@@ -431,6 +431,7 @@ static double ge_at(const oc_problem* p, int s, int i, int j, int k)
 static double src_value(const oc_problem* p, int src, int kind, int i, int j, int k)
 {
     const comp_t* c = &p->comp[src];
+    if (src < 3 && kind == SRC_E_RAW) return p->f[src][ix(c, i, j, k)];   /* E itself */
     if (src < 3) return ge_at(p, src, i, j, k);               /* E sources: Step 2 */
     if (kind == SRC_RAW) return p->f[src][ix(c, i, j, k)];    /* H raw */
     return g_at(p, c, p->f[src], i, j, k);                      /* G(H): Step 1 */
@@ -605,6 +606,75 @@ int oc_half_step_h(oc_problem* p, double rs)
                 }
         free(b);
         free(phi);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Taylor start of H (Section 5.1, eq:talorh, J = 0): with H holding H(0)     */
+/* and E holding E(0), replace H by                                           */
+/*   H(h_tau/2) = H + a H_t + a^2/2 H_tt + a^3/6 H_ttt + a^4/24 H_tttt,      */
+/* a = h_tau/2, where (maxh, secondorderh and their derivatives)              */
+/*   H_t = -(1/Z) curl E,  H_tt = Delta H,  H_ttt = Delta H_t,               */
+/*   H_tttt = Delta H_tt.                                                      */
+/* Spatial derivatives: the scheme's Pade curl for curl E, the second-order  */
+/* Laplacian Delta_h of Definition def:operatorsP for Delta, with the ghost  */
+/* rules of Corollary cor:ghost_cor; on the walls an H component is normal   */
+/* to, all its time derivatives vanish (it is constant in time there).       */
+/* ------------------------------------------------------------------------ */
+
+/* h^2 Delta_h a at the points of component c off its node walls, 0 on them */
+static void lap5(const comp_t* c, const double* a, double* out)
+{
+    for (int k = 0; k < c->n[2]; ++k)
+        for (int j = 0; j < c->n[1]; ++j)
+            for (int i = 0; i < c->n[0]; ++i) {
+                double v = 0.0;
+                if (!on_node_wall(c, i, j, k))
+                    for (int d = 0; d < 3; ++d)
+                        if (c->active[d]) v += d2(c, a, d, i, j, k);
+                out[ix(c, i, j, k)] = v;
+            }
+}
+
+int oc_init_h_taylor(oc_problem* p)
+{
+    if (!p) return -1;
+    const double r = p->r, z = p->z;
+    for (int s = 3; s < 6; ++s) {
+        const comp_t* c = &p->comp[s];
+        if (!c->present) continue;
+        const size_t sz = comp_size(c);
+        double* cu = (double*)calloc(sz, sizeof(double));    /* curl^A E = -Z h H_t */
+        double* lh = (double*)calloc(sz, sizeof(double));    /* h^2 Delta_h H = h^2 H_tt */
+        double* lc = (double*)calloc(sz, sizeof(double));    /* h^2 Delta_h curl^A E */
+        double* llh = (double*)calloc(sz, sizeof(double));   /* h^4 Delta_h Delta_h H */
+        if (!cu || !lh || !lc || !llh) {
+            free(cu); free(lh); free(lc); free(llh);
+            return -2;
+        }
+        int rc = curl_component(p, 0, SRC_E_RAW, s, 1.0, cu);
+        if (rc) {
+            free(cu); free(lh); free(lc); free(llh);
+            return rc;
+        }
+        /* the curl on the wall points the component is normal to is zero
+         * (tangential E vanishes there); curl_component fills the unknowns only */
+        lap5(c, p->f[s], lh);
+        lap5(c, cu, lc);
+        lap5(c, lh, llh);
+        /* with a = h_tau/2 = r h/2:  a H_t = -(r/(2Z)) cu,  a^2/2 H_tt = (r^2/8) lh,
+         * a^3/6 H_ttt = -(r^3/(48 Z)) lc,  a^4/24 H_tttt = (r^4/384) llh */
+        double* hh = p->f[s];
+        for (int k = 0; k < c->n[2]; ++k)
+            for (int j = 0; j < c->n[1]; ++j)
+                for (int i = 0; i < c->n[0]; ++i) {
+                    if (on_node_wall(c, i, j, k)) continue;
+                    const size_t q = ix(c, i, j, k);
+                    hh[q] += -(r / (2.0 * z)) * cu[q] + (r * r / 8.0) * lh[q] - (r * r * r / (48.0 * z)) * lc[q] +
+                             (r * r * r * r / 384.0) * llh[q];
+                }
+        free(cu); free(lh); free(lc); free(llh);
     }
     return 0;
 }

@@ -47,6 +47,10 @@ int oc_step(oc_problem* p, long nsteps);
 /* Single half-steps with a signed CFL number (negative runs backwards). */
 int oc_half_step_e(oc_problem* p, double r_signed);
 int oc_half_step_h(oc_problem* p, double r_signed);
+/* Taylor start (Section 5.1, eq:talorh, J = 0): with E at tau = 0 and H at
+ * tau = 0 set, replace H by H at tau = h_tau/2 (Pade curl for curl E,
+ * second-order Laplacian Delta_h for the higher terms). */
+int oc_init_h_taylor(oc_problem* p);
 /* CG iterations used by the last solve, and the maximum so far. */
 int oc_cg_stats(const oc_problem* p, int* last, int* max_seen);
 

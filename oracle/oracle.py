@@ -53,6 +53,7 @@ def load():
     lib.oc_apply_m.argtypes = [P, ctypes.c_int, D, D]
     lib.oc_solve_m.argtypes = [P, ctypes.c_int, D, D]
     lib.oc_rhs.argtypes = [P, ctypes.c_int, D]
+    lib.oc_init_h_taylor.argtypes = [P]
     _lib = lib
     return lib
 
@@ -150,6 +151,11 @@ class OracleProblem:
         if it < 0:
             raise ValueError(name)
         return x
+
+    def init_h_taylor(self):
+        """Replace H (at tau = 0) by H at tau = h_tau/2 (eq:talorh)."""
+        if self._lib.oc_init_h_taylor(self._p):
+            raise RuntimeError("oc_init_h_taylor")
 
     def rhs(self, name: str) -> np.ndarray:
         out = np.empty(self.shape(name))
