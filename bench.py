@@ -297,7 +297,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="batch", choices=["2d", "batch", "3d", "serve", "sweep"],
+    ap.add_argument("--workload", default="batch", choices=["2d", "batch", "3d", "serve", "sweep", "nc"],
                     help="batch: 512 seeded 2D cavities of uneven N (default); 2d: the N=2048 "
                          "refinement-sweep cavity; 3d: the cube cavity")
     ap.add_argument("--count", type=int, default=512)
@@ -326,6 +326,8 @@ def main():
         return bench_serve(args)
     if args.workload == "sweep":
         return bench_sweep(args)
+    if args.workload == "nc":
+        return bench_nc(args)
 
     import torch
     if not torch.cuda.is_available():
@@ -752,6 +754,77 @@ def bench_3d(args):
                                f"{args.closure} closure, {args.lap} Laplacian, {args.precision}", "n": n},
         "l2_vs_exact": l2,
         "roofline": roofline,
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_nc(args):
+    """The comparison scheme NC (Section 5.2) on the 2D cavity of the
+    refinement sweep (N = 2048, mode (4, 3), CFL 0.5, T = 1), next to the
+    compact scheme on the same grid and steps: throughput and the L2 error
+    against the exact mode of each (accuracy per cost)."""
+    import torch
+    from paper_2306_17263_amd import Problem
+    from paper_2306_17263_amd import _lib as L
+    n = args.n
+    k = tuple(int(v) for v in args.mode.split(","))
+    cfl = args.cfl
+    ht = cfl / n
+    steps = args.steps if args.steps is not None else int(round(1.0 / ht))
+    names = ["ez", "hx", "hy"]
+    init = exact_fields(n, k, 0.0, ht / 2)
+    st = torch.cuda.Stream()
+    runs = {}
+    per = {}
+    for scheme in ("nc", "c4"):
+        p = Problem(2, n, cfl, stream=st, scheme=scheme)
+        for name in p.fields():
+            p.set(name, init[name])
+        p.step(args.warmup)
+        for name in p.fields():
+            p.set(name, init[name])
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(st)
+        p.step(steps)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        el = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3)
+        ex = exact_fields(n, k, steps * ht, (steps + 0.5) * ht)
+        runs[scheme] = {"ms_per_step": round(el * 1e3 / steps, 5), "l2_vs_exact": rel_l2({a: p.get(a) for a in names}, ex, names),
+                        "mcell_steps_per_s": round(n * n * steps / el / 1e6, 2)}
+        if scheme == "nc":
+            value = n * n * steps / el / 1e6
+        p.close()
+    # per-kernel averages from a separate profiled run (events around every launch)
+    p = Problem(2, n, cfl, stream=st, scheme="nc", flags=L.FLAG_PROFILE)
+    for name in p.fields():
+        p.set(name, init[name])
+    p.step(args.warmup)
+    w0 = p.info()
+    p.step(min(steps, args.profile_steps))
+    inf = p.info()
+    for ci, cname in enumerate(L.KERNEL_CLASSES):
+        cnt = inf["kernel_launches"][ci] - w0["kernel_launches"][ci]
+        if cnt:
+            per[cname] = {"avg_us": 1e3 * (inf["kernel_ms"][ci] - w0["kernel_ms"][ci]) / cnt,
+                          "alg_bytes": inf["kernel_alg_bytes"][ci]}
+    p.close()
+    dom = max(per, key=lambda c: per[c]["avg_us"])
+    ach = per[dom]["alg_bytes"] / (per[dom]["avg_us"] * 1e-6) / 1e9
+    line = {
+        "metric": METRIC, "value": round(value, 2), "unit": "Mcell-steps/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": runs["nc"]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic (exact PEC cavity mode sampled on the Yee grids)",
+        "config": {"workload": f"NC scheme, 2D TM PEC cavity N={n}, mode {k}, CFL {cfl}, {steps} steps", "n": n},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dom,
+                     "kernels": "k_nc_e (Ez update) / k_nc_h (Hx and Hy updates)",
+                     "avg_us": round(per[dom]["avg_us"], 3), "alg_bytes_per_launch": per[dom]["alg_bytes"],
+                     "per_kernel_avg_us": {c: round(v["avg_us"], 3) for c, v in per.items()}},
+        "runs": runs,
+        "error_ratio_nc_over_c4": runs["nc"]["l2_vs_exact"] / runs["c4"]["l2_vs_exact"],
     }
     print(json.dumps(line), flush=True)
 

@@ -68,6 +68,12 @@ enum { C4M_LAP_TRACKED = 0,      /* carry l = h^2 Delta E as in Step 1          
        C4M_LAP_DISCRETE = 1 };   /* recompute l = L5 E (second-order Laplacian)     */
 enum { C4M_FP64 = 0,             /* all arithmetic in FP64                          */
        C4M_FP32_REFINED = 1 };   /* FP32 sweeps, FP64 residuals and state           */
+enum { C4M_SCHEME_C4 = 0,        /* the compact fourth-order scheme (Section 3.4)   */
+       C4M_SCHEME_NC = 1 };      /* the non-compact comparison scheme NC (Section   *
+                                  * 5.2): the Yee update with stencil K4 at a = 0,  *
+                                  * one-sided rows at the walls; 2D, FP64, no solve; *
+                                  * closure, lap_mode, solver, sweeps ignored;      *
+                                  * CFL bound 6/(7 sqrt 2) (leapfrog with K4)       */
 enum { C4M_SOLVER_CHEBYSHEV = 0, /* reduction-free Chebyshev on the closed-form     *
                                   * spectral bounds of M (Appendix A.2)             */
        C4M_SOLVER_PCG = 1 };     /* Jacobi-preconditioned CG with device dot products */
@@ -107,7 +113,8 @@ typedef struct {
     uint32_t flags;     /* C4M_FLAG_*                                                  */
     int32_t batch_wait_limit; /* batched strip form: polls before a stage wait gives  *
                                * up and flags (0 = about a second); see c4m_batch_check */
-    int32_t reserved[4];
+    int32_t scheme;     /* C4M_SCHEME_* (0 = the compact scheme)                       */
+    int32_t reserved[3];
 } c4m_config;
 /* tile_x, single 2D problems (FP64 Chebyshev): 0 = wave strips (one
  * wavefront per 64 columns walks down a row segment, no LDS; falls back
@@ -197,6 +204,16 @@ c4m_status c4m_get_field(c4m_problem* p, c4m_field f, double* dst, int dst_on_de
  * fields afterwards, waits, and returns ENONFINITE (sticky in c4m_info)
  * when a NaN or Inf is found. */
 c4m_status c4m_step(c4m_problem* p, int64_t nsteps);
+
+/* Taylor start (Section 5.1, eq:talorh, J = 0): with E set at tau = 0 and
+ * H set at tau = 0 (not yet stepped), replace H by H at tau = h_tau/2:
+ *   H + a H_t + a^2/2 H_tt + a^3/6 H_ttt + a^4/24 H_tttt,  a = h_tau/2,
+ * H_t = -(1/Z) curl E (the scheme's Pade curl), H_tt = Delta H, H_ttt =
+ * Delta H_t, H_tttt = Delta H_tt (the second-order Laplacian Delta_h with
+ * the ghost rules of Corollary cor:ghost_cor); H keeps its values on the
+ * walls it is normal to.  Asynchronous; ESTATE after a step, EINVAL for the
+ * NC scheme. */
+c4m_status c4m_init_h_taylor(c4m_problem* p);
 
 /* Counters and sticky flags; synchronises the stream when PCG statistics
  * or the finite check are involved. */

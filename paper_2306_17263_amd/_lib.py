@@ -13,6 +13,7 @@ CLOSURE = {"paper": 0, "reflect": 1}
 LAP = {"tracked": 0, "discrete": 1}
 PRECISION = {"fp64": 0, "fp32_refined": 1}
 SOLVER = {"chebyshev": 0, "pcg": 1}
+SCHEME = {"c4": 0, "nc": 1}
 FLAG_ALLOW_ANY_CFL = 0x1
 FLAG_CHECK_FINITE = 0x2
 FLAG_PROFILE = 0x4
@@ -21,7 +22,7 @@ KERNEL_CLASSES = ["rhs_e", "solve_e", "rhs_h", "solve_h", "step_e", "step_h", "o
 # every symbol include/c4m.h declares
 EXPORTS = [
     "c4m_config_default", "c4m_workspace_bytes", "c4m_create", "c4m_field_shape",
-    "c4m_set_field", "c4m_set_boundary", "c4m_get_field", "c4m_step", "c4m_get_info", "c4m_destroy",
+    "c4m_set_field", "c4m_set_boundary", "c4m_get_field", "c4m_step", "c4m_init_h_taylor", "c4m_get_info", "c4m_destroy",
     "c4m_batch_workspace_bytes", "c4m_batch_create", "c4m_batch_problem", "c4m_batch_step",
     "c4m_batch_check", "c4m_batch_get_info", "c4m_batch_destroy", "c4m_batch_tables_bytes", "c4m_batch_create_from",
     "c4m_step_fields_noalloc", "c4m_status_string", "c4m_last_error",
@@ -35,7 +36,7 @@ class C4mConfig(ctypes.Structure):
         ("precision", ctypes.c_int32), ("solver", ctypes.c_int32), ("sweeps", ctypes.c_int32),
         ("max_iter", ctypes.c_int32), ("rtol", ctypes.c_double), ("tile_x", ctypes.c_int32),
         ("tile_y", ctypes.c_int32), ("flags", ctypes.c_uint32), ("batch_wait_limit", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("scheme", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -77,6 +78,7 @@ def load():
     lib.c4m_set_boundary.argtypes = [vp, i32, i32, vp, i32]
     lib.c4m_get_field.argtypes = [vp, i32, vp, i32]
     lib.c4m_step.argtypes = [vp, i64]
+    lib.c4m_init_h_taylor.argtypes = [vp]
     lib.c4m_get_info.argtypes = [vp, ctypes.POINTER(C4mInfo)]
     lib.c4m_destroy.argtypes = [vp]
     lib.c4m_batch_workspace_bytes.argtypes = [cfgp, i32, ctypes.POINTER(sz)]

@@ -555,6 +555,7 @@ c4m_status check_uniform(const c4m_config* cfgs, int32_t count)
     for (int i = 0; i < count; ++i) {
         const c4m_config& c = cfgs[i];
         if (c.dim != 2) return set_error(C4M_EINVAL, "batched form takes 2D problems");
+        if (c.scheme != C4M_SCHEME_C4) return set_error(C4M_EINVAL, "batched form runs the compact scheme");
         if (c.solver != C4M_SOLVER_CHEBYSHEV)
             return set_error(C4M_EINVAL, "batched form runs the fused Chebyshev solve only");
         if (c.cfl != cfgs[0].cfl || c.z != cfgs[0].z || c.closure != cfgs[0].closure ||

@@ -46,6 +46,12 @@ hipError_t launch_lap_convert(hipStream_t st, double* a, const double* e, double
                               int P, size_t plane, double alpha, int mode);
 hipError_t launch_count_nonfinite(hipStream_t st, const double* a, const Box& bx, int P,
                                   size_t plane, int* count);
+hipError_t launch_nc_e(hipStream_t st, double* ez, const double* hx, const double* hy, int N, int P, double r,
+                       double z);
+hipError_t launch_nc_h(hipStream_t st, const double* ez, double* hx, double* hy, int N, int P, double r, double z);
+hipError_t launch_taylor_lap(hipStream_t st, const double* a, double* out, const Box& bx, int P, size_t plane);
+hipError_t launch_taylor_combine(hipStream_t st, double* h, const double* cu, const double* lh, const Box& bx, int P,
+                                 size_t plane, const double c[4]);
 hipError_t launch_wall_max(hipStream_t st, const double* a, const Box& bx, int P, size_t plane,
                            unsigned long long* out);
 hipError_t launch_put_plane(hipStream_t st, double* a, const double* vals, const Box& bx, int axis, int at,
@@ -366,6 +372,15 @@ c4m_status validate(const c4m_config* c)
     if (c->solver != C4M_SOLVER_CHEBYSHEV && c->solver != C4M_SOLVER_PCG)
         return fail(C4M_EINVAL, "bad solver");
     if (c->sweeps < 0 || c->sweeps > MAX_SWEEPS) return fail(C4M_EINVAL, "sweeps out of range");
+    if (c->scheme != C4M_SCHEME_C4 && c->scheme != C4M_SCHEME_NC) return fail(C4M_EINVAL, "bad scheme");
+    if (c->scheme == C4M_SCHEME_NC) {
+        if (c->dim != 2) return fail(C4M_EINVAL, "the NC scheme is 2D");
+        if (c->precision != C4M_FP64) return fail(C4M_EINVAL, "the NC scheme runs in FP64");
+        // leapfrog with the K4 rows: r^2 (2 (9/8 + 1/24))^2 dim <= 4
+        if (!(c->flags & C4M_FLAG_ALLOW_ANY_CFL) && c->cfl > 6.0 / (7.0 * sqrt(2.0)) * (1.0 + 1e-12))
+            return fail(C4M_EUNSTABLE, "cfl above the NC stability bound 6/(7 sqrt 2)");
+        return C4M_OK;
+    }
     if (c->tile_x < 0 || c->tile_x > 4) return fail(C4M_EINVAL, "tile_x (column kernel shape) must be in 0..4");
     if (c->tile_y < 0 || c->tile_y > 8) return fail(C4M_EINVAL, "tile_y (persistent grid multiplier) out of range");
     // Section 4: r <= 1/(sqrt(d) ||A^{-1}||) with ||A^{-1}|| ~ 6/5
@@ -396,18 +411,19 @@ Layout layout(const c4m_config* c)
     L.arr = c->dim == 2 ? L.plane : L.plane * (N + 1);
     L.arr_bytes = align256(L.arr * sizeof(double));
     L.n_fields = c->dim == 2 ? 3 : 6;
-    L.n_ge = c->lap_mode == C4M_LAP_TRACKED ? (c->dim == 2 ? 1 : 3) : 0;
-    const bool pcg = c->solver == C4M_SOLVER_PCG;
+    const bool nc = c->scheme == C4M_SCHEME_NC;
+    L.n_ge = (c->lap_mode == C4M_LAP_TRACKED && !nc) ? (c->dim == 2 ? 1 : 3) : 0;
+    const bool pcg = c->solver == C4M_SOLVER_PCG && !nc;
     // 2D: T0, T1 (+ x, r, two directions, M p, 1/diag, z for PCG);
     // 3D: b, x, d0, d1, curl (+ M p, 1/diag, z for PCG)
-    L.n_tmp = c->dim == 2 ? (pcg ? 9 : 2) : (pcg ? 8 : 5);
+    L.n_tmp = nc ? 1 : (c->dim == 2 ? (pcg ? 9 : 2) : (pcg ? 8 : 5));
     L.pcg_bytes = pcg ? align256(3 * ((L.arr + 255) / 256) * sizeof(double)) + 256 : 0;
     for (int k = 0; k < 2; ++k) {
         const int n_out = (k == 0 ? N + 1 : N) - 1;
         L.table_bytes[k] = align256(line_image_doubles(n_out) * sizeof(double));
     }
     // 2D strip form: raw and conditioned derivatives of the band rows at both ends
-    L.band_bytes = c->dim == 2 ? align256((size_t)4 * YB_ROWS * L.P * sizeof(double)) : 0;
+    L.band_bytes = (c->dim == 2 && !nc) ? align256((size_t)4 * YB_ROWS * L.P * sizeof(double)) : 0;
     L.total = (size_t)(L.n_fields + L.n_ge + L.n_tmp) * L.arr_bytes + L.pcg_bytes + L.band_bytes +
               L.table_bytes[0] + L.table_bytes[1] + 256;
     return L;
@@ -602,6 +618,18 @@ c4m_status step_once(c4m_problem* p)
 {
     const int N = p->N, P = p->P;
     const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+    if (p->cfg.scheme == C4M_SCHEME_NC) {
+        // the comparison scheme NC (Section 5.2): Yee update with K4 at a = 0
+        double *ez = p->f[C4M_EZ], *hx = p->f[C4M_HX], *hy = p->f[C4M_HY];
+        c4m_status s = timed(p, C4M_K_STEP_E, "NC E update", [&] {
+            return launch_nc_e(p->stream, ez, hx, hy, N, P, p->coef.cfl, p->coef.z);
+        });
+        if (s == C4M_OK)
+            s = timed(p, C4M_K_STEP_H, "NC H update", [&] {
+                return launch_nc_h(p->stream, ez, hx, hy, N, P, p->coef.cfl, p->coef.z);
+            });
+        return s;
+    }
     if (p->dim == 2) {
         double *hx = p->f[C4M_HX], *hy = p->f[C4M_HY], *ez = p->f[C4M_EZ], *ge = p->ge[2];
         double *t0 = p->tmp[0], *t1 = p->tmp[1];
@@ -660,6 +688,13 @@ void set_alg_bytes(c4m_problem* p)
     // right-hand sides read the three H components once, ...).
     const double w = 8.0;
     const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+    if (p->cfg.scheme == C4M_SCHEME_NC) {
+        // E update: Hx, Hy read, Ez read and written; H update: Ez read, Hx, Hy read and written
+        const double cells = (double)p->N * p->N;
+        p->alg_bytes[C4M_K_STEP_E] = w * cells * 4;
+        p->alg_bytes[C4M_K_STEP_H] = w * cells * 5;
+        return;
+    }
     if (p->dim == 2) {
         const double cells = (double)p->N * p->N;
         p->alg_bytes[C4M_K_RHS_E] = w * cells;
@@ -783,11 +818,15 @@ c4m_status c4m_workspace_bytes(const c4m_config* cfg, size_t* bytes)
     return C4M_OK;
 }
 
-c4m_status c4m_create(const c4m_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+c4m_status c4m_create(const c4m_config* cfg_in, void* d_workspace, size_t bytes, void* hip_stream,
                       c4m_problem** out)
 {
-    c4m_status s = validate(cfg);
+    c4m_status s = validate(cfg_in);
     if (s != C4M_OK) return s;
+    // the NC scheme carries no Laplacian of E
+    c4m_config cfg_local = *cfg_in;
+    if (cfg_local.scheme == C4M_SCHEME_NC) cfg_local.lap_mode = C4M_LAP_DISCRETE;
+    const c4m_config* cfg = &cfg_local;
     if (!out) return fail(C4M_EINVAL, "null out");
     *out = nullptr;
     if (!d_workspace || ((uintptr_t)d_workspace & 255)) return fail(C4M_EINVAL, "workspace must be 256-byte aligned");
@@ -1040,6 +1079,39 @@ c4m_status c4m_step(c4m_problem* p, int64_t nsteps)
             p->nonfinite = 1;
             return fail(C4M_ENONFINITE, "non-finite field values");
         }
+    }
+    return C4M_OK;
+}
+
+c4m_status c4m_init_h_taylor(c4m_problem* p)
+{
+    if (!p) return fail(C4M_EINVAL, "null problem");
+    if (p->cfg.scheme != C4M_SCHEME_C4) return fail(C4M_EINVAL, "the Taylor start belongs to the compact scheme");
+    if (p->steps != 0) return fail(C4M_ESTATE, "the Taylor start takes the fields at tau = 0 (no step taken)");
+    const double r = p->cfg.cfl, z = p->cfg.z;
+    // a = h_tau/2 = r h/2:  a H_t = -(r/(2Z)) curl^A E,  a^2/2 H_tt = (r^2/8) L5 H,
+    // a^3/6 H_ttt = -(r^3/(48 Z)) L5 curl^A E,  a^4/24 H_tttt = (r^4/384) L5 L5 H
+    const double c[4] = {-r / (2.0 * z), r * r / 8.0, -r * r * r / (48.0 * z), r * r * r * r / 384.0};
+    double *cu = p->tmp[0], *lh = p->tmp[1];
+    for (int comp = 0; comp < 3; ++comp) {
+        double* h = p->f[3 + comp];
+        if (!h) continue;
+        const Box& bh = p->box[3 + comp];
+        hipError_t e = hipMemsetAsync(cu, 0, p->arr * sizeof(double), p->stream);
+        // (curl^A E)_c = delta_{c1} E_{c2} - delta_{c2} E_{c1}: every E
+        // derivative runs along a node axis of E (a node -> half line)
+        int first = 1;
+        for (int t = 0; t < 2 && e == hipSuccess; ++t) {
+            const int axis = t == 0 ? (comp + 1) % 3 : (comp + 2) % 3;
+            const int src = t == 0 ? (comp + 2) % 3 : (comp + 1) % 3;
+            if (axis >= p->dim || !p->f[src]) continue;
+            Term3 tm{p->f[src], cu, p->box[src], unknowns(bh), p->P, p->plane, t == 0 ? 1.0 : -1.0, first ? 0 : 1};
+            e = launch_term3(p->stream, axis, T3_RAW, tm, p->coef.alpha, p->pade_host[0].taps, p->line[0]);
+            first = 0;
+        }
+        if (e == hipSuccess) e = launch_taylor_lap(p->stream, h, lh, bh, p->P, p->plane);
+        if (e == hipSuccess) e = launch_taylor_combine(p->stream, h, cu, lh, bh, p->P, p->plane, c);
+        if (e != hipSuccess) return hip_fail(e, "Taylor start");
     }
     return C4M_OK;
 }

@@ -109,6 +109,45 @@ __global__ void k_put_plane(double* a, const double* vals, Box bx, int axis, int
     a[q[2] * plane + (size_t)q[1] * P + q[0]] = vals[e];
 }
 
+// h^2 Delta_h a (sum of second differences; even ghosts along half axes)
+// at point o of box bx, valid off the node walls
+__device__ __forceinline__ double lap5_at(const double* a, const Box& bx, int P, size_t plane, int i, int j, int k)
+{
+    const int q[3] = {i, j, k};
+    const size_t st[3] = {1, (size_t)P, plane};
+    const size_t o = k * plane + (size_t)j * P + i;
+    double lap = 0.0;
+    for (int d = 0; d < 3; ++d) {
+        if (!bx.active[d]) continue;
+        const size_t om = (q[d] == 0) ? o : o - st[d];
+        const size_t op = (q[d] == bx.n[d] - 1) ? o : o + st[d];
+        lap += a[om] - 2.0 * a[o] + a[op];
+    }
+    return lap;
+}
+
+// Taylor start of H: out = h^2 Delta_h a off the node walls, 0 on them
+__global__ void k_taylor_lap(const double* a, double* out, Box bx, int P, size_t plane)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int k = blockIdx.z;
+    if (i >= bx.n[0]) return;
+    out[k * plane + (size_t)j * P + i] = on_node_wall(bx, i, j, k) ? 0.0 : lap5_at(a, bx, P, plane, i, j, k);
+}
+
+// h += c[0] cu + c[1] lh + c[2] h^2 Delta_h cu + c[3] h^2 Delta_h lh off the node walls
+__global__ void k_taylor_combine(double* h, const double* cu, const double* lh, Box bx, int P, size_t plane,
+                                 double c0, double c1, double c2, double c3)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.y;
+    const int k = blockIdx.z;
+    if (i >= bx.n[0] || on_node_wall(bx, i, j, k)) return;
+    const size_t o = k * plane + (size_t)j * P + i;
+    h[o] += c0 * cu[o] + c1 * lh[o] + c2 * lap5_at(cu, bx, P, plane, i, j, k) + c3 * lap5_at(lh, bx, P, plane, i, j, k);
+}
+
 static dim3 box_grid(const Box& bx) { return dim3((bx.n[0] + 255) / 256, bx.n[1], bx.n[2]); }
 
 hipError_t launch_zero_walls(hipStream_t st, double* a, const Box& bx, int P, size_t plane)
@@ -137,6 +176,20 @@ hipError_t launch_put_plane(hipStream_t st, double* a, const double* vals, const
 {
     const int cnt = bx.n[0] * bx.n[1] * bx.n[2] / bx.n[axis];
     hipLaunchKernelGGL(k_put_plane, dim3((cnt + 255) / 256), dim3(256), 0, st, a, vals, bx, axis, at, P, plane);
+    return hipGetLastError();
+}
+
+hipError_t launch_taylor_lap(hipStream_t st, const double* a, double* out, const Box& bx, int P, size_t plane)
+{
+    hipLaunchKernelGGL(k_taylor_lap, box_grid(bx), dim3(256), 0, st, a, out, bx, P, plane);
+    return hipGetLastError();
+}
+
+hipError_t launch_taylor_combine(hipStream_t st, double* h, const double* cu, const double* lh, const Box& bx, int P,
+                                 size_t plane, const double c[4])
+{
+    hipLaunchKernelGGL(k_taylor_combine, box_grid(bx), dim3(256), 0, st, h, cu, lh, bx, P, plane, c[0], c[1], c[2],
+                       c[3]);
     return hipGetLastError();
 }
 

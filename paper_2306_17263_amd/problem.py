@@ -14,7 +14,7 @@ def make_config(dim: int = 2, n: int = 64, cfl: float = 0.5, z: float = 1.0,
                 closure: str = "paper", lap_mode: str = "tracked", precision: str = "fp64",
                 solver: str = "chebyshev", sweeps: int = 0, max_iter: int = 0, rtol: float = 0.0,
                 tile_x: int = 0, tile_y: int = 0, flags: int = 0,
-                batch_wait_limit: int = 0) -> L.C4mConfig:
+                batch_wait_limit: int = 0, scheme: str = "c4") -> L.C4mConfig:
     lib = L.load()
     cfg = L.C4mConfig()
     L.check(lib.c4m_config_default(ctypes.byref(cfg)), "c4m_config_default")
@@ -26,6 +26,7 @@ def make_config(dim: int = 2, n: int = 64, cfl: float = 0.5, z: float = 1.0,
     cfg.sweeps, cfg.max_iter, cfg.rtol = sweeps, max_iter, rtol
     cfg.tile_x, cfg.tile_y, cfg.flags = tile_x, tile_y, flags
     cfg.batch_wait_limit = batch_wait_limit
+    cfg.scheme = L.SCHEME[scheme]
     return cfg
 
 
@@ -123,6 +124,10 @@ class Problem:
                 f"c4m_get_field({name})")
         return out
 
+    def init_h_taylor(self):
+        """Replace H (set at tau = 0) by H at tau = h_tau/2 (Taylor start)."""
+        L.check(self._lib.c4m_init_h_taylor(self._h), "c4m_init_h_taylor")
+
     def step(self, nsteps: int = 1):
         L.check(self._lib.c4m_step(self._h, int(nsteps)), "c4m_step")
 
@@ -137,6 +142,6 @@ class Problem:
 
     def fields(self):
         names = ["ez", "hx", "hy"] if self.dim == 2 else ["ex", "ey", "ez", "hx", "hy", "hz"]
-        if self.cfg.lap_mode == L.LAP["tracked"]:
+        if self.cfg.lap_mode == L.LAP["tracked"] and self.cfg.scheme == L.SCHEME["c4"]:
             names += ["lz"] if self.dim == 2 else ["lx", "ly", "lz"]
         return names
