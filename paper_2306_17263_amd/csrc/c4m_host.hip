@@ -49,6 +49,8 @@ hipError_t launch_count_nonfinite(hipStream_t st, const double* a, const Box& bx
 hipError_t launch_nc_e(hipStream_t st, double* ez, const double* hx, const double* hy, int N, int P, double r,
                        double z);
 hipError_t launch_nc_h(hipStream_t st, const double* ez, double* hx, double* hy, int N, int P, double r, double z);
+hipError_t launch_condition3(hipStream_t st, int mode, const double* src, double* out, const Box& bx, int P,
+                             size_t plane, double alpha);
 hipError_t launch_taylor_lap(hipStream_t st, const double* a, double* out, const Box& bx, int P, size_t plane);
 hipError_t launch_taylor_combine(hipStream_t st, double* h, const double* cu, const double* lh, const Box& bx, int P,
                                  size_t plane, const double c[4]);
@@ -299,7 +301,7 @@ struct c4m_problem {
     size_t ws_bytes = 0, used = 0;
     double* f[6] = {};                  // Ex Ey Ez Hx Hy Hz
     double* ge[3] = {};                 // G_E per E component (carried Laplacian)
-    double* tmp[9] = {};
+    double* tmp[12] = {};
     double* pcg_part = nullptr;         // PCG per-workgroup partial sums
     PcgState* pcg_state = nullptr;      // PCG scalars and statistics
     double* pade_dev[2] = {};           // [0] node->half (n_in N+1), [1] half->node (n_in N)
@@ -415,8 +417,9 @@ Layout layout(const c4m_config* c)
     L.n_ge = (c->lap_mode == C4M_LAP_TRACKED && !nc) ? (c->dim == 2 ? 1 : 3) : 0;
     const bool pcg = c->solver == C4M_SOLVER_PCG && !nc;
     // 2D: T0, T1 (+ x, r, two directions, M p, 1/diag, z for PCG);
-    // 3D: b, x, d0, d1, curl (+ M p, 1/diag, z for PCG)
-    L.n_tmp = nc ? 1 : (c->dim == 2 ? (pcg ? 9 : 2) : (pcg ? 8 : 5));
+    // 3D: b, x, d0, d1, curl (+ M p, 1/diag, z for PCG), then the three
+    // conditioned sources of the line terms
+    L.n_tmp = nc ? 1 : (c->dim == 2 ? (pcg ? 9 : 2) : (pcg ? 8 : 5) + 3);
     L.pcg_bytes = pcg ? align256(3 * ((L.arr + 255) / 256) * sizeof(double)) + 256 : 0;
     for (int k = 0; k < 2; ++k) {
         const int n_out = (k == 0 ? N + 1 : N) - 1;
@@ -540,6 +543,7 @@ UGrid unknowns(const Box& b)
 
 // 3D: Step 1 then Step 2 of Section 3.4, one component at a time.
 enum { T3_RAW = 0, T3_G = 1, T3_GE_STORED = 2, T3_GE_DISCRETE = 3 };
+constexpr int SRC_G_HOST = T3_G, SRC_GE_DISCRETE_HOST = T3_GE_DISCRETE;
 c4m_status step3(c4m_problem* p)
 {
     const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
@@ -566,18 +570,29 @@ c4m_status step3(c4m_problem* p)
         return a;
     };
     c4m_status s = C4M_OK;
-    auto term = [&](int axis, int src, int mode, double* out, double scale, int acc, int tgt, int line) {
-        Term3 t{p->f[src], out, p->box[src], unknowns(p->box[tgt]), p->P, p->plane, scale, acc};
-        if (mode == T3_GE_STORED) t.src = p->ge[src];
+    // conditioned sources: G(H_j) for Step 1, G(E_j) on the discrete
+    // Laplacian for Step 2 (tracked Step 2 reads the stored G_E)
+    double* cond[3] = {p->tmp[pcg ? 8 : 5], p->tmp[pcg ? 9 : 6], p->tmp[pcg ? 10 : 7]};
+    auto condition = [&](int first_src, int mode) {
+        hipError_t e = hipSuccess;
+        for (int j = 0; j < 3 && e == hipSuccess; ++j)
+            e = launch_condition3(p->stream, mode, p->f[first_src + j], cond[j], p->box[first_src + j], p->P,
+                                  p->plane, p->coef.alpha);
+        return e;
+    };
+    auto term = [&](int axis, int src, const double* sp, int mode, double* out, double scale, int acc, int tgt,
+                    int line) {
+        Term3 t{sp, out, p->box[src], unknowns(p->box[tgt]), p->P, p->plane, scale, acc};
         return launch_term3(p->stream, axis, mode, t, p->coef.alpha, p->pade_host[line].taps, p->line[line]);
     };
     for (int c = 0; c < 3 && s == C4M_OK; ++c) {
         const int s1 = (c + 1) % 3, s2 = (c + 2) % 3;
         s = timed(p, C4M_K_RHS_E, "rhs E", [&] {
-            hipError_t e = term(s1, 3 + s2, T3_G, b, z, 0, c, 1);
-            if (e == hipSuccess) e = term(s2, 3 + s1, T3_G, b, -z, 1, c, 1);
-            if (e == hipSuccess && tracked) e = term(s1, 3 + s2, T3_RAW, cur, 1.0, 0, c, 1);
-            if (e == hipSuccess && tracked) e = term(s2, 3 + s1, T3_RAW, cur, -1.0, 1, c, 1);
+            hipError_t e = c == 0 ? condition(3, SRC_G_HOST) : hipSuccess;
+            if (e == hipSuccess) e = term(s1, 3 + s2, cond[s2], T3_RAW, b, z, 0, c, 1);
+            if (e == hipSuccess) e = term(s2, 3 + s1, cond[s1], T3_RAW, b, -z, 1, c, 1);
+            if (e == hipSuccess && tracked) e = term(s1, 3 + s2, p->f[3 + s2], T3_RAW, cur, 1.0, 0, c, 1);
+            if (e == hipSuccess && tracked) e = term(s2, 3 + s1, p->f[3 + s1], T3_RAW, cur, -1.0, 1, c, 1);
             return e;
         });
         if (s != C4M_OK) break;
@@ -592,12 +607,14 @@ c4m_status step3(c4m_problem* p)
             return launch_solve3(p->stream, ch, p->f[c], tracked ? p->ge[c] : nullptr, cur, p->coef, p->cheb);
         });
     }
-    const int gmode = tracked ? T3_GE_STORED : T3_GE_DISCRETE;
     for (int c = 0; c < 3 && s == C4M_OK; ++c) {
         const int s1 = (c + 1) % 3, s2 = (c + 2) % 3;
         s = timed(p, C4M_K_RHS_H, "rhs H", [&] {
-            hipError_t e = term(s1, s2, gmode, b, -1.0 / z, 0, 3 + c, 0);
-            if (e == hipSuccess) e = term(s2, s1, gmode, b, 1.0 / z, 1, 3 + c, 0);
+            hipError_t e = (c == 0 && !tracked) ? condition(0, SRC_GE_DISCRETE_HOST) : hipSuccess;
+            const double* src1 = tracked ? p->ge[s1] : cond[s1];
+            const double* src2 = tracked ? p->ge[s2] : cond[s2];
+            if (e == hipSuccess) e = term(s1, s2, src2, T3_RAW, b, -1.0 / z, 0, 3 + c, 0);
+            if (e == hipSuccess) e = term(s2, s1, src1, T3_RAW, b, 1.0 / z, 1, 3 + c, 0);
             return e;
         });
         if (s != C4M_OK) break;

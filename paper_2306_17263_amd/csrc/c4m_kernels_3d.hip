@@ -39,7 +39,7 @@ __device__ __forceinline__ const double* pade_row3(const PadeLine& L, int m)
 // the stored box and the value is selected at the end, so a caller can have
 // the loads of several values in flight at once.
 template <int MODE>
-__device__ __forceinline__ double src_value(const Term3& t, int i, int j, int k, double alpha, bool ok)
+__device__ __forceinline__ double src_value(const Term3& t, int i, int j, int k, double alpha, bool ok, double& raw)
 {
     const Box& b = t.sb;
     const int q[3] = {i, j, k};
@@ -52,7 +52,8 @@ __device__ __forceinline__ double src_value(const Term3& t, int i, int j, int k,
     }
     const double* p = t.src + c[2] * t.plane + (size_t)c[1] * t.P + c[0];
     const double u0 = p[0];
-    if (MODE == SRC_RAW || MODE == SRC_GE_STORED) return in ? u0 : 0.0;
+    raw = in ? u0 : 0.0;
+    if (MODE == SRC_RAW || MODE == SRC_GE_STORED) return raw;
     const long st[3] = {1, (long)t.P, (long)t.plane};
     if (MODE == SRC_GE_DISCRETE) {
 #pragma unroll
@@ -107,7 +108,8 @@ __global__ __launch_bounds__(256) void k_term3(Term3 t, double alpha, PadeTaps t
             idx[D] = g;
             idx[W] = wi;
             idx[SX] = s;
-            v[c] = src_value<MODE>(t, idx[0], idx[1], idx[2], alpha, ok);
+            double raw;
+            v[c] = src_value<MODE>(t, idx[0], idx[1], idx[2], alpha, ok, raw);
         }
 #pragma unroll
         for (int c = 0; c < CH; ++c) {
@@ -182,6 +184,90 @@ __global__ __launch_bounds__(256) void k_term3(Term3 t, double alpha, PadeTaps t
         const size_t oi = idx[2] * t.plane + (size_t)idx[1] * t.P + idx[0];
         const double v = t.scale * out[k];
         t.out[oi] = t.accumulate ? t.out[oi] + v : v;
+    }
+}
+
+// k_condition3: the conditioned source G(u) (SRC_G) or its discrete-
+// Laplacian form on E (SRC_GE_DISCRETE) at every stored point of a box, as
+// src_value forms it, so that the line terms can read it raw.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_condition3(Term3 t, double alpha)
+{
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int j = blockIdx.y, k = blockIdx.z;
+    if (i >= t.sb.n[0]) return;
+    double raw;
+    t.out[(size_t)k * t.plane + (size_t)j * t.P + i] = src_value<MODE>(t, i, j, k, alpha, true, raw);
+}
+
+// k_march3: the same line term along y or z (D = 1, 2) as a streaming pass.
+// A wave owns 64 consecutive x positions at one index of the third axis and
+// marches along its lines over a segment of outputs; the conditioned inputs
+// of the current block of Q outputs sit in a register window (Q + 25
+// values), and the inputs of the next block are loaded before the current
+// block's FIR runs, so their latency overlaps the arithmetic.  Taps and
+// summation order are those of k_term3.
+constexpr int M3_Q = 8, M3_WIN = M3_Q + PADE_TAPS - 1;
+
+template <int D, int MODE>
+__global__ __launch_bounds__(256) void k_march3(Term3 t, double alpha, PadeTaps taps, PadeLine L, int seg_len)
+{
+    constexpr int T = 3 - D;                       // third axis (x is always across lanes)
+    const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+    const int xi = t.tg.lo[0] + blockIdx.x * 64 + lane;
+    const int ti = t.tg.lo[T] + blockIdx.y * 4 + wv;
+    if (xi >= t.tg.hi[0] || ti >= t.tg.hi[T]) return;
+    const int m0 = blockIdx.z * seg_len;
+    const int m1 = min(m0 + seg_len, L.n_out);
+    const int n_in = L.n_in;
+    auto input = [&](int g) {
+        int idx[3];
+        idx[0] = xi;
+        idx[D] = g;
+        idx[T] = ti;
+        double raw;
+        return src_value<MODE>(t, idx[0], idx[1], idx[2], alpha, g >= 0 && g < n_in, raw);
+    };
+    double win[M3_WIN], nxt[M3_Q];
+#pragma unroll
+    for (int u = 0; u < PADE_TAPS - 1; ++u) win[u] = input(m0 - PADE_R + u);
+#pragma unroll
+    for (int q = 0; q < M3_Q; ++q) nxt[q] = input(m0 - PADE_R + PADE_TAPS - 1 + q);
+    size_t o = (size_t)(D == 2 ? t.tg.lo[2] + m0 : ti) * t.plane + (size_t)(D == 1 ? t.tg.lo[1] + m0 : ti) * t.P + xi;
+    const size_t ostep = D == 2 ? t.plane : (size_t)t.P;
+    for (int mb = m0; mb < m1; mb += M3_Q) {
+#pragma unroll
+        for (int q = 0; q < M3_Q; ++q) win[PADE_TAPS - 1 + q] = nxt[q];
+        // the accumulated outputs are read before the prefetch is issued
+        // (loads complete in order, so a later read would wait for it)
+        double prev[M3_Q];
+#pragma unroll
+        for (int k = 0; k < M3_Q; ++k)
+            prev[k] = (t.accumulate && mb + k < m1) ? t.out[o + (size_t)k * ostep] : 0.0;
+        if (mb + M3_Q < m1) {
+#pragma unroll
+            for (int q = 0; q < M3_Q; ++q) nxt[q] = input(mb + M3_Q - PADE_R + PADE_TAPS - 1 + q);
+        }
+        const bool fast = !L.all && mb >= L.b && mb + M3_Q - 1 < L.n_out - L.b;
+#pragma unroll
+        for (int k = 0; k < M3_Q; ++k) {
+            const int m = mb + k;
+            if (m >= m1) break;
+            double acc = 0.0;
+            if (fast) {
+#pragma unroll
+                for (int u = 0; u < PADE_TAPS; ++u) acc = fma(taps.c[u], win[k + u], acc);
+            } else {
+                const double* cr = pade_row3(L, m);
+#pragma unroll
+                for (int u = 0; u < PADE_TAPS; ++u) acc = fma(cr[u], win[k + u], acc);
+            }
+            const double v = t.scale * acc;
+            t.out[o] = t.accumulate ? prev[k] + v : v;
+            o += ostep;
+        }
+#pragma unroll
+        for (int u = 0; u < PADE_TAPS - 1; ++u) win[u] = win[u + M3_Q];
     }
 }
 
@@ -421,6 +507,37 @@ hipError_t launch_solve3_mixed(hipStream_t st, const Cheb3& c, size_t arr, doubl
 // ---------------------------------------------------------------------------
 // Launchers.
 // ---------------------------------------------------------------------------
+// Segment of outputs per wave of k_march3: lines are cut so that a launch
+// has at least about 8 waves per SIMD of the device.
+static int march_segment(int n_out, long waves_per_seg)
+{
+    int seg = 256;
+    while (seg > 32 && waves_per_seg * ((n_out + seg - 1) / seg) < 8192) seg /= 2;
+    return seg;
+}
+
+template <int D>
+static hipError_t launch_march_d(hipStream_t st, int mode, const Term3& t, double alpha, const PadeTaps& taps,
+                                 const PadeLine& L)
+{
+    constexpr int T = 3 - D;
+    const int nx = t.tg.hi[0] - t.tg.lo[0], nt = t.tg.hi[T] - t.tg.lo[T];
+    const dim3 g0((nx + 63) / 64, (nt + 3) / 4, 1);
+    const int seg = march_segment(L.n_out, (long)g0.x * g0.y * 4);
+    const dim3 grid(g0.x, g0.y, (L.n_out + seg - 1) / seg);
+    switch (mode) {
+        case SRC_RAW: hipLaunchKernelGGL((k_march3<D, SRC_RAW>), grid, dim3(256), 0, st, t, alpha, taps, L, seg); break;
+        case SRC_G: hipLaunchKernelGGL((k_march3<D, SRC_G>), grid, dim3(256), 0, st, t, alpha, taps, L, seg); break;
+        case SRC_GE_STORED:
+            hipLaunchKernelGGL((k_march3<D, SRC_GE_STORED>), grid, dim3(256), 0, st, t, alpha, taps, L, seg);
+            break;
+        default:
+            hipLaunchKernelGGL((k_march3<D, SRC_GE_DISCRETE>), grid, dim3(256), 0, st, t, alpha, taps, L, seg);
+            break;
+    }
+    return hipGetLastError();
+}
+
 template <int D>
 static hipError_t launch_term_d(hipStream_t st, int mode, const Term3& t, double alpha, const PadeTaps& taps,
                                 const PadeLine& L)
@@ -445,12 +562,27 @@ static hipError_t launch_term_d(hipStream_t st, int mode, const Term3& t, double
     return hipGetLastError();
 }
 
+hipError_t launch_condition3(hipStream_t st, int mode, const double* src, double* out, const Box& bx, int P,
+                             size_t plane, double alpha)
+{
+    Term3 t{};
+    t.src = src;
+    t.out = out;
+    t.sb = bx;
+    t.P = P;
+    t.plane = plane;
+    const dim3 grid((bx.n[0] + 255) / 256, bx.n[1], bx.n[2]);
+    if (mode == SRC_G) hipLaunchKernelGGL((k_condition3<SRC_G>), grid, dim3(256), 0, st, t, alpha);
+    else hipLaunchKernelGGL((k_condition3<SRC_GE_DISCRETE>), grid, dim3(256), 0, st, t, alpha);
+    return hipGetLastError();
+}
+
 hipError_t launch_term3(hipStream_t st, int axis, int mode, const Term3& t, double alpha, const PadeTaps& taps,
                         const PadeLine& L)
 {
     if (axis == 0) return launch_term_d<0>(st, mode, t, alpha, taps, L);
-    if (axis == 1) return launch_term_d<1>(st, mode, t, alpha, taps, L);
-    return launch_term_d<2>(st, mode, t, alpha, taps, L);
+    if (axis == 1) return launch_march_d<1>(st, mode, t, alpha, taps, L);
+    return launch_march_d<2>(st, mode, t, alpha, taps, L);
 }
 
 hipError_t launch_solve3(hipStream_t st, const Cheb3& c, double* field, double* ge, const double* cur,
