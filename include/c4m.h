@@ -205,6 +205,20 @@ c4m_status c4m_get_field(c4m_problem* p, c4m_field f, double* dst, int dst_on_de
  * when a NaN or Inf is found. */
 c4m_status c4m_step(c4m_problem* p, int64_t nsteps);
 
+/* Capture, once, the graphs that c4m_step(p, nsteps) replays (runs of up to
+ * 32 steps and the remainder), without running anything, so that a later
+ * c4m_step with that count only launches them.  Lets a caller build them
+ * off its critical path (another thread, a set-up stream).  No-op where
+ * c4m_step launches directly (profiling, null stream, capture in progress).
+ * EINVAL for nsteps < 0. */
+c4m_status c4m_prepare(c4m_problem* p, int64_t nsteps);
+
+/* Move the problem to another HIP stream: waits for the work queued on its
+ * current stream, then every later call enqueues on `stream` (graphs
+ * captured before stay valid).  For handing a problem set up on a private
+ * stream to the stream it will be stepped on.  ESTATE for a batch member. */
+c4m_status c4m_set_stream(c4m_problem* p, void* stream);
+
 /* Taylor start (Section 5.1, eq:talorh, J = 0): with E set at tau = 0 and
  * H set at tau = 0 (not yet stepped), replace H by H at tau = h_tau/2:
  *   H + a H_t + a^2/2 H_tt + a^3/6 H_ttt + a^4/24 H_tttt,  a = h_tau/2,

@@ -22,7 +22,8 @@ KERNEL_CLASSES = ["rhs_e", "solve_e", "rhs_h", "solve_h", "step_e", "step_h", "o
 # every symbol include/c4m.h declares
 EXPORTS = [
     "c4m_config_default", "c4m_workspace_bytes", "c4m_create", "c4m_field_shape",
-    "c4m_set_field", "c4m_set_boundary", "c4m_get_field", "c4m_step", "c4m_init_h_taylor", "c4m_get_info", "c4m_destroy",
+    "c4m_set_field", "c4m_set_boundary", "c4m_get_field", "c4m_step", "c4m_init_h_taylor", "c4m_prepare",
+    "c4m_set_stream", "c4m_get_info", "c4m_destroy",
     "c4m_batch_workspace_bytes", "c4m_batch_create", "c4m_batch_problem", "c4m_batch_step",
     "c4m_batch_check", "c4m_batch_get_info", "c4m_batch_destroy", "c4m_batch_tables_bytes", "c4m_batch_create_from",
     "c4m_step_fields_noalloc", "c4m_status_string", "c4m_last_error",
@@ -79,6 +80,8 @@ def load():
     lib.c4m_get_field.argtypes = [vp, i32, vp, i32]
     lib.c4m_step.argtypes = [vp, i64]
     lib.c4m_init_h_taylor.argtypes = [vp]
+    lib.c4m_prepare.argtypes = [vp, i64]
+    lib.c4m_set_stream.argtypes = [vp, vp]
     lib.c4m_get_info.argtypes = [vp, ctypes.POINTER(C4mInfo)]
     lib.c4m_destroy.argtypes = [vp]
     lib.c4m_batch_workspace_bytes.argtypes = [cfgp, i32, ctypes.POINTER(sz)]

@@ -458,21 +458,31 @@ c4m_status copy_field(c4m_problem* p, double* dev, const Box& bx, const double* 
 {
     const size_t w = (size_t)bx.n[0] * sizeof(double);
     const size_t dpitch = (size_t)p->P * sizeof(double);
-    const hipMemcpyKind kind = other_on_device ? hipMemcpyDeviceToDevice
-                                               : (to_device ? hipMemcpyHostToDevice
-                                                            : hipMemcpyDeviceToHost);
-    for (int k = 0; k < bx.n[2]; ++k) {
+    const size_t dense = w * bx.n[1] * bx.n[2];
+    // host data pass through a temporary as one contiguous copy; the planes
+    // move between the dense and the padded layout on the device
+    double* stage = nullptr;
+    if (!other_on_device) stage = dev == p->tmp[0] ? p->tmp[1] : p->tmp[0];
+    hipError_t e = hipSuccess;
+    if (stage && to_device)
+        e = hipMemcpyAsync(stage, host_or_dev, dense, hipMemcpyHostToDevice, p->stream);
+    const double* other = stage ? stage : host_or_dev;
+    const hipMemcpyKind kind = (other_on_device || stage) ? hipMemcpyDeviceToDevice
+                                                          : (to_device ? hipMemcpyHostToDevice
+                                                                       : hipMemcpyDeviceToHost);
+    for (int k = 0; k < bx.n[2] && e == hipSuccess; ++k) {
         double* d = dev + k * p->plane;
-        const double* o = host_or_dev + (size_t)k * bx.n[1] * bx.n[0];
-        hipError_t e;
+        const double* o = other + (size_t)k * bx.n[1] * bx.n[0];
         if (to_device)
             e = hipMemcpy2DAsync(d, dpitch, o, w, w, bx.n[1], kind, p->stream);
         else
             e = hipMemcpy2DAsync((void*)o, w, d, dpitch, w, bx.n[1], kind, p->stream);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpy2DAsync");
     }
+    if (e == hipSuccess && stage && !to_device)
+        e = hipMemcpyAsync((void*)host_or_dev, stage, dense, hipMemcpyDeviceToHost, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "field copy");
     if (!other_on_device) {
-        hipError_t e = hipStreamSynchronize(p->stream);
+        e = hipStreamSynchronize(p->stream);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
     }
     return C4M_OK;
@@ -736,12 +746,47 @@ void set_alg_bytes(c4m_problem* p)
 // captured) or the caller is capturing the stream already.
 constexpr int64_t GRAPH_STEPS = 32;
 
-c4m_status run_steps(c4m_problem* p, int64_t nsteps)
+// The graph of a run of len steps, captured on the problem's stream the
+// first time it is asked for (nothing runs: capture only records).
+c4m_status step_graph(c4m_problem* p, int64_t len, hipGraphExec_t* out)
+{
+    auto it = p->graphs.find(len);
+    if (it == p->graphs.end()) {
+        hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        c4m_status s = C4M_OK;
+        for (int64_t t = 0; t < len && s == C4M_OK; ++t) s = step_once(p);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(p->stream, &g);
+        if (s != C4M_OK) {
+            if (g) (void)hipGraphDestroy(g);
+            return s;
+        }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        hipGraphExec_t x = nullptr;
+        e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            (void)hipGraphDestroy(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        it = p->graphs.emplace(len, std::make_pair(g, x)).first;
+    }
+    *out = it->second.second;
+    return C4M_OK;
+}
+
+// Whether c4m_step launches the steps directly rather than as graphs.
+bool steps_direct(c4m_problem* p)
 {
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     bool direct = (p->cfg.flags & C4M_FLAG_PROFILE) || !p->stream || p->direct;
     if (!direct && hipStreamIsCapturing(p->stream, &cap) != hipSuccess) direct = true;
-    if (direct || cap != hipStreamCaptureStatusNone) {
+    return direct || cap != hipStreamCaptureStatusNone;
+}
+
+c4m_status run_steps(c4m_problem* p, int64_t nsteps)
+{
+    if (steps_direct(p)) {
         for (int64_t t = 0; t < nsteps; ++t) {
             c4m_status s = step_once(p);
             if (s != C4M_OK) return s;
@@ -752,28 +797,10 @@ c4m_status run_steps(c4m_problem* p, int64_t nsteps)
     int64_t left = nsteps;
     while (left > 0) {
         const int64_t len = std::min(left, GRAPH_STEPS);
-        auto it = p->graphs.find(len);
-        if (it == p->graphs.end()) {
-            hipError_t e = hipStreamBeginCapture(p->stream, hipStreamCaptureModeThreadLocal);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-            c4m_status s = C4M_OK;
-            for (int64_t t = 0; t < len && s == C4M_OK; ++t) s = step_once(p);
-            hipGraph_t g = nullptr;
-            e = hipStreamEndCapture(p->stream, &g);
-            if (s != C4M_OK) {
-                if (g) (void)hipGraphDestroy(g);
-                return s;
-            }
-            if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
-            hipGraphExec_t x = nullptr;
-            e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
-            if (e != hipSuccess) {
-                (void)hipGraphDestroy(g);
-                return hip_fail(e, "hipGraphInstantiate");
-            }
-            it = p->graphs.emplace(len, std::make_pair(g, x)).first;
-        }
-        hipError_t e = hipGraphLaunch(it->second.second, p->stream);
+        hipGraphExec_t x = nullptr;
+        c4m_status s = step_graph(p, len, &x);
+        if (s != C4M_OK) return s;
+        hipError_t e = hipGraphLaunch(x, p->stream);
         if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
         left -= len;
         p->steps += len;
@@ -1097,6 +1124,27 @@ c4m_status c4m_step(c4m_problem* p, int64_t nsteps)
             return fail(C4M_ENONFINITE, "non-finite field values");
         }
     }
+    return C4M_OK;
+}
+
+c4m_status c4m_prepare(c4m_problem* p, int64_t nsteps)
+{
+    if (!p || nsteps < 0) return fail(C4M_EINVAL, "bad step count");
+    if (nsteps == 0 || steps_direct(p)) return C4M_OK;
+    const int64_t full = std::min(nsteps, GRAPH_STEPS), rest = nsteps % GRAPH_STEPS;
+    hipGraphExec_t x = nullptr;
+    c4m_status s = step_graph(p, full, &x);
+    if (s == C4M_OK && rest != 0 && nsteps > GRAPH_STEPS) s = step_graph(p, rest, &x);
+    return s;
+}
+
+c4m_status c4m_set_stream(c4m_problem* p, void* stream)
+{
+    if (!p) return fail(C4M_EINVAL, "null problem");
+    if (p->owned_by_batch) return fail(C4M_ESTATE, "problem belongs to a batch");
+    hipError_t e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    p->stream = (hipStream_t)stream;
     return C4M_OK;
 }
 

@@ -128,6 +128,15 @@ class Problem:
         """Replace H (set at tau = 0) by H at tau = h_tau/2 (Taylor start)."""
         L.check(self._lib.c4m_init_h_taylor(self._h), "c4m_init_h_taylor")
 
+    def prepare(self, nsteps: int):
+        """Capture the graphs that step(nsteps) replays, without running them."""
+        L.check(self._lib.c4m_prepare(self._h, int(nsteps)), "c4m_prepare")
+
+    def set_stream(self, stream):
+        """Wait for the work queued on the current stream, then use `stream`."""
+        L.check(self._lib.c4m_set_stream(self._h, ctypes.c_void_p(_stream_ptr(stream))), "c4m_set_stream")
+        self.stream = stream
+
     def step(self, nsteps: int = 1):
         L.check(self._lib.c4m_step(self._h, int(nsteps)), "c4m_step")
 

@@ -1,26 +1,36 @@
 """Serving form: a continuous-batching request loop over the c4m stepper.
 
 Requests (cavity simulations of different sizes and step counts) arrive over
-time.  Each tick the server
-  1. moves requests whose arrival time has passed into the queue;
-  2. admits queued requests in arrival order while their device footprint
-     fits the HBM budget and a slot is free (a request that does not fit
-     waits; smaller later ones may pass it, up to `max_skip` of them);
-  3. advances every active request: the active 2D requests together as one
-     batch (persistent launches, re-formed only when membership changes),
-     the 3D requests on side streams, by k = min(chunk, fewest remaining)
-     steps so nobody overshoots; their work overlaps on the device;
-  4. retires finished requests (fields copied out, memory released).
-Latency of a request is completion minus arrival; the loop reports p50/p99
-latency and completed cell-steps per second.  Fields stay resident on the
-device from admission to retirement.
+time.  Work is issued in units that run asynchronously on the device:
+  * the 2D cohort: every active 2D request, stepped together as one batch
+    (persistent launches; the batch is re-formed only when its membership
+    changed and no chunk of it is in flight);
+  * each 3D request on its own side stream.
+A unit advances by a chunk of k = min(chunk, fewest remaining steps among
+its members) steps, so nobody overshoots, and records a completion event.
+The loop polls those events: a finished chunk retires the requests it
+completed (fields copied out, memory released) and the unit is relaunched at
+once; arrivals are queued and admitted in arrival order while their device
+footprint fits the HBM budget and the active count is below max_active (a
+request that does not fit waits; up to max_skip smaller later ones may pass
+it); at most admit_per_poll requests are created per pass of the loop, so
+polling and relaunching keep going while a burst of arrivals is admitted.
+Nothing waits for the whole device.  The device backend sets a request up
+(workspace, initial fields, the step graphs of its chunk lengths) on a
+worker thread and a private stream, then hands it to its compute stream, so
+set-up never waits behind other requests' queued chunks; the request joins
+its unit when that is done.  Latency of a request is
+completion minus arrival; the loop reports p50/p99 latency and completed
+cell-steps per second.  Fields stay resident from admission to retirement.
 
 The backend is pluggable so the scheduling logic is testable on the CPU
-(see tests/test_serve_cpu.py); DeviceBackend drives libc4m.so.
+(tests/test_serve_cpu.py); DeviceBackend drives libc4m.so.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
+import threading
 import time
 
 import numpy as np
@@ -41,6 +51,7 @@ class Request:
     remaining: int = 0
     handle: object = None
     result: dict = None
+    side: int = 0
 
     @property
     def cells(self) -> int:
@@ -48,9 +59,11 @@ class Request:
 
 
 class DeviceBackend:
-    """Requests on the GPU through libc4m.so (PyTorch for memory/streams)."""
+    """Requests on the GPU through libc4m.so (PyTorch for memory and
+    streams); completion of a chunk is an event recorded on its stream."""
 
-    def __init__(self, n_side_streams: int = 2, settings: dict | None = None, keep_results: bool = False):
+    def __init__(self, n_side_streams: int = 4, settings: dict | None = None, keep_results: bool = False,
+                 chunk: int = 96, workers: int = 2, per_stream: int = 2):
         import torch
         from .problem import make_config, workspace_bytes
         self.torch = torch
@@ -62,40 +75,117 @@ class DeviceBackend:
         self.keep_results = keep_results
         self._batch = None
         self._members = ()
+        self._next_side = 0
+        self.chunk = int(chunk)
+        self.per_stream = int(per_stream)
+        self._inflight = {}             # side stream index -> chunks in flight
+        self._pool = concurrent.futures.ThreadPoolExecutor(max_workers=workers)
+        self._local = threading.local()
+        self._lock = threading.Lock()
+        self.host_s = {"create": 0.0, "launch_2d": 0.0, "reform_2d": 0.0, "launch_3d": 0.0, "finish": 0.0}
+        self.reforms = 0
 
     def footprint(self, req: Request) -> int:
         return self._workspace_bytes(self._make_config(req.dim, req.n, req.r, **self.settings))
 
     def create(self, req: Request):
+        """Starts the set-up of a request; returns a future of its handle."""
+        if req.dim == 2:
+            stream = self.main
+        else:
+            req.side = self._next_side % len(self.side)
+            stream = self.side[req.side]
+            self._next_side += 1
+        return self._pool.submit(self._create, req, stream)
+
+    def can_launch(self, req: Request) -> bool:
+        """A 3D request launches only while its stream has fewer than
+        per_stream chunks queued: every step is some fifty kernels, and a
+        deep backlog would block the loop in the launch."""
+        return req.dim == 2 or self._inflight.get(req.side, 0) < self.per_stream
+
+    def _create(self, req: Request, stream):
         from workloads import mode_fields
         from .problem import Problem
-        stream = self.main if req.dim == 2 else self.side[req.id % len(self.side)]
-        p = Problem(req.dim, req.n, req.r, stream=stream, **self.settings)
+        t = time.perf_counter()
+        setup = getattr(self._local, "stream", None)
+        if setup is None:
+            setup = self._local.stream = self.torch.cuda.Stream()
+        p = Problem(req.dim, req.n, req.r, stream=setup, **self.settings)
+        t1 = time.perf_counter()
         h = 1.0 / req.n
         init = mode_fields(req.dim, req.n, req.k, 0.0, req.r * h / 2, amp=req.amp)
+        t2 = time.perf_counter()
         for name in p.fields():
             p.set(name, init[name])
+        t3 = time.perf_counter()
+        if req.dim == 3:                        # the graphs of its chunk lengths
+            p.prepare(min(self.chunk, req.steps))
+            if req.steps % self.chunk:
+                p.prepare(req.steps % self.chunk)
+        t4 = time.perf_counter()
+        p.set_stream(stream)
+        t5 = time.perf_counter()
+        with self._lock:
+            for key, dt in (("create", t5 - t), ("c_problem", t1 - t), ("c_fields_host", t2 - t1),
+                            ("c_set", t3 - t2), ("c_prepare", t4 - t3), ("c_set_stream", t5 - t4)):
+                self.host_s[key] = self.host_s.get(key, 0.0) + dt
         return p
 
-    def step(self, active2d, active3d, k: int):
+    def launch(self, reqs, k: int):
+        """Start k steps of a unit (the 2D cohort or one 3D request);
+        returns the event that marks its end."""
         from .batch import Batch
-        key = tuple(id(r.handle) for r in active2d)
-        if key != self._members:
-            if self._batch is not None:
-                self._batch.close()
-            self._batch = Batch.from_problems([r.handle for r in active2d], stream=self.main) if active2d else None
-            self._members = key
-        if self._batch is not None:
+        t = time.perf_counter()
+        if reqs[0].dim == 2:
+            key = tuple(id(r.handle) for r in reqs)
+            if key != self._members:
+                if self._batch is not None:
+                    self._batch.close()
+                self._batch = Batch.from_problems([r.handle for r in reqs], stream=self.main)
+                self._members = key
+                self.reforms += 1
+                t1 = time.perf_counter()
+                self.host_s["reform_2d"] += t1 - t
+                t = t1
             self._batch.step(k)
-        for r in active3d:
-            r.handle.step(k)
+            stream = self.main
+            self.host_s["launch_2d"] += time.perf_counter() - t
+        else:
+            reqs[0].handle.step(k)
+            stream = reqs[0].handle.stream
+            self._inflight[reqs[0].side] = self._inflight.get(reqs[0].side, 0) + 1
+            self.host_s["launch_3d"] += time.perf_counter() - t
+        ev = self.torch.cuda.Event()
+        ev.record(stream)
+        return (ev, reqs[0].side if reqs[0].dim == 3 else None)
 
-    def sync(self):
-        self.torch.cuda.synchronize()
+    def done(self, token) -> bool:
+        ev, side = token
+        if not ev.query():
+            return False
+        if side is not None:
+            self._inflight[side] -= 1
+        return True
+
+    def idle(self):
+        time.sleep(2e-4)
 
     def finish(self, req: Request):
+        t = time.perf_counter()
+        self._finish(req, self.keep_results)
+        self.host_s["finish"] += time.perf_counter() - t
+
+    def drain(self):
+        self.torch.cuda.synchronize()
+        self._inflight.clear()
+
+    def abandon(self, req: Request):
+        self._finish(req, False)
+
+    def _finish(self, req: Request, keep: bool):
         names = ["ez", "hx", "hy"] if req.dim == 2 else ["ex", "ey", "ez", "hx", "hy", "hz"]
-        if self.keep_results:
+        if keep:
             req.result = {a: req.handle.get(a) for a in names}
         if self._batch is not None and id(req.handle) in self._members:
             self._batch.close()                 # the batch references this problem
@@ -104,37 +194,76 @@ class DeviceBackend:
         req.handle.close()
         req.handle = None
 
+    def close(self):
+        self._pool.shutdown(wait=True)
+        if self._batch is not None:
+            self._batch.close()
+            self._batch = None
+            self._members = ()
+
 
 class Server:
-    def __init__(self, backend, hbm_budget: int, chunk: int = 50, max_active: int = 256, max_skip: int = 8,
-                 clock=time.perf_counter):
+    def __init__(self, backend, hbm_budget: int, chunk: int = 50, max_active: int = 32, max_skip: int = 8,
+                 admit_per_poll: int = 4, clock=time.perf_counter):
         self.backend = backend
         self.budget = int(hbm_budget)
         self.chunk = int(chunk)
         self.max_active = int(max_active)
         self.max_skip = int(max_skip)
+        self.admit_per_poll = int(admit_per_poll)
         self.clock = clock
         self.in_use = 0
         self.peak_in_use = 0
 
     def run(self, requests, time_limit: float | None = None) -> dict:
         pending = sorted(requests, key=lambda q: q.t_arrive)
-        queue, active, done = [], [], []
+        queue, done = [], []
+        active2, active3 = [], []
+        starting = []               # admitted, set-up still running (backend futures)
+        flight = {}                 # unit key -> (token, members, k); key 0 = 2D cohort, else 3D request id + 1
         footprint = {}
         t0 = self.clock()
         i = 0
-        ticks = 0
-        while i < len(pending) or queue or active:
+        chunks = 0
+        executed = 0.0              # cell-steps of finished chunks, finished requests or not
+        while i < len(pending) or queue or active2 or active3 or starting:
             now = self.clock() - t0
             if time_limit is not None and now > time_limit:
                 break
             while i < len(pending) and pending[i].t_arrive <= now:
                 queue.append(pending[i])
                 i += 1
+            progressed = False
+            # finished chunks: retire the requests they completed
+            for key in list(flight):
+                token, members, k = flight[key]
+                if not self.backend.done(token):
+                    continue
+                del flight[key]
+                progressed = True
+                t_end = self.clock() - t0
+                for r in members:
+                    executed += float(r.cells) * k
+                    r.remaining -= k
+                    if r.remaining <= 0:
+                        r.t_done = t_end
+                        self.backend.finish(r)
+                        self.in_use -= footprint[r.id]
+                        done.append(r)
+                        (active2 if r.dim == 2 else active3).remove(r)
+            # requests whose set-up finished join their unit
+            for q in list(starting):
+                if q.handle.done():
+                    q.handle = q.handle.result()
+                    starting.remove(q)
+                    (active2 if q.dim == 2 else active3).append(q)
+                    progressed = True
             # admission by footprint, arrival order with bounded skipping
             skipped = 0
+            admitted = 0
             j = 0
-            while j < len(queue) and len(active) < self.max_active:
+            while (j < len(queue) and len(active2) + len(active3) + len(starting) < self.max_active
+                   and admitted < self.admit_per_poll):
                 q = queue[j]
                 if q.id not in footprint:
                     footprint[q.id] = self.backend.footprint(q)
@@ -147,45 +276,58 @@ class Server:
                     q.remaining = q.steps
                     self.in_use += fp
                     self.peak_in_use = max(self.peak_in_use, self.in_use)
-                    active.append(q)
+                    if isinstance(q.handle, concurrent.futures.Future):
+                        starting.append(q)
+                    else:
+                        (active2 if q.dim == 2 else active3).append(q)
                     queue.pop(j)
+                    admitted += 1
+                    progressed = True
                 else:
                     skipped += 1
                     if skipped > self.max_skip:
                         break
                     j += 1
-            if not active:
-                if i < len(pending):                # idle until the next arrival
+            # launch every idle unit
+            if active2 and 0 not in flight:
+                k = min(self.chunk, min(r.remaining for r in active2))
+                flight[0] = (self.backend.launch(list(active2), k), list(active2), k)
+                chunks += 1
+                progressed = True
+            for r in active3:
+                if r.id + 1 not in flight and self.backend.can_launch(r):
+                    k = min(self.chunk, r.remaining)
+                    flight[r.id + 1] = (self.backend.launch([r], k), [r], k)
+                    chunks += 1
+                    progressed = True
+            if not progressed:
+                if not flight and i < len(pending):       # idle until the next arrival
                     wait = pending[i].t_arrive - (self.clock() - t0)
                     if wait > 0:
                         self._sleep(wait)
-                continue
-            k = min(self.chunk, min(r.remaining for r in active))
-            a2 = [r for r in active if r.dim == 2]
-            a3 = [r for r in active if r.dim == 3]
-            self.backend.step(a2, a3, k)
-            self.backend.sync()
-            ticks += 1
-            now = self.clock() - t0
-            still = []
-            for r in active:
-                r.remaining -= k
-                if r.remaining <= 0:
-                    r.t_done = now
-                    self.backend.finish(r)
-                    self.in_use -= footprint[r.id]
-                    done.append(r)
                 else:
-                    still.append(r)
-            active = still
+                    self.backend.idle()
         wall = self.clock() - t0
+        # a time limit leaves requests unfinished: release them
+        for q in starting:
+            q.handle = q.handle.result()
+        unfinished = active2 + active3 + starting
+        if unfinished:
+            self.backend.drain()
+            for r in unfinished:
+                self.backend.abandon(r)
+                self.in_use -= footprint[r.id]
+        if hasattr(self.backend, "close"):
+            self.backend.close()
         lat = np.array([r.t_done - r.t_arrive for r in done]) if done else np.array([np.nan])
         cell_steps = float(sum(r.cells * r.steps for r in done))
         return {
-            "completed": len(done), "submitted": len(requests), "wall_s": wall, "ticks": ticks,
+            "completed": len(done), "submitted": len(requests), "wall_s": wall, "chunks": chunks,
             "p50_latency_s": float(np.percentile(lat, 50)), "p99_latency_s": float(np.percentile(lat, 99)),
             "mean_latency_s": float(np.mean(lat)),
             "cell_steps_per_s": cell_steps / wall if wall > 0 else 0.0,
+            "executed_cell_steps_per_s": executed / wall if wall > 0 else 0.0,
+            "queued_or_active_at_end": len(requests) - len(done),
             "peak_hbm_bytes": self.peak_in_use, "done": done,
         }
 

@@ -63,3 +63,28 @@ def test_batch_graph_replays_equal_direct(tile_y):
     d.check()
     g.close()
     d.close()
+
+
+@pytest.mark.parametrize("dim,n", [(2, 70), (3, 20)])
+def test_prepare_and_set_stream_change_nothing(dim, n):
+    # graphs captured ahead by c4m_prepare on a set-up stream, the problem
+    # then moved to another stream: same bits as a problem stepped plainly
+    import torch
+    from paper_2306_17263_amd import Problem
+    init = random_fields(dim, n, seed=n)
+    setup, work = torch.cuda.Stream(), torch.cuda.Stream()
+    a = Problem(dim, n, 0.4, stream=setup)
+    b = Problem(dim, n, 0.4, stream=work)
+    for p in (a, b):
+        for name in p.fields():
+            p.set(name, init[name])
+    a.prepare(70)
+    a.prepare(6)
+    a.set_stream(work)
+    for k in (70, 6, 0, 33):
+        a.step(k)
+        b.step(k)
+    for name in a.fields():
+        assert np.array_equal(a.get(name), b.get(name)), name
+    a.close()
+    b.close()

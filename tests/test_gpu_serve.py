@@ -17,7 +17,7 @@ def test_served_results_equal_alone_and_oracle():
     from workloads import mode_fields, serving_arrivals
     mix = serving_arrivals(count=10, seed=11, rate=400.0, n2=(24, 96), n3=(10, 20), steps=(8, 40))
     reqs = requests_from_mix(mix)
-    be = DeviceBackend(keep_results=True)
+    be = DeviceBackend(keep_results=True, chunk=7)
     budget = 3 * max(be.footprint(r) for r in reqs)            # forces queueing
     out = Server(be, hbm_budget=budget, chunk=7).run(reqs)
     assert out["completed"] == len(reqs)

@@ -1,6 +1,6 @@
 """Scheduling logic of the serving loop on the CPU: a fake backend (the
-oracle for the fields, a virtual clock for time) behind the same interface
-as the device backend."""
+oracle for the fields, a virtual clock for time, one serial device on which
+launched chunks queue up) behind the same interface as the device backend."""
 import numpy as np
 import pytest
 
@@ -30,6 +30,9 @@ class FakeBackend:
         self.steps_done = {}
         self.live = set()
         self.max_live = 0
+        self.device_free = 0.0
+        self.outstanding = set()
+        self.launches = 0
 
     def footprint(self, req):
         return req.cells * self.bpc
@@ -44,16 +47,41 @@ class FakeBackend:
         self.max_live = max(self.max_live, len(self.live))
         return p
 
-    def step(self, a2, a3, k):
+    def launch(self, reqs, k):
         assert k >= 1
-        for r in a2 + a3:
+        assert len({r.dim for r in reqs}) == 1 and (reqs[0].dim == 2 or len(reqs) == 1)
+        for r in reqs:
             assert self.steps_done[r.id] + k <= r.steps          # never overshoots
             r.handle.step(k)
             self.steps_done[r.id] += k
-        self.clock.advance(self.cost * k * sum(r.cells for r in a2 + a3))
+        start = max(self.device_free, self.clock())
+        self.device_free = start + self.cost * k * sum(r.cells for r in reqs)
+        self.outstanding.add(self.device_free)
+        self.launches += 1
+        return self.device_free
 
-    def sync(self):
-        pass
+    def can_launch(self, req):
+        return True
+
+    def done(self, token):
+        if self.clock() >= token:
+            self.outstanding.discard(token)
+            return True
+        return False
+
+    def idle(self):
+        if self.outstanding:
+            self.clock.t = max(self.clock.t, min(self.outstanding))
+        else:
+            self.clock.advance(1e-6)
+
+    def drain(self):
+        self.clock.t = max([self.clock.t] + list(self.outstanding))
+        self.outstanding.clear()
+
+    def abandon(self, req):
+        self.live.discard(req.id)
+        req.handle = None
 
     def finish(self, req):
         names = ["ez", "hx", "hy"] if req.dim == 2 else ["ex", "ey", "ez", "hx", "hy", "hz"]
@@ -118,3 +146,30 @@ def test_latency_percentiles_reported():
     out = Server(FakeBackend(clock), hbm_budget=10 ** 9, chunk=4, clock=clock).run(_mix(10))
     assert 0 <= out["p50_latency_s"] <= out["p99_latency_s"]
     assert out["cell_steps_per_s"] > 0
+
+
+def test_units_progress_independently():
+    # a long 3D request admitted first does not hold back 2D requests that
+    # arrive after it: their chunks interleave with its chunks on the device
+    from paper_2306_17263_amd.serve import Request
+    clock = VirtualClock()
+    be = FakeBackend(clock)
+    reqs = [Request(id=0, t_arrive=0.0, dim=3, n=10, k=(1, 1, 1), steps=40, r=0.4),
+            Request(id=1, t_arrive=1e-7, dim=2, n=12, k=(1, 2), steps=4),
+            Request(id=2, t_arrive=2e-7, dim=2, n=16, k=(2, 1), steps=6)]
+    out = Server(be, hbm_budget=10 ** 9, chunk=2, clock=clock).run(reqs)
+    assert out["completed"] == 3
+    t = {r.id: r.t_done for r in out["done"]}
+    assert t[1] < t[0] and t[2] < t[0]
+    assert be.steps_done == {0: 40, 1: 4, 2: 6}
+
+
+def test_time_limit_releases_unfinished_requests():
+    clock = VirtualClock()
+    be = FakeBackend(clock, cost_per_cell_step=1e-6)
+    reqs = _mix(12)
+    srv = Server(be, hbm_budget=10 ** 9, chunk=2, clock=clock)
+    out = srv.run(reqs, time_limit=1e-3)
+    assert out["completed"] < len(reqs)
+    assert srv.in_use == 0 and not be.live
+    assert out["queued_or_active_at_end"] == len(reqs) - out["completed"]
