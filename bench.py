@@ -308,7 +308,7 @@ def main():
     ap.add_argument("--serve-chunk", type=int, default=96)
     ap.add_argument("--serve-skip-full", action="store_true", help="serving: only the 200/s run")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
-    ap.add_argument("--solver", default="chebyshev", choices=["chebyshev", "pcg"],
+    ap.add_argument("--solver", default="chebyshev", choices=["chebyshev", "pcg", "transform"],
                     help="2d/3d workloads: fused fixed-sweep Chebyshev (default) or PCG with device reductions")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="for a rocprofv3 --pmc run: one plain copy kernel of known size, then a few "
@@ -412,6 +412,8 @@ def main():
                 "per_kernel_avg_us": {c: round(v["avg_us"], 3) for c, v in per.items()}}
     step_alg = sum(per[c]["alg_bytes"] for c in per)
     roofline["step_frac"] = round(step_alg * value * 1e6 / cells / 1e9 / HBM_PEAK_GBS, 4)
+    if args.solver == "transform":
+        roofline = transform_roofline(2, n, per)
 
     # ---- CPU baseline: the oracle on the host cores, bounded sample of the
     # same workload; the device result after the same steps is compared.
@@ -464,7 +466,7 @@ def main():
                    "precision": args.precision,
                    "n": n, "mode": list(k), "cfl": cfl, "closure": args.closure,
                    "lap_mode": args.lap,
-                   "solver": f"chebyshev x{sweeps}" if args.solver == "chebyshev" else "pcg"},
+                   "solver": f"chebyshev x{sweeps}" if args.solver == "chebyshev" else args.solver},
         "l2_vs_exact": l2_exact,
         "parity_sample": parity,
         **({"pcg": pcg_stats} if pcg_stats else {}),
@@ -750,6 +752,8 @@ def bench_3d(args):
                 "step_alg_bytes_per_cell": round(step_alg / cells, 3),
                 "per_kernel_avg_us": {c: round(v["avg_us"], 3) for c, v in per.items()},
                 "step_frac": round(step_alg * steps / elapsed / 1e9 / HBM_PEAK_GBS, 4)}
+    if args.solver == "transform":
+        roofline = transform_roofline(3, n, per)
     line = {
         "metric": METRIC,
         "value": round(value, 2), "unit": "Mcell-steps/s", "n_gpus": 1, "steps": steps, "warmup": min(args.warmup, 4),
@@ -894,6 +898,35 @@ def bench_sweep(args):
     print(json.dumps(line), flush=True)
 
 
+MFMA_F64_PEAK_TFLOPS = 78.6
+
+
+def transform_flops(dim: int, n: int) -> dict:
+    """Algorithmic flops of one launch group of the transform solve (a dense
+    product per axis forward and back, 2 flops per multiply-add): 2D solve_e
+    = Ez, solve_h = Hx and Hy; 3D one component of either kind."""
+    def solve(sizes):
+        cells = 1
+        for v in sizes:
+            cells *= v
+        return 2.0 * cells * 2 * sum(sizes)        # forward and inverse along every axis
+    if dim == 2:
+        return {"solve_e": solve((n - 1, n - 1)), "solve_h": 2 * solve((n - 1, n))}
+    return {"solve_e": solve((n, n - 1, n - 1)), "solve_h": solve((n - 1, n, n))}
+
+
+def transform_roofline(dim: int, n: int, per: dict) -> dict:
+    fl = transform_flops(dim, n)
+    dom = max(fl, key=lambda c: per[c]["avg_us"] * per[c]["launches"])
+    ach = fl[dom] / (per[dom]["avg_us"] * 1e-6) / 1e12
+    return {"bound": "mfma", "achieved": round(ach, 2), "peak": MFMA_F64_PEAK_TFLOPS, "unit": "TFLOP/s",
+            "frac": round(ach / MFMA_F64_PEAK_TFLOPS, 4), "traffic": None, "kernel": dom,
+            "kernels": "k_gemm_f64 (FP64 MFMA 16x16x4 tiles): 4 products per 2D component, 6 per 3D one",
+            "flops_per_launch_group": fl[dom], "avg_us": round(per[dom]["avg_us"], 3),
+            "note": "2D solve classes also hold the right-hand-side kernel of the component",
+            "per_kernel_avg_us": {c: round(v["avg_us"], 3) for c, v in per.items()}}
+
+
 def bench_serve(args):
     """Serving form: Poisson arrivals (seed 17263) of mixed 2D (N 64..1024)
     and 3D (N 32..128) cavity solves of 100..2000 steps, admitted by HBM
@@ -922,7 +955,8 @@ def bench_serve(args):
         reqs = requests_from_mix(serving_arrivals(count=count, seed=17263, rate=rate))
         print(f"serve run {label}: {count} requests at {rate:.3f}/s, limit {limit}", file=sys.stderr, flush=True)
         be = DeviceBackend(settings=settings, chunk=args.serve_chunk)
-        out = Server(be, hbm_budget=budget, chunk=args.serve_chunk).run(reqs, time_limit=limit)
+        out = Server(be, hbm_budget=budget, chunk=args.serve_chunk).run(
+            reqs, time_limit=limit, progress=lambda t: print(f"  {label}: {t}", file=sys.stderr, flush=True))
         torch.cuda.synchronize()
         d2 = [r for r in out["done"] if r.dim == 2]
         d3 = [r for r in out["done"] if r.dim == 3]

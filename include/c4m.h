@@ -76,7 +76,9 @@ enum { C4M_SCHEME_C4 = 0,        /* the compact fourth-order scheme (Section 3.4
                                   * CFL bound 6/(7 sqrt 2) (leapfrog with K4)       */
 enum { C4M_SOLVER_CHEBYSHEV = 0, /* reduction-free Chebyshev on the closed-form     *
                                   * spectral bounds of M (Appendix A.2)             */
-       C4M_SOLVER_PCG = 1 };     /* Jacobi-preconditioned CG with device dot products */
+       C4M_SOLVER_PCG = 1,       /* Jacobi-preconditioned CG with device dot products */
+       C4M_SOLVER_TRANSFORM = 2 }; /* exact: DST-I / DCT-II along each axis (Appendix *
+                                  * A.2) as FP64 matrix products; FP64 only         */
 
 #define C4M_FLAG_ALLOW_ANY_CFL 0x1u   /* skip the CFL guard of create               */
 #define C4M_FLAG_CHECK_FINITE  0x2u   /* scan the fields for NaN/Inf after each call */

@@ -12,7 +12,7 @@ FIELD = {"ex": 0, "ey": 1, "ez": 2, "hx": 3, "hy": 4, "hz": 5, "lx": 6, "ly": 7,
 CLOSURE = {"paper": 0, "reflect": 1}
 LAP = {"tracked": 0, "discrete": 1}
 PRECISION = {"fp64": 0, "fp32_refined": 1}
-SOLVER = {"chebyshev": 0, "pcg": 1}
+SOLVER = {"chebyshev": 0, "pcg": 1, "transform": 2}
 SCHEME = {"c4": 0, "nc": 1}
 FLAG_ALLOW_ANY_CFL = 0x1
 FLAG_CHECK_FINITE = 0x2

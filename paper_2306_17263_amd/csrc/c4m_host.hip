@@ -31,6 +31,13 @@ hipError_t launch_pcg_e_2d(hipStream_t st, bool tracked, const double* hx, doubl
                            const double* t0, double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
                            const PadeLine& line_h2n, const ChebSchedule& cs, double* const* pt, double* part,
                            PcgState* pst, double rtol, int max_iter);
+hipError_t launch_tsolve_e_2d(hipStream_t st, bool tracked, const double* hx, double* ez, double* ge,
+                              const double* t0, double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
+                              const PadeLine& line_h2n, const ChebSchedule& cs, double* const* pt,
+                              const TransformTables& tt);
+hipError_t launch_tsolve_h_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy, double* t1,
+                              int N, int P, const Coef& cf, const PadeTaps& taps, const PadeLine& line_n2h,
+                              const ChebSchedule& cs, double* const* pt, const TransformTables& tt);
 hipError_t launch_pcg_h_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy, double* t1,
                            int N, int P, const Coef& cf, const PadeTaps& taps, const PadeLine& line_n2h,
                            const ChebSchedule& cs, double* const* pt, double* part, PcgState* pst, double rtol,
@@ -306,6 +313,9 @@ struct c4m_problem {
     PcgState* pcg_state = nullptr;      // PCG scalars and statistics
     double* pade_dev[2] = {};           // [0] node->half (n_in N+1), [1] half->node (n_in N)
     double* yband = nullptr;            // 2D strip form: band derivatives near the y-line ends
+    double* tr_dev = nullptr;           // transform solver tables
+    TransformTables tt{};
+    std::vector<double> tr_host;        // their image (kept until the upload completed)
     int* counter = nullptr;
     PadeHost pade_host[2];
     std::vector<double> line_img[2];    // device table images (kept until the upload completed)
@@ -371,7 +381,7 @@ c4m_status validate(const c4m_config* c)
         return fail(C4M_EINVAL, "bad lap_mode");
     if (c->precision != C4M_FP64 && c->precision != C4M_FP32_REFINED)
         return fail(C4M_EINVAL, "bad precision");
-    if (c->solver != C4M_SOLVER_CHEBYSHEV && c->solver != C4M_SOLVER_PCG)
+    if (c->solver != C4M_SOLVER_CHEBYSHEV && c->solver != C4M_SOLVER_PCG && c->solver != C4M_SOLVER_TRANSFORM)
         return fail(C4M_EINVAL, "bad solver");
     if (c->sweeps < 0 || c->sweeps > MAX_SWEEPS) return fail(C4M_EINVAL, "sweeps out of range");
     if (c->scheme != C4M_SCHEME_C4 && c->scheme != C4M_SCHEME_NC) return fail(C4M_EINVAL, "bad scheme");
@@ -391,6 +401,8 @@ c4m_status validate(const c4m_config* c)
         return fail(C4M_EUNSTABLE, "cfl above the stability bound 5/(6 sqrt(dim))");
     if (c->solver == C4M_SOLVER_PCG && c->precision != C4M_FP64)
         return fail(C4M_EINVAL, "the PCG solver runs in FP64 only");
+    if (c->solver == C4M_SOLVER_TRANSFORM && c->precision != C4M_FP64)
+        return fail(C4M_EINVAL, "the transform solver runs in FP64 only");
     if (c->max_iter < 0 || c->max_iter > 1000) return fail(C4M_EINVAL, "max_iter out of range");
     if (!(c->rtol >= 0.0) || c->rtol >= 1.0) return fail(C4M_EINVAL, "rtol must be in [0, 1)");
     if (c->precision == C4M_FP32_REFINED && (c->sweeps > 3 || (c->dim == 2 && c->tile_x != 0)))
@@ -400,7 +412,7 @@ c4m_status validate(const c4m_config* c)
 
 struct Layout {
     int P;
-    size_t plane, arr, arr_bytes, table_bytes[2], pcg_bytes, band_bytes, total;
+    size_t plane, arr, arr_bytes, table_bytes[2], pcg_bytes, band_bytes, tr_bytes, total;
     int n_fields, n_ge, n_tmp;
 };
 
@@ -416,10 +428,12 @@ Layout layout(const c4m_config* c)
     const bool nc = c->scheme == C4M_SCHEME_NC;
     L.n_ge = (c->lap_mode == C4M_LAP_TRACKED && !nc) ? (c->dim == 2 ? 1 : 3) : 0;
     const bool pcg = c->solver == C4M_SOLVER_PCG && !nc;
+    const bool tr = c->solver == C4M_SOLVER_TRANSFORM && !nc;
     // 2D: T0, T1 (+ x, r, two directions, M p, 1/diag, z for PCG);
     // 3D: b, x, d0, d1, curl (+ M p, 1/diag, z for PCG), then the three
     // conditioned sources of the line terms
-    L.n_tmp = nc ? 1 : (c->dim == 2 ? (pcg ? 9 : 2) : (pcg ? 8 : 5) + 3);
+    L.n_tmp = nc ? 1 : (c->dim == 2 ? (pcg || tr ? 9 : 2) : (pcg ? 8 : 5) + 3);
+    L.tr_bytes = tr ? align256(transform_table_doubles(N) * sizeof(double)) : 0;
     L.pcg_bytes = pcg ? align256(3 * ((L.arr + 255) / 256) * sizeof(double)) + 256 : 0;
     for (int k = 0; k < 2; ++k) {
         const int n_out = (k == 0 ? N + 1 : N) - 1;
@@ -427,7 +441,7 @@ Layout layout(const c4m_config* c)
     }
     // 2D strip form: raw and conditioned derivatives of the band rows at both ends
     L.band_bytes = (c->dim == 2 && !nc) ? align256((size_t)4 * YB_ROWS * L.P * sizeof(double)) : 0;
-    L.total = (size_t)(L.n_fields + L.n_ge + L.n_tmp) * L.arr_bytes + L.pcg_bytes + L.band_bytes +
+    L.total = (size_t)(L.n_fields + L.n_ge + L.n_tmp) * L.arr_bytes + L.pcg_bytes + L.band_bytes + L.tr_bytes +
               L.table_bytes[0] + L.table_bytes[1] + 256;
     return L;
 }
@@ -560,6 +574,7 @@ c4m_status step3(c4m_problem* p)
     const double z = p->coef.z;
     double *b = p->tmp[0], *x = p->tmp[1], *d0 = p->tmp[2], *d1 = p->tmp[3], *cur = p->tmp[4];
     const bool pcg = p->cfg.solver == C4M_SOLVER_PCG;
+    const bool tsolve = p->cfg.solver == C4M_SOLVER_TRANSFORM;
     auto pcg_args = [&](int comp) {
         PcgArgs a{};
         a.x = x;
@@ -607,6 +622,9 @@ c4m_status step3(c4m_problem* p)
         });
         if (s != C4M_OK) break;
         s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
+            if (tsolve)
+                return launch_transform_solve(p->stream, 3, p->tt, unknowns(p->box[c]), p->P, p->plane, b, x, d0,
+                                              p->f[c], tracked ? p->ge[c] : nullptr, cur, p->coef);
             if (pcg)
                 return launch_pcg(p->stream, 3, pcg_args(c), pcg_max_iter(p), p->f[c], tracked ? p->ge[c] : nullptr,
                                   cur, p->coef);
@@ -629,6 +647,9 @@ c4m_status step3(c4m_problem* p)
         });
         if (s != C4M_OK) break;
         s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
+            if (tsolve)
+                return launch_transform_solve(p->stream, 3, p->tt, unknowns(p->box[3 + c]), p->P, p->plane, b, x, d0,
+                                              p->f[3 + c], nullptr, nullptr, p->coef);
             if (pcg)
                 return launch_pcg(p->stream, 3, pcg_args(3 + c), pcg_max_iter(p), p->f[3 + c], nullptr, nullptr,
                                   p->coef);
@@ -664,7 +685,7 @@ c4m_status step_once(c4m_problem* p)
         // the strip form (band table filled by the x-line launches): one
         // buffer resource spans the arrays it touches, so the used part of
         // the workspace must stay below 4 GiB
-        double* yb = (!pcg && p->yband && p->used < (size_t)0xFFFFF000u &&
+        double* yb = (p->cfg.solver == C4M_SOLVER_CHEBYSHEV && p->yband && p->used < (size_t)0xFFFFF000u &&
                       strip_form_2d(p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, p->cheb.sweeps))
                          ? p->yband
                          : nullptr;
@@ -672,7 +693,13 @@ c4m_status step_once(c4m_problem* p)
             return launch_rhs_e_2d(p->stream, tracked, hx, hy, t0, t1, N, P, p->coef,
                                    p->pade_host[1].taps, p->line[1], yb);
         });
-        if (s == C4M_OK && pcg)
+        const bool tsolve = p->cfg.solver == C4M_SOLVER_TRANSFORM;
+        if (s == C4M_OK && tsolve)
+            s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
+                return launch_tsolve_e_2d(p->stream, tracked, hx, ez, ge, t0, t1, N, P, p->coef, p->pade_host[1].taps,
+                                          p->line[1], p->cheb, p->tmp + 2, p->tt);
+            });
+        else if (s == C4M_OK && pcg)
             s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
                 return launch_pcg_e_2d(p->stream, tracked, hx, ez, ge, t0, t1, N, P, p->coef, p->pade_host[1].taps,
                                        p->line[1], p->cheb, p->tmp + 2, p->pcg_part, p->pcg_state, pcg_rtol(p),
@@ -688,7 +715,12 @@ c4m_status step_once(c4m_problem* p)
                 return launch_rhs_h_2d(p->stream, tracked, tracked ? ge : ez, t0, t1, N, P, p->coef,
                                        p->pade_host[0].taps, p->line[0], yb);
             });
-        if (s == C4M_OK && pcg)
+        if (s == C4M_OK && tsolve)
+            s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
+                return launch_tsolve_h_2d(p->stream, tracked, tracked ? ge : ez, hx, hy, t1, N, P, p->coef,
+                                          p->pade_host[0].taps, p->line[0], p->cheb, p->tmp + 2, p->tt);
+            });
+        else if (s == C4M_OK && pcg)
             s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
                 return launch_pcg_h_2d(p->stream, tracked, tracked ? ge : ez, hx, hy, t1, N, P, p->coef,
                                        p->pade_host[0].taps, p->line[0], p->cheb, p->tmp + 2, p->pcg_part,
@@ -907,6 +939,7 @@ c4m_status c4m_create(const c4m_config* cfg_in, void* d_workspace, size_t bytes,
         p->pcg_part = (double*)take(L.pcg_bytes - 256);
     }
     if (L.band_bytes) p->yband = (double*)take(L.band_bytes);
+    if (L.tr_bytes) p->tr_dev = (double*)take(L.tr_bytes);
     p->pade_dev[0] = (double*)take(L.table_bytes[0]);
     p->pade_dev[1] = (double*)take(L.table_bytes[1]);
     p->counter = (int*)take(256);
@@ -947,8 +980,18 @@ c4m_status c4m_create(const c4m_config* cfg_in, void* d_workspace, size_t bytes,
             return hip_fail(e, "table upload");
         }
     }
+    if (p->tr_dev) {
+        p->tr_host.resize(transform_table_doubles(p->N));
+        build_transform_tables(p->N, p->tr_host.data(), &p->tt, p->tr_dev);
+        hipError_t e = hipMemcpyAsync(p->tr_dev, p->tr_host.data(), p->tr_host.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, p->stream);
+        if (e != hipSuccess) {
+            delete p;
+            return hip_fail(e, "transform table upload");
+        }
+    }
     // zero fields, G_E and temporaries
-    const size_t zero_bytes = (size_t)((char*)p->pade_dev[0] - p->ws);
+    const size_t zero_bytes = (size_t)((char*)(p->tr_dev ? p->tr_dev : p->pade_dev[0]) - p->ws);
     s = memset_async(p, p->ws, zero_bytes);
     if (s == C4M_OK) s = memset_async(p, p->counter, 256);
     if (s == C4M_OK) {

@@ -107,6 +107,21 @@ struct Cheb3 {
     size_t plane;
 };
 
+// Device tables of the transform solve for one N (c4m_transform.hip):
+// orthonormal DST-I (N-1 x N-1), DCT-II (N x N) and its transpose, sigma.
+struct TransformTables {
+    const double* S;
+    const double* C;
+    const double* Ct;
+    const double* sig_d;
+    const double* sig_n;
+};
+size_t transform_table_doubles(int N);
+void build_transform_tables(int N, double* host, TransformTables* t, double* dev);
+hipError_t launch_transform_solve(hipStream_t st, int dim, const TransformTables& t, const UGrid& g, int P,
+                                  size_t plane, const double* b, double* w1, double* w2, double* field, double* ge,
+                                  const double* cur, const Coef& cf);
+
 // PCG solve state on the device (one per problem).
 struct PcgState {
     int arrived;          // workgroups that published their partials (reset by the last)

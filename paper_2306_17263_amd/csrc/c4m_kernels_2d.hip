@@ -374,4 +374,33 @@ hipError_t launch_pcg_h_2d(hipStream_t st, bool tracked, const double* src, doub
                       cf);
 }
 
+// The same right-hand sides as the PCG form, solved by the transforms
+// (pt[0], pt[2]: work arrays; pt[1]: b).
+hipError_t launch_tsolve_e_2d(hipStream_t st, bool tracked, const double* hx, double* ez, double* ge,
+                              const double* t0, double* t1, int N, int P, const Coef& cf, const PadeTaps& taps,
+                              const PadeLine& line_h2n, const ChebSchedule& cs, double* const* pt,
+                              const TransformTables& tt)
+{
+    ColArgs a{hx, t0, t1, ez, ge, ugrid_ez(N), N, P, pt[1], t1};
+    hipError_t e = tracked ? launch_col_rhs<COL_E_TRACKED>(st, a, cf, taps, line_h2n, cs)
+                           : launch_col_rhs<COL_E_DISCRETE>(st, a, cf, taps, line_h2n, cs);
+    if (e != hipSuccess) return e;
+    return launch_transform_solve(st, 2, tt, ugrid_ez(N), P, 0, pt[1], pt[0], pt[2], ez, tracked ? ge : nullptr, t1,
+                                  cf);
+}
+
+hipError_t launch_tsolve_h_2d(hipStream_t st, bool tracked, const double* src, double* hx, double* hy, double* t1,
+                              int N, int P, const Coef& cf, const PadeTaps& taps, const PadeLine& line_n2h,
+                              const ChebSchedule& cs, double* const* pt, const TransformTables& tt)
+{
+    ColArgs ax{src, nullptr, nullptr, hx, nullptr, ugrid_hx(N), N, P, pt[1], nullptr};
+    hipError_t e = tracked ? launch_col_rhs<COL_HX_TRACKED>(st, ax, cf, taps, line_n2h, cs)
+                           : launch_col_rhs<COL_HX_DISCRETE>(st, ax, cf, taps, line_n2h, cs);
+    if (e != hipSuccess) return e;
+    e = launch_transform_solve(st, 2, tt, ugrid_hx(N), P, 0, pt[1], pt[0], pt[2], hx, nullptr, nullptr, cf);
+    if (e != hipSuccess) return e;
+    // Hy: the x-line right-hand side T1 is b
+    return launch_transform_solve(st, 2, tt, ugrid_hy(N), P, 0, t1, pt[0], pt[2], hy, nullptr, nullptr, cf);
+}
+
 }  // namespace c4m

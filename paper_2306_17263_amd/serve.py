@@ -215,7 +215,9 @@ class Server:
         self.in_use = 0
         self.peak_in_use = 0
 
-    def run(self, requests, time_limit: float | None = None) -> dict:
+    def run(self, requests, time_limit: float | None = None, progress=None, progress_every: float = 20.0) -> dict:
+        """Serve `requests`; `progress(text)` (if given) is called about every
+        `progress_every` seconds with the counts so far."""
         pending = sorted(requests, key=lambda q: q.t_arrive)
         queue, done = [], []
         active2, active3 = [], []
@@ -226,8 +228,13 @@ class Server:
         i = 0
         chunks = 0
         executed = 0.0              # cell-steps of finished chunks, finished requests or not
+        next_report = progress_every
         while i < len(pending) or queue or active2 or active3 or starting:
             now = self.clock() - t0
+            if progress is not None and now >= next_report:
+                next_report += progress_every
+                progress(f"t={now:.0f}s arrived={i} queued={len(queue)} active={len(active2) + len(active3)} "
+                         f"done={len(done)} executed={executed / max(now, 1e-9) / 1e6:.0f} Mcell-steps/s")
             if time_limit is not None and now > time_limit:
                 break
             while i < len(pending) and pending[i].t_arrive <= now:
