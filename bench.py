@@ -36,7 +36,7 @@ LAPS_O = {"tracked": 0, "discrete": 1}
 BATCH_KERNELS = {
     ("rhs_e", True): "k_batch_stage<K, T, 0> (Step 1 x-line tiles: raw x-derivatives, T0 on the end-band columns; band-table rows)",
     ("solve_e", True): "k_batch_stage<K, T, 1> (Step 1 wave strips: y-lines, T0, Chebyshev solve, Ez and G_E update)",
-    ("rhs_h", True): "k_batch_stage<K, T, 2> (Step 2 x-line tiles of G_E; band-table rows)",
+    ("rhs_h", True): "k_batch_xstage<T, 2> (Step 2 x-line tiles of G_E; band-table rows; one workgroup per item)",
     ("solve_h", True): "k_batch_stage<K, T, 3> (Step 2 Hx and Hy wave strips: solves and updates)",
     ("step", False): "k_batch_step<K, T> (the whole step: all four stages, per-problem stage counters)",
 }
@@ -46,7 +46,7 @@ BATCH_KERNELS = {
 # not void its counter results)
 KERNEL_SOURCES = {
     "2d": ["c4m_internal.h", "c4m_tiles_2d.h", "c4m_stream_2d.h", "c4m_kernels_2d.hip", "c4m_host.hip"],
-    "batch": ["c4m_internal.h", "c4m_tiles_2d.h", "c4m_stream_2d.h", "c4m_batch.hip", "c4m_host.hip"],
+    "batch": ["c4m_internal.h", "c4m_tiles_2d.h", "c4m_stream_2d.h", "c4m_batch.hip"],
     "3d": ["c4m_internal.h", "c4m_kernels_3d.hip", "c4m_host.hip"],
 }
 
@@ -112,9 +112,9 @@ CALLS_3D = {"rhs_e": 3, "rhs_h": 3, "solve": 6}
 # kernel-class -> kernel-name pattern of the batched form (strip stage
 # launches, the single launch per step, the column-tile form)
 BATCH_CLASS_PATTERNS = {
-    "rhs_e": r"k_batch_stage<\d+, (?:true|false), 0>|k_batch_x<[01]>",
+    "rhs_e": r"k_batch_stage<\d+, (?:true|false), 0>|k_batch_xstage<(?:true|false), 0>|k_batch_x<[01]>",
     "solve_e": r"k_batch_stage<\d+, (?:true|false), 1>|k_batch_col<\d+, [01],",
-    "rhs_h": r"k_batch_stage<\d+, (?:true|false), 2>|k_batch_x<[23]>",
+    "rhs_h": r"k_batch_stage<\d+, (?:true|false), 2>|k_batch_xstage<(?:true|false), 2>|k_batch_x<[23]>",
     "solve_h": r"k_batch_stage<\d+, (?:true|false), 3>|k_batch_col<\d+, [234],",
     "step": r"k_batch_step<",
 }

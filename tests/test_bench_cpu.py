@@ -50,11 +50,13 @@ def test_class_patterns_attribute_each_kernel_to_one_class():
 
 BATCH_NAMES = {
     "rhs_e": ["void c4m::k_batch_stage<5, true, 0>(c4m::BatchProb const*, c4m::Sched, c4m::Coef)",
-              "void c4m::k_batch_x<1>(c4m::BatchProb const*, c4m::Sched, int, c4m::Coef, c4m::PadeTaps)"],
+              "void c4m::k_batch_x<1>(c4m::BatchProb const*, c4m::Sched, int, c4m::Coef, c4m::PadeTaps)",
+              "void c4m::k_batch_xstage<true, 0>(c4m::BatchProb const*, c4m::Sched, c4m::Coef, c4m::PadeTaps)"],
     "solve_e": ["void c4m::k_batch_stage<5, false, 1>(c4m::BatchProb const*, c4m::Sched)",
                 "void c4m::k_batch_col<5, 0, c4m::TileShape<128, 2>, 0>(c4m::BatchProb const*)"],
     "rhs_h": ["void c4m::k_batch_stage<6, true, 2>(c4m::BatchProb const*, c4m::Sched)",
-              "void c4m::k_batch_x<2>(c4m::BatchProb const*, c4m::Sched, int, c4m::Coef, c4m::PadeTaps)"],
+              "void c4m::k_batch_x<2>(c4m::BatchProb const*, c4m::Sched, int, c4m::Coef, c4m::PadeTaps)",
+              "void c4m::k_batch_xstage<false, 2>(c4m::BatchProb const*, c4m::Sched, c4m::Coef, c4m::PadeTaps)"],
     "solve_h": ["void c4m::k_batch_stage<5, true, 3>(c4m::BatchProb const*, c4m::Sched)",
                 "void c4m::k_batch_col<5, 4, c4m::TileShape<64, 4>, 0>(c4m::BatchProb const*)",
                 "void c4m::k_batch_col<5, 2, c4m::TileShape<128, 2>, 1>(c4m::BatchProb const*)"],
