@@ -306,6 +306,10 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=None,
                     help="serving: rate of the full-mix run (default 70%% of the measured capacity)")
     ap.add_argument("--serve-chunk", type=int, default=96)
+    ap.add_argument("--serve-chunk3", type=int, default=32, help="serving: steps per chunk of the 3D cohort")
+    ap.add_argument("--serve-active", type=int, default=32, help="serving: requests active at once")
+    ap.add_argument("--serve-streams", type=int, default=8, help="serving: side streams of the 3D requests")
+    ap.add_argument("--serve-queues", type=int, default=16, help="serving: HIP hardware queues of the process")
     ap.add_argument("--serve-skip-full", action="store_true", help="serving: only the 200/s run")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_refined"])
     ap.add_argument("--solver", default="chebyshev", choices=["chebyshev", "pcg", "transform"],
@@ -939,7 +943,7 @@ def bench_serve(args):
     The loop runs on several streams (the 2D cohort, the 3D requests, the
     set-up of new requests); the process asks HIP for 8 hardware queues so
     that set-up copies do not queue behind another stream's kernels."""
-    os.environ["GPU_MAX_HW_QUEUES"] = "8"        # read when HIP initialises (not yet here)
+    os.environ["GPU_MAX_HW_QUEUES"] = str(args.serve_queues)   # read when HIP initialises (not yet here)
     import torch
     from paper_2306_17263_amd.serve import DeviceBackend, Server, requests_from_mix
     from workloads import serving_arrivals
@@ -954,8 +958,9 @@ def bench_serve(args):
     def one(label, rate, limit):
         reqs = requests_from_mix(serving_arrivals(count=count, seed=17263, rate=rate))
         print(f"serve run {label}: {count} requests at {rate:.3f}/s, limit {limit}", file=sys.stderr, flush=True)
-        be = DeviceBackend(settings=settings, chunk=args.serve_chunk)
-        out = Server(be, hbm_budget=budget, chunk=args.serve_chunk).run(
+        be = DeviceBackend(settings=settings, chunk=args.serve_chunk, n_side_streams=args.serve_streams)
+        out = Server(be, hbm_budget=budget, chunk=args.serve_chunk, chunk_3d=args.serve_chunk3,
+                     max_active=args.serve_active).run(
             reqs, time_limit=limit, progress=lambda t: print(f"  {label}: {t}", file=sys.stderr, flush=True))
         torch.cuda.synchronize()
         d2 = [r for r in out["done"] if r.dim == 2]

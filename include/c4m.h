@@ -85,6 +85,10 @@ enum { C4M_SOLVER_CHEBYSHEV = 0, /* reduction-free Chebyshev on the closed-form 
 #define C4M_FLAG_PROFILE       0x4u   /* time every launch (group) of a kernel class *
                                        * with HIP events on the problem's stream (no   *
                                        * host waits; c4m_get_info reads them)          */
+#define C4M_FLAG_DIRECT        0x8u   /* launch every step directly, never as a     *
+                                       * captured graph (for batches whose members   *
+                                       * change often, where a capture per new batch *
+                                       * would cost more than it saves)               */
 
 /* Kernel classes reported by the profiling counters of c4m_info. */
 enum { C4M_K_RHS_E = 0,      /* Pade curl of G(H): Step 1 right-hand side          */
@@ -272,13 +276,18 @@ c4m_status c4m_batch_check(c4m_batch* b);
 c4m_status c4m_batch_get_info(c4m_batch* b, c4m_info* info);
 c4m_status c4m_batch_destroy(c4m_batch* b);
 
-/* Batched form over 2D problems the caller already created (each on its own
+/* Batched form over problems the caller already created (each on its own
  * workspace, sharing cfl, z, closure, lap_mode, precision, solver, sweeps and
  * tiles).  `d_tables` (>= c4m_batch_tables_bytes of the same problems,
  * 256-byte aligned) holds only the work tables; the problems stay the
  * caller's, must outlive the batch, and keep their own stream-ordered state
  * (they are stepped on the batch's stream).  Lets a serving loop re-form
- * batches as requests come and go without moving resident fields. */
+ * batches as requests come and go without moving resident fields.
+ * 3D members (any N; FP64 Chebyshev form only, else EINVAL): every launch of
+ * the 3D step (Section 3.4, Step 1 and Step 2) runs once over all members,
+ * each member's share of the workgroups running the single-problem kernel
+ * body, so a member's fields equal those of the problem stepped alone, bit
+ * for bit.  c4m_batch_create takes 2D configurations only. */
 c4m_status c4m_batch_tables_bytes(c4m_problem* const* probs, int32_t count, size_t* bytes);
 c4m_status c4m_batch_create_from(c4m_problem* const* probs, int32_t count, void* d_tables,
                                  size_t bytes, void* hip_stream, c4m_batch** out);

@@ -17,6 +17,7 @@ SCHEME = {"c4": 0, "nc": 1}
 FLAG_ALLOW_ANY_CFL = 0x1
 FLAG_CHECK_FINITE = 0x2
 FLAG_PROFILE = 0x4
+FLAG_DIRECT = 0x8
 KERNEL_CLASSES = ["rhs_e", "solve_e", "rhs_h", "solve_h", "step_e", "step_h", "other", "step"]
 
 # every symbol include/c4m.h declares

@@ -533,6 +533,7 @@ using namespace c4m;
 namespace c4m {
 c4m_status problem_view(c4m_problem* p, ProblemView* v);
 c4m_status problem_prepare(c4m_problem* p);     // carried-Laplacian conversion before stepping
+const std::vector<Launch3>* problem_step3_plan(c4m_problem* p);
 c4m_status problem_create_owned(const c4m_config* cfg, void* ws, size_t bytes, hipStream_t st,
                                 c4m_problem** out);
 void problem_add_steps(c4m_problem* p, int64_t n);
@@ -558,6 +559,16 @@ struct c4m_batch {
     int blocks[NSTMAX] = {};       // workgroups of each launch
     bool owns = true;              // problems created by (and destroyed with) the batch
     bool strips = false;           // strip form: one launch per step
+    // 3D members: every launch of the recorded step over all members
+    bool three_d = false;
+    struct L3 {
+        Launch3 proto;             // member 0's record (kind, template choice, class)
+        size_t off;                // its member arguments in the table
+        unsigned blocks;           // workgroups over all members
+    };
+    std::vector<L3> l3;
+    char* d_tab3 = nullptr;
+    PadeTaps taps3[2]{};
     std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;   // captured runs of steps
     // C4M_FLAG_PROFILE: every launch bracketed by HIP events on the stream
     // (no graph, no host wait); read and summed by c4m_batch_get_info
@@ -585,7 +596,9 @@ c4m_status check_uniform(const c4m_config* cfgs, int32_t count)
     if (!cfgs || count < 1) return set_error(C4M_EINVAL, "empty batch");
     for (int i = 0; i < count; ++i) {
         const c4m_config& c = cfgs[i];
-        if (c.dim != 2) return set_error(C4M_EINVAL, "batched form takes 2D problems");
+        if (c.dim != cfgs[0].dim) return set_error(C4M_EINVAL, "batched problems must share the dimension");
+        if (c.dim == 3 && (c.precision != C4M_FP64 || c.solver != C4M_SOLVER_CHEBYSHEV))
+            return set_error(C4M_EINVAL, "batched 3D problems: FP64 Chebyshev form only");
         if (c.scheme != C4M_SCHEME_C4) return set_error(C4M_EINVAL, "batched form runs the compact scheme");
         if (c.solver != C4M_SOLVER_CHEBYSHEV)
             return set_error(C4M_EINVAL, "batched form runs the fused Chebyshev solve only");
@@ -1028,6 +1041,79 @@ c4m_status build_tables(c4m_batch* b, Layout& lay, char* cur, size_t bytes)
 
 }  // namespace
 
+namespace c4m {
+
+// Table bytes of the batched 3D step: every launch's member arguments.
+c4m_status plan_batch3(c4m_problem* const* probs, int count, std::vector<c4m_batch::L3>* l3, size_t* bytes)
+{
+    const std::vector<Launch3>* p0 = problem_step3_plan(probs[0]);
+    if (!p0) return set_error(C4M_EINVAL, "3D batch members must take the FP64 Chebyshev form");
+    size_t off = 0;
+    for (size_t i = 0; i < p0->size(); ++i) {
+        unsigned blocks = 0;
+        for (int m = 0; m < count; ++m) {
+            const std::vector<Launch3>* pm = problem_step3_plan(probs[m]);
+            if (!pm || pm->size() != p0->size() || (*pm)[i].kind != (*p0)[i].kind || (*pm)[i].axis != (*p0)[i].axis ||
+                (*pm)[i].mode != (*p0)[i].mode || (*pm)[i].first != (*p0)[i].first || (*pm)[i].out != (*p0)[i].out)
+                return set_error(C4M_EINVAL, "3D batch members differ in their step");
+            blocks += (*pm)[i].gx * (*pm)[i].gy * (*pm)[i].gz;
+        }
+        if (l3) l3->push_back(c4m_batch::L3{(*p0)[i], off, blocks});
+        off = (off + (size_t)count * launch3_arg_bytes((*p0)[i]) + 255) / 256 * 256;
+    }
+    *bytes = off + 256;
+    return C4M_OK;
+}
+
+c4m_status build_batch3(c4m_batch* b, char* d_tab, size_t bytes)
+{
+    size_t need = 0;
+    b->l3.clear();
+    c4m_status s = plan_batch3(b->probs.data(), b->count, &b->l3, &need);
+    if (s != C4M_OK) return s;
+    if (bytes < need) return set_error(C4M_ENOMEM, "table space smaller than c4m_batch_tables_bytes");
+    std::vector<char> host(need, 0);
+    for (size_t i = 0; i < b->l3.size(); ++i) {
+        const size_t ab = launch3_arg_bytes(b->l3[i].proto);
+        int first = 0;
+        for (int m = 0; m < b->count; ++m) {
+            const Launch3& r = (*problem_step3_plan(b->probs[m]))[i];
+            launch3_pack(r, first, host.data() + b->l3[i].off + (size_t)m * ab);
+            first += (int)(r.gx * r.gy * r.gz);
+        }
+    }
+    b->d_tab3 = d_tab;
+    hipError_t e = hipMemcpyAsync(d_tab, host.data(), need, hipMemcpyHostToDevice, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) return set_error(C4M_EDEVICE, "3D batch table upload");
+    ProblemView v{};
+    problem_view(b->probs[0], &v);
+    b->taps3[0] = v.taps[0];
+    b->taps3[1] = v.taps[1];
+    b->three_d = true;
+    return C4M_OK;
+}
+
+c4m_status launch_step3b(c4m_batch* b)
+{
+    const size_t n = b->l3.size();
+    for (size_t i = 0; i < n;) {
+        size_t j = i;
+        while (j < n && b->l3[j].proto.cls == b->l3[i].proto.cls && b->l3[j].proto.group == b->l3[i].proto.group) ++j;
+        if (mark(b, b->l3[i].proto.cls, true) != C4M_OK) return C4M_EDEVICE;
+        for (size_t k = i; k < j; ++k) {
+            const c4m_batch::L3& l = b->l3[k];
+            hipError_t e = launch3_batched(b->stream, l.proto, b->d_tab3 + l.off, b->count, l.blocks, b->taps3);
+            if (e != hipSuccess) return set_error(C4M_EDEVICE, hipGetErrorString(e));
+        }
+        if (mark(b, b->l3[i].proto.cls, false) != C4M_OK) return C4M_EDEVICE;
+        i = j;
+    }
+    return C4M_OK;
+}
+
+}  // namespace c4m
+
 extern "C" {
 
 c4m_status c4m_batch_workspace_bytes(const c4m_config* cfgs, int32_t count, size_t* bytes)
@@ -1035,6 +1121,7 @@ c4m_status c4m_batch_workspace_bytes(const c4m_config* cfgs, int32_t count, size
     c4m_status s = check_uniform(cfgs, count);
     if (s != C4M_OK) return s;
     if (!bytes) return set_error(C4M_EINVAL, "null bytes");
+    if (cfgs[0].dim == 3) return set_error(C4M_EINVAL, "3D batches are formed from existing problems (c4m_batch_create_from)");
     Layout lay;
     s = plan_layout(cfgs, count, strips_fit_cfg(cfgs, count), lay);
     if (s != C4M_OK) return s;
@@ -1096,6 +1183,7 @@ c4m_status c4m_batch_tables_bytes(c4m_problem* const* probs, int32_t count, size
     std::vector<c4m_config> cfgs = member_configs(probs, count);
     c4m_status s = check_uniform(cfgs.data(), count);
     if (s != C4M_OK) return s;
+    if (cfgs[0].dim == 3) return plan_batch3(probs, count, nullptr, bytes);
     Layout lay;
     s = plan_layout(cfgs.data(), count, strips_fit(probs, count), lay);
     if (s != C4M_OK) return s;
@@ -1114,6 +1202,22 @@ c4m_status c4m_batch_create_from(c4m_problem* const* probs, int32_t count, void*
     std::vector<c4m_config> cfgs = member_configs(probs, count);
     c4m_status s = check_uniform(cfgs.data(), count);
     if (s != C4M_OK) return s;
+    if (cfgs[0].dim == 3) {
+        c4m_batch* b = new (std::nothrow) c4m_batch();
+        if (!b) return set_error(C4M_ENOMEM, "host allocation");
+        b->count = count;
+        b->base = cfgs[0];
+        b->stream = (hipStream_t)hip_stream;
+        b->owns = false;
+        b->probs.assign(probs, probs + count);
+        s = build_batch3(b, (char*)d_tables, bytes);
+        if (s != C4M_OK) {
+            delete b;
+            return s;
+        }
+        *out = b;
+        return C4M_OK;
+    }
     Layout lay;
     s = plan_layout(cfgs.data(), count, strips_fit(probs, count), lay);
     if (s != C4M_OK) return s;
@@ -1150,13 +1254,13 @@ c4m_status c4m_batch_step(c4m_batch* b, int64_t nsteps)
         if (s != C4M_OK) return s;
     }
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    bool direct = (b->base.flags & C4M_FLAG_PROFILE) || !b->stream;
+    bool direct = (b->base.flags & (C4M_FLAG_PROFILE | C4M_FLAG_DIRECT)) || !b->stream;
     if (!direct && hipStreamIsCapturing(b->stream, &cap) != hipSuccess) direct = true;
     if (direct || cap != hipStreamCaptureStatusNone) {
         // profiled (every launch timed by events on the stream), the null
         // stream (no capture), or captured by the caller: no graph
         for (int64_t t = 0; t < nsteps; ++t) {
-            c4m_status s = launch_step(b);
+            c4m_status s = b->three_d ? launch_step3b(b) : launch_step(b);
             if (s != C4M_OK) return s;
         }
         for (auto* p : b->probs) problem_add_steps(p, nsteps);
@@ -1172,7 +1276,7 @@ c4m_status c4m_batch_step(c4m_batch* b, int64_t nsteps)
             hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
             if (e != hipSuccess) return set_error(C4M_EDEVICE, "hipStreamBeginCapture");
             c4m_status s = C4M_OK;
-            for (int64_t t = 0; t < len && s == C4M_OK; ++t) s = launch_step(b);
+            for (int64_t t = 0; t < len && s == C4M_OK; ++t) s = b->three_d ? launch_step3b(b) : launch_step(b);
             hipGraph_t g = nullptr;
             e = hipStreamEndCapture(b->stream, &g);
             if (s != C4M_OK) {
@@ -1199,6 +1303,7 @@ c4m_status c4m_batch_step(c4m_batch* b, int64_t nsteps)
 c4m_status c4m_batch_check(c4m_batch* b)
 {
     if (!b) return set_error(C4M_EINVAL, "null batch");
+    if (b->three_d) return C4M_OK;             // no stage waits in the 3D form
     int h = 0;
     hipError_t e = hipMemcpyAsync(&h, b->sched.err, sizeof(int), hipMemcpyDeviceToHost, b->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(b->stream);

@@ -338,6 +338,7 @@ struct c4m_problem {
     double alg_bytes[C4M_K_COUNT] = {};
     std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;   // captured runs of steps
     bool direct = false;                // launch steps without graphs (no-allocation call)
+    std::vector<Launch3> plan3;         // 3D FP64 Chebyshev step as recorded launches (built on first use)
 };
 
 namespace {
@@ -565,11 +566,58 @@ UGrid unknowns(const Box& b)
     return g;
 }
 
+// The recorded 3D step of a problem (FP64 Chebyshev form), built once.
+const std::vector<Launch3>& problem_plan3(c4m_problem* p)
+{
+    if (p->plan3.empty()) {
+        Plan3In in{};
+        for (int c = 0; c < 6; ++c) {
+            in.f[c] = p->f[c];
+            in.box[c] = p->box[c];
+            in.ug[c] = unknowns(p->box[c]);
+        }
+        for (int c = 0; c < 3; ++c) in.ge[c] = p->ge[c];
+        for (int t = 0; t < 8; ++t) in.tmp[t] = p->tmp[t];
+        in.P = p->P;
+        in.plane = p->plane;
+        in.coef = p->coef;
+        in.cheb = p->cheb;
+        in.line[0] = p->line[0];
+        in.line[1] = p->line[1];
+        in.tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+        plan_step3(in, p->plan3);
+    }
+    return p->plan3;
+}
+
+bool plan3_form(const c4m_problem* p)
+{
+    return p->dim == 3 && p->cfg.scheme == C4M_SCHEME_C4 && p->cfg.solver == C4M_SOLVER_CHEBYSHEV &&
+           p->cfg.precision == C4M_FP64;
+}
+
 // 3D: Step 1 then Step 2 of Section 3.4, one component at a time.
 enum { T3_RAW = 0, T3_G = 1, T3_GE_STORED = 2, T3_GE_DISCRETE = 3 };
 constexpr int SRC_G_HOST = T3_G, SRC_GE_DISCRETE_HOST = T3_GE_DISCRETE;
 c4m_status step3(c4m_problem* p)
 {
+    if (plan3_form(p)) {
+        // the recorded launches, grouped by class and component for profiling
+        const std::vector<Launch3>& rec = problem_plan3(p);
+        const PadeTaps taps[2] = {p->pade_host[0].taps, p->pade_host[1].taps};
+        c4m_status s = C4M_OK;
+        for (size_t i = 0; i < rec.size() && s == C4M_OK;) {
+            size_t j = i;
+            while (j < rec.size() && rec[j].cls == rec[i].cls && rec[j].group == rec[i].group) ++j;
+            s = timed(p, rec[i].cls, "3D step", [&] {
+                hipError_t e = hipSuccess;
+                for (size_t k = i; k < j && e == hipSuccess; ++k) e = launch3_single(p->stream, rec[k], taps);
+                return e;
+            });
+            i = j;
+        }
+        return s;
+    }
     const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
     const double z = p->coef.z;
     double *b = p->tmp[0], *x = p->tmp[1], *d0 = p->tmp[2], *d1 = p->tmp[3], *cur = p->tmp[4];
@@ -811,7 +859,7 @@ c4m_status step_graph(c4m_problem* p, int64_t len, hipGraphExec_t* out)
 bool steps_direct(c4m_problem* p)
 {
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    bool direct = (p->cfg.flags & C4M_FLAG_PROFILE) || !p->stream || p->direct;
+    bool direct = (p->cfg.flags & (C4M_FLAG_PROFILE | C4M_FLAG_DIRECT)) || !p->stream || p->direct;
     if (!direct && hipStreamIsCapturing(p->stream, &cap) != hipSuccess) direct = true;
     return direct || cap != hipStreamCaptureStatusNone;
 }
@@ -1293,6 +1341,9 @@ c4m_status problem_view(c4m_problem* p, ProblemView* v)
 }
 
 c4m_status problem_prepare(c4m_problem* p) { return ensure_ge(p); }
+
+// The recorded 3D step of a member (null where the problem does not take that form).
+const std::vector<Launch3>* problem_step3_plan(c4m_problem* p) { return plan3_form(p) ? &problem_plan3(p) : nullptr; }
 
 c4m_status problem_create_owned(const c4m_config* cfg, void* ws, size_t bytes, hipStream_t st,
                                 c4m_problem** out)

@@ -7,6 +7,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <vector>
 #include <stdint.h>
 
 #include "c4m.h"
@@ -106,6 +107,64 @@ struct Cheb3 {
     int P;
     size_t plane;
 };
+
+// 3D Chebyshev pass (c4m_kernels_3d.hip).
+enum { C3_STORE = 0, C3_FIELD = 1, C3_RESID = 2 };
+// TX: storage of the iterates, TB: storage of b.
+template <class TX, class TB>
+struct Cheb3T {
+    const TB* b;
+    const TX* xk;           // x_k (unused in the first pass: x_1 = b / theta)
+    const TX* xkm1;         // x_{k-1} (first pass: x_0 = 0; second pass: x_1 = b / theta, formed here)
+    TX* xout;               // C3_STORE: x_{k+1}
+    const TX* xadd;         // C3_FIELD: an earlier round's solution added to Phi (or null)
+    float* rout;            // C3_RESID: b - M x_k, rounded to FP32
+    double* field;          // C3_FIELD: field += cfl Phi
+    double* ge;             // C3_FIELD, carried Laplacian: G_E update (or null)
+    const double* cur;      // raw curl for the G_E update
+    UGrid g;
+    int P;
+    size_t plane;
+    double inv_theta, c1, c2;
+    Coef cf;
+};
+
+// One launch of the 3D step of one problem (FP64 Chebyshev form), recorded
+// once per problem: the single-problem step launches the records in order,
+// the batched step launches each record over all members at once.
+enum { L3_COND = 0, L3_TERM = 1, L3_MARCH = 2, L3_CHEB = 3 };
+struct Launch3 {
+    int kind;               // L3_*
+    int axis, mode;         // term / march: line axis; cond: source mode
+    int line;               // Pade line (taps) of a term
+    int first, out;         // cheb: first pass, output kind
+    int cls, group;         // kernel class and component (profiling groups)
+    Term3 t;
+    PadeLine L;
+    int seg;                // march: outputs per wave
+    Cheb3T<double, double> c;
+    unsigned gx, gy, gz;    // this problem's grid of the launch
+};
+// What the planner needs of a problem.
+struct Plan3In {
+    double* f[6];
+    double* ge[3];
+    double* tmp[8];
+    Box box[6];
+    UGrid ug[6];
+    int P;
+    size_t plane;
+    Coef coef;
+    ChebSchedule cheb;
+    PadeLine line[2];
+    bool tracked;
+};
+void plan_step3(const Plan3In& in, std::vector<Launch3>& out);
+hipError_t launch3_single(hipStream_t st, const Launch3& r, const PadeTaps* taps);
+size_t launch3_arg_bytes(const Launch3& r);
+void launch3_pack(const Launch3& r, int first_block, void* dst);
+hipError_t launch3_batched(hipStream_t st, const Launch3& proto, const void* dev_args, int count,
+                           unsigned total_blocks, const PadeTaps* taps);
 
 // Device tables of the transform solve for one N (c4m_transform.hip):
 // orthonormal DST-I (N-1 x N-1), DCT-II (N x N) and its transpose, sigma.

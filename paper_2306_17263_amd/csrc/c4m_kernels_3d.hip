@@ -17,6 +17,8 @@
 // Chebyshev: three-term form, one z-marching launch per application of M
 // with the planes of the iterate staged in LDS (k_cheb3t); the FP32-refined
 // form runs the same passes with FP32 iterates around one FP64 residual.
+#include <string.h>
+
 #include "c4m_internal.h"
 
 namespace c4m {
@@ -72,21 +74,30 @@ __device__ __forceinline__ double src_value(const Term3& t, int i, int j, int k,
 
 constexpr int T3_SEG = 8;
 
+// LDS doubles of a k_term3 tile along axis D
+template <int D>
+constexpr int term3_lds()
+{
+    constexpr int A = D == 0 ? 32 : 64, NO = D == 0 ? 64 : 32, BW = NO + PADE_TAPS - 1;
+    return A * ((BW % 2) ? BW : BW + 1);
+}
+
+// One tile (block coordinates blk) of the line term; sv: term3_lds<D>() doubles of LDS.
 template <int D, int MODE>
-__global__ __launch_bounds__(256) void k_term3(Term3 t, double alpha, PadeTaps taps, PadeLine L)
+__device__ __forceinline__ void term3_body(const Term3& t, double alpha, const PadeTaps& taps, const PadeLine& L,
+                                           uint3 blk, double* sv)
 {
     // tile geometry: A lines x NO outputs per line
     constexpr int A = D == 0 ? 32 : 64;
     constexpr int NO = D == 0 ? 64 : 32;
     constexpr int BW = NO + PADE_TAPS - 1;       // staged window per line
     constexpr int BS = (BW % 2) ? BW : BW + 1;   // odd stride
-    __shared__ double sv[A * BS];
     // axes: D = line axis, W = across lines in the tile, Sx = slab (blockIdx.z)
     constexpr int W = D == 0 ? 1 : 0;
     constexpr int SX = 3 - D - W;
-    const int m0 = blockIdx.x * NO;                       // first output along D
-    const int w0 = t.tg.lo[W] + blockIdx.y * A;           // first line along W
-    const int s = t.tg.lo[SX] + blockIdx.z;               // slab index
+    const int m0 = blk.x * NO;                            // first output along D
+    const int w0 = t.tg.lo[W] + blk.y * A;                // first line along W
+    const int s = t.tg.lo[SX] + blk.z;                    // slab index
     const int tid = threadIdx.x;
     const int n_in = L.n_in;
     // staging in chunks of CH elements per thread, the loads of a chunk all
@@ -187,17 +198,30 @@ __global__ __launch_bounds__(256) void k_term3(Term3 t, double alpha, PadeTaps t
     }
 }
 
+template <int D, int MODE>
+__global__ __launch_bounds__(256) void k_term3(Term3 t, double alpha, PadeTaps taps, PadeLine L)
+{
+    __shared__ double sv[term3_lds<D>()];
+    term3_body<D, MODE>(t, alpha, taps, L, make_uint3(blockIdx.x, blockIdx.y, blockIdx.z), sv);
+}
+
 // k_condition3: the conditioned source G(u) (SRC_G) or its discrete-
 // Laplacian form on E (SRC_GE_DISCRETE) at every stored point of a box, as
 // src_value forms it, so that the line terms can read it raw.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_condition3(Term3 t, double alpha)
+__device__ __forceinline__ void condition3_body(const Term3& t, double alpha, uint3 blk)
 {
-    const int i = blockIdx.x * 256 + threadIdx.x;
-    const int j = blockIdx.y, k = blockIdx.z;
+    const int i = blk.x * 256 + threadIdx.x;
+    const int j = blk.y, k = blk.z;
     if (i >= t.sb.n[0]) return;
     double raw;
     t.out[(size_t)k * t.plane + (size_t)j * t.P + i] = src_value<MODE>(t, i, j, k, alpha, true, raw);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) void k_condition3(Term3 t, double alpha)
+{
+    condition3_body<MODE>(t, alpha, make_uint3(blockIdx.x, blockIdx.y, blockIdx.z));
 }
 
 // k_march3: the same line term along y or z (D = 1, 2) as a streaming pass.
@@ -210,14 +234,15 @@ __global__ __launch_bounds__(256) void k_condition3(Term3 t, double alpha)
 constexpr int M3_Q = 8, M3_WIN = M3_Q + PADE_TAPS - 1;
 
 template <int D, int MODE>
-__global__ __launch_bounds__(256) void k_march3(Term3 t, double alpha, PadeTaps taps, PadeLine L, int seg_len)
+__device__ __forceinline__ void march3_body(const Term3& t, double alpha, const PadeTaps& taps, const PadeLine& L,
+                                            int seg_len, uint3 blk)
 {
     constexpr int T = 3 - D;                       // third axis (x is always across lanes)
     const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-    const int xi = t.tg.lo[0] + blockIdx.x * 64 + lane;
-    const int ti = t.tg.lo[T] + blockIdx.y * 4 + wv;
+    const int xi = t.tg.lo[0] + blk.x * 64 + lane;
+    const int ti = t.tg.lo[T] + blk.y * 4 + wv;
     if (xi >= t.tg.hi[0] || ti >= t.tg.hi[T]) return;
-    const int m0 = blockIdx.z * seg_len;
+    const int m0 = blk.z * seg_len;
     const int m1 = min(m0 + seg_len, L.n_out);
     const int n_in = L.n_in;
     auto input = [&](int g) {
@@ -271,6 +296,12 @@ __global__ __launch_bounds__(256) void k_march3(Term3 t, double alpha, PadeTaps 
     }
 }
 
+template <int D, int MODE>
+__global__ __launch_bounds__(256) void k_march3(Term3 t, double alpha, PadeTaps taps, PadeLine L, int seg_len)
+{
+    march3_body<D, MODE>(t, alpha, taps, L, seg_len, make_uint3(blockIdx.x, blockIdx.y, blockIdx.z));
+}
+
 // ---------------------------------------------------------------------------
 // Solve: Chebyshev in three-term form on the same schedule,
 //   x_1 = b / theta,  x_{k+1} = x_k + c1_{k-1} (x_k - x_{k-1}) + c2_{k-1} (b - M x_k),
@@ -287,26 +318,7 @@ __global__ __launch_bounds__(256) void k_march3(Term3 t, double alpha, PadeTaps 
 constexpr int C3_TX = 64, C3_TY = 4, C3_CZ = 16;
 constexpr int C3_LX = C3_TX + 2, C3_LY = C3_TY + 2, C3_PL = C3_LX * C3_LY;
 
-enum { C3_STORE = 0, C3_FIELD = 1, C3_RESID = 2 };
 
-// TX: storage of the iterates, TB: storage of b.
-template <class TX, class TB>
-struct Cheb3T {
-    const TB* b;
-    const TX* xk;           // x_k (unused in the first pass: x_1 = b / theta)
-    const TX* xkm1;         // x_{k-1} (first pass: x_0 = 0; second pass: x_1 = b / theta, formed here)
-    TX* xout;               // C3_STORE: x_{k+1}
-    const TX* xadd;         // C3_FIELD: an earlier round's solution added to Phi (or null)
-    float* rout;            // C3_RESID: b - M x_k, rounded to FP32
-    double* field;          // C3_FIELD: field += cfl Phi
-    double* ge;             // C3_FIELD, carried Laplacian: G_E update (or null)
-    const double* cur;      // raw curl for the G_E update
-    UGrid g;
-    int P;
-    size_t plane;
-    double inv_theta, c1, c2;
-    Coef cf;
-};
 
 // Index of grid point (i, j, k) after the boundary rules of the unknowns:
 // Dirichlet outside the range -> -1 (zero), Neumann -> mirrored onto the
@@ -327,16 +339,15 @@ __device__ __forceinline__ long rule_index(const UGrid& g, int P, size_t plane, 
     return (long)q[2] * (long)plane + (long)q[1] * P + q[0];
 }
 
-// TC: arithmetic type of the pass.
+// TC: arithmetic type of the pass; ring: 4 C3_PL planes of LDS.
 template <class TX, class TB, class TC, bool FIRST, int OUT>
-__global__ __launch_bounds__(256) void k_cheb3t(Cheb3T<TX, TB> a)
+__device__ __forceinline__ void cheb3t_body(const Cheb3T<TX, TB>& a, uint3 blk, TC (*ring)[C3_PL])
 {
-    __shared__ TC ring[4][C3_PL];
     const int tid = threadIdx.x;
     const int tx = tid % C3_TX, ty = tid / C3_TX;
-    const int bx = a.g.lo[0] + blockIdx.x * C3_TX, by = a.g.lo[1] + blockIdx.y * C3_TY;
+    const int bx = a.g.lo[0] + blk.x * C3_TX, by = a.g.lo[1] + blk.y * C3_TY;
     const int i = bx + tx, j = by + ty;
-    const int z0 = a.g.lo[2] + blockIdx.z * C3_CZ;
+    const int z0 = a.g.lo[2] + blk.z * C3_CZ;
     const int z1 = min(z0 + C3_CZ, a.g.hi[2]);
     const bool own = i < a.g.hi[0] && j < a.g.hi[1];
     const TC scale = FIRST ? TC(a.inv_theta) : TC(1);
@@ -417,6 +428,13 @@ __global__ __launch_bounds__(256) void k_cheb3t(Cheb3T<TX, TB> a)
             }
         }
     }
+}
+
+template <class TX, class TB, class TC, bool FIRST, int OUT>
+__global__ __launch_bounds__(256) void k_cheb3t(Cheb3T<TX, TB> a)
+{
+    __shared__ TC ring[4][C3_PL];
+    cheb3t_body<TX, TB, TC, FIRST, OUT>(a, make_uint3(blockIdx.x, blockIdx.y, blockIdx.z), ring);
 }
 
 static dim3 cheb3_grid(const UGrid& g)
@@ -591,6 +609,279 @@ hipError_t launch_solve3(hipStream_t st, const Cheb3& c, double* field, double* 
     // x_k rotates through three arrays: x, d0, d1 (b stays in r)
     double* bufs[3] = {c.x, c.d0, c.d1};
     cheb3_round<double, double, double>(st, c, c.r, bufs, cs.sweeps, cs, cf, nullptr, field, ge, cur);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// The recorded 3D step (Launch3): one problem's launches, in the order of
+// Step 1 then Step 2 of Section 3.4 for the FP64 Chebyshev form, and the
+// same launches over many problems.  A batched launch has one workgroup
+// range per member ([first, first + gx gy gz)); the workgroup finds its
+// member by a binary search over the range starts and runs the member's
+// tile with the kernel body of the single-problem launch, so a member's
+// results are those of the problem stepped alone.
+// ---------------------------------------------------------------------------
+struct TermB {
+    Term3 t;
+    PadeLine L;
+    int seg;
+    unsigned gx, gy;
+    int first;
+};
+struct ChebB {
+    Cheb3T<double, double> a;
+    unsigned gx, gy;
+    int first;
+};
+
+template <class B>
+__device__ __forceinline__ uint3 member_block(const B* a, int count, int& m)
+{
+    const int b = (int)blockIdx.x;
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a[mid].first <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    m = lo;
+    const unsigned local = (unsigned)(b - a[m].first), gx = a[m].gx, gy = a[m].gy;
+    return make_uint3(local % gx, (local / gx) % gy, local / (gx * gy));
+}
+
+// The member's arguments are copied out of the table first: read through
+// the table, every field would be reloaded after each store of the kernel
+// (the stores could alias the table as far as the compiler knows).
+template <int MODE>
+__global__ __launch_bounds__(256) void k_condition3_b(const TermB* a, int count, double alpha)
+{
+    int m;
+    const uint3 blk = member_block(a, count, m);
+    const TermB arg = a[m];
+    condition3_body<MODE>(arg.t, alpha, blk);
+}
+
+__global__ __launch_bounds__(256) void k_term3_b(const TermB* a, int count, double alpha, PadeTaps taps)
+{
+    __shared__ double sv[term3_lds<0>()];
+    int m;
+    const uint3 blk = member_block(a, count, m);
+    const TermB arg = a[m];
+    term3_body<0, SRC_RAW>(arg.t, alpha, taps, arg.L, blk, sv);
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void k_march3_b(const TermB* a, int count, double alpha, PadeTaps taps)
+{
+    int m;
+    const uint3 blk = member_block(a, count, m);
+    const TermB arg = a[m];
+    march3_body<D, SRC_RAW>(arg.t, alpha, taps, arg.L, arg.seg, blk);
+}
+
+template <bool FIRST, int OUT>
+__global__ __launch_bounds__(256) void k_cheb3t_b(const ChebB* a, int count)
+{
+    __shared__ double ring[4][C3_PL];
+    int m;
+    const uint3 blk = member_block(a, count, m);
+    const ChebB arg = a[m];
+    cheb3t_body<double, double, double, FIRST, OUT>(arg.a, blk, ring);
+}
+
+void plan_step3(const Plan3In& in, std::vector<Launch3>& out)
+{
+    out.clear();
+    const double z = in.coef.z;
+    double *b = in.tmp[0], *x = in.tmp[1], *d0 = in.tmp[2], *d1 = in.tmp[3], *cur = in.tmp[4];
+    double* cond[3] = {in.tmp[5], in.tmp[6], in.tmp[7]};
+    auto condition = [&](int first_src, int mode, int cls) {
+        for (int j = 0; j < 3; ++j) {
+            Launch3 r{};
+            r.c.cf = in.coef;
+            r.kind = L3_COND;
+            r.mode = mode;
+            r.cls = cls;
+            r.group = 0;
+            r.t.src = in.f[first_src + j];
+            r.t.out = cond[j];
+            r.t.sb = in.box[first_src + j];
+            r.t.P = in.P;
+            r.t.plane = in.plane;
+            const Box& bx = in.box[first_src + j];
+            r.gx = (unsigned)((bx.n[0] + 255) / 256);
+            r.gy = (unsigned)bx.n[1];
+            r.gz = (unsigned)bx.n[2];
+            out.push_back(r);
+        }
+    };
+    auto term = [&](int axis, int src, const double* sp, double* o, double scale, int acc, int tgt, int line,
+                    int cls, int group) {
+        Launch3 r{};
+        r.c.cf = in.coef;
+        r.kind = axis == 0 ? L3_TERM : L3_MARCH;
+        r.axis = axis;
+        r.mode = SRC_RAW;
+        r.line = line;
+        r.cls = cls;
+        r.group = group;
+        r.t = Term3{sp, o, in.box[src], in.ug[tgt], in.P, in.plane, scale, acc};
+        r.L = in.line[line];
+        const UGrid& tg = r.t.tg;
+        if (axis == 0) {
+            r.gx = (unsigned)((r.L.n_out + 63) / 64);
+            r.gy = (unsigned)((tg.hi[1] - tg.lo[1] + 31) / 32);
+            r.gz = (unsigned)(tg.hi[2] - tg.lo[2]);
+        } else {
+            const int T = 3 - axis;
+            const unsigned g0 = (unsigned)((tg.hi[0] - tg.lo[0] + 63) / 64), g1 = (unsigned)((tg.hi[T] - tg.lo[T] + 3) / 4);
+            r.seg = march_segment(r.L.n_out, (long)g0 * g1 * 4);
+            r.gx = g0;
+            r.gy = g1;
+            r.gz = (unsigned)((r.L.n_out + r.seg - 1) / r.seg);
+        }
+        out.push_back(r);
+    };
+    auto solve = [&](int comp, double* field, double* ge, const double* cr, int cls, int group) {
+        double* bufs[3] = {x, d0, d1};
+        const int K = in.cheb.sweeps;
+        for (int k = 1; k <= K; ++k) {
+            Launch3 r{};
+            r.kind = L3_CHEB;
+            r.cls = cls;
+            r.group = group;
+            r.first = k == 1;
+            const bool last = k == K;
+            r.out = last ? C3_FIELD : C3_STORE;
+            Cheb3T<double, double>& a = r.c;
+            a.b = b;
+            a.xk = bufs[k % 3];
+            a.xkm1 = k == 2 ? nullptr : bufs[(k - 1) % 3];
+            a.xout = bufs[(k + 1) % 3];
+            a.field = last ? field : nullptr;
+            a.ge = last ? ge : nullptr;
+            a.cur = last ? cr : nullptr;
+            a.g = in.ug[comp];
+            a.P = in.P;
+            a.plane = in.plane;
+            a.inv_theta = in.cheb.inv_theta;
+            a.c1 = in.cheb.c1[k - 1];
+            a.c2 = in.cheb.c2[k - 1];
+            a.cf = in.coef;
+            const dim3 g = cheb3_grid(a.g);
+            r.gx = g.x;
+            r.gy = g.y;
+            r.gz = g.z;
+            out.push_back(r);
+        }
+    };
+    // Step 1: conditioned H once, then per E component the line terms of
+    // b (and of the raw curl with the carried Laplacian) and the solve
+    condition(3, SRC_G, C4M_K_RHS_E);
+    for (int c = 0; c < 3; ++c) {
+        const int s1 = (c + 1) % 3, s2 = (c + 2) % 3;
+        term(s1, 3 + s2, cond[s2], b, z, 0, c, 1, C4M_K_RHS_E, c);
+        term(s2, 3 + s1, cond[s1], b, -z, 1, c, 1, C4M_K_RHS_E, c);
+        if (in.tracked) {
+            term(s1, 3 + s2, in.f[3 + s2], cur, 1.0, 0, c, 1, C4M_K_RHS_E, c);
+            term(s2, 3 + s1, in.f[3 + s1], cur, -1.0, 1, c, 1, C4M_K_RHS_E, c);
+        }
+        solve(c, in.f[c], in.tracked ? in.ge[c] : nullptr, cur, C4M_K_SOLVE_E, c);
+    }
+    // Step 2: the stored G_E (or G(E) of the discrete Laplacian), per H component
+    if (!in.tracked) condition(0, SRC_GE_DISCRETE, C4M_K_RHS_H);
+    for (int c = 0; c < 3; ++c) {
+        const int s1 = (c + 1) % 3, s2 = (c + 2) % 3;
+        term(s1, s2, in.tracked ? in.ge[s2] : cond[s2], b, -1.0 / z, 0, 3 + c, 0, C4M_K_RHS_H, c);
+        term(s2, s1, in.tracked ? in.ge[s1] : cond[s1], b, 1.0 / z, 1, 3 + c, 0, C4M_K_RHS_H, c);
+        solve(3 + c, in.f[3 + c], nullptr, nullptr, C4M_K_SOLVE_H, c);
+    }
+}
+
+hipError_t launch3_single(hipStream_t st, const Launch3& r, const PadeTaps* taps)
+{
+    const dim3 grid(r.gx, r.gy, r.gz), blk(256);
+    switch (r.kind) {
+        case L3_COND:
+            if (r.mode == SRC_G) hipLaunchKernelGGL((k_condition3<SRC_G>), grid, blk, 0, st, r.t, r.c.cf.alpha);
+            else hipLaunchKernelGGL((k_condition3<SRC_GE_DISCRETE>), grid, blk, 0, st, r.t, r.c.cf.alpha);
+            break;
+        case L3_TERM:
+            hipLaunchKernelGGL((k_term3<0, SRC_RAW>), grid, blk, 0, st, r.t, r.c.cf.alpha, taps[r.line], r.L);
+            break;
+        case L3_MARCH:
+            if (r.axis == 1)
+                hipLaunchKernelGGL((k_march3<1, SRC_RAW>), grid, blk, 0, st, r.t, r.c.cf.alpha, taps[r.line], r.L, r.seg);
+            else
+                hipLaunchKernelGGL((k_march3<2, SRC_RAW>), grid, blk, 0, st, r.t, r.c.cf.alpha, taps[r.line], r.L, r.seg);
+            break;
+        default:
+            if (r.first && r.out == C3_FIELD)
+                hipLaunchKernelGGL((k_cheb3t<double, double, double, true, C3_FIELD>), grid, blk, 0, st, r.c);
+            else if (r.first)
+                hipLaunchKernelGGL((k_cheb3t<double, double, double, true, C3_STORE>), grid, blk, 0, st, r.c);
+            else if (r.out == C3_FIELD)
+                hipLaunchKernelGGL((k_cheb3t<double, double, double, false, C3_FIELD>), grid, blk, 0, st, r.c);
+            else
+                hipLaunchKernelGGL((k_cheb3t<double, double, double, false, C3_STORE>), grid, blk, 0, st, r.c);
+            break;
+    }
+    return hipGetLastError();
+}
+
+size_t launch3_arg_bytes(const Launch3& r) { return r.kind == L3_CHEB ? sizeof(ChebB) : sizeof(TermB); }
+
+void launch3_pack(const Launch3& r, int first_block, void* dst)
+{
+    if (r.kind == L3_CHEB) {
+        ChebB c{};
+        c.a = r.c;
+        c.gx = r.gx;
+        c.gy = r.gy;
+        c.first = first_block;
+        memcpy(dst, &c, sizeof(c));
+    } else {
+        TermB t{};
+        t.t = r.t;
+        t.L = r.L;
+        t.seg = r.seg;
+        t.gx = r.gx;
+        t.gy = r.gy;
+        t.first = first_block;
+        memcpy(dst, &t, sizeof(t));
+    }
+}
+
+hipError_t launch3_batched(hipStream_t st, const Launch3& proto, const void* dev_args, int count,
+                           unsigned total_blocks, const PadeTaps* taps)
+{
+    const dim3 grid(total_blocks), blk(256);
+    const TermB* tb = (const TermB*)dev_args;
+    const ChebB* cb = (const ChebB*)dev_args;
+    const double alpha = proto.c.cf.alpha;
+    switch (proto.kind) {
+        case L3_COND:
+            if (proto.mode == SRC_G) hipLaunchKernelGGL((k_condition3_b<SRC_G>), grid, blk, 0, st, tb, count, alpha);
+            else hipLaunchKernelGGL((k_condition3_b<SRC_GE_DISCRETE>), grid, blk, 0, st, tb, count, alpha);
+            break;
+        case L3_TERM:
+            hipLaunchKernelGGL(k_term3_b, grid, blk, 0, st, tb, count, alpha, taps[proto.line]);
+            break;
+        case L3_MARCH:
+            if (proto.axis == 1) hipLaunchKernelGGL((k_march3_b<1>), grid, blk, 0, st, tb, count, alpha, taps[proto.line]);
+            else hipLaunchKernelGGL((k_march3_b<2>), grid, blk, 0, st, tb, count, alpha, taps[proto.line]);
+            break;
+        default:
+            if (proto.first && proto.out == C3_FIELD)
+                hipLaunchKernelGGL((k_cheb3t_b<true, C3_FIELD>), grid, blk, 0, st, cb, count);
+            else if (proto.first)
+                hipLaunchKernelGGL((k_cheb3t_b<true, C3_STORE>), grid, blk, 0, st, cb, count);
+            else if (proto.out == C3_FIELD)
+                hipLaunchKernelGGL((k_cheb3t_b<false, C3_FIELD>), grid, blk, 0, st, cb, count);
+            else
+                hipLaunchKernelGGL((k_cheb3t_b<false, C3_STORE>), grid, blk, 0, st, cb, count);
+            break;
+    }
     return hipGetLastError();
 }
 

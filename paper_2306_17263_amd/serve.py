@@ -2,10 +2,12 @@
 
 Requests (cavity simulations of different sizes and step counts) arrive over
 time.  Work is issued in units that run asynchronously on the device:
-  * the 2D cohort: every active 2D request, stepped together as one batch
-    (persistent launches; the batch is re-formed only when its membership
-    changed and no chunk of it is in flight);
-  * each 3D request on its own side stream.
+  * a cohort per dimension: every active request of that dimension, stepped
+    together as one batch (2D: persistent launches; 3D: every launch of the
+    step over all members), re-formed only when its membership changed and
+    no chunk of it is in flight;
+  * with a backend that does not batch a dimension, each such request on
+    its own side stream.
 A unit advances by a chunk of k = min(chunk, fewest remaining steps among
 its members) steps, so nobody overshoots, and records a completion event.
 The loop polls those events: a finished chunk retires the requests it
@@ -63,7 +65,7 @@ class DeviceBackend:
     streams); completion of a chunk is an event recorded on its stream."""
 
     def __init__(self, n_side_streams: int = 4, settings: dict | None = None, keep_results: bool = False,
-                 chunk: int = 96, workers: int = 2, per_stream: int = 2):
+                 chunk: int = 96, workers: int = 2, per_stream: int = 2, batch_3d: bool = True):
         import torch
         from .problem import make_config, workspace_bytes
         self.torch = torch
@@ -73,8 +75,10 @@ class DeviceBackend:
         self.main = torch.cuda.Stream()
         self.side = [torch.cuda.Stream() for _ in range(n_side_streams)]
         self.keep_results = keep_results
-        self._batch = None
-        self._members = ()
+        self._batch = {}                # dim -> batch of the cohort
+        self._members = {}              # dim -> member handles of that batch
+        self.cohort_dims = (2, 3) if batch_3d else (2,)
+        self.main3 = torch.cuda.Stream()
         self._next_side = 0
         self.chunk = int(chunk)
         self.per_stream = int(per_stream)
@@ -92,6 +96,8 @@ class DeviceBackend:
         """Starts the set-up of a request; returns a future of its handle."""
         if req.dim == 2:
             stream = self.main
+        elif 3 in self.cohort_dims:
+            stream = self.main3
         else:
             req.side = self._next_side % len(self.side)
             stream = self.side[req.side]
@@ -102,7 +108,7 @@ class DeviceBackend:
         """A 3D request launches only while its stream has fewer than
         per_stream chunks queued: every step is some fifty kernels, and a
         deep backlog would block the loop in the launch."""
-        return req.dim == 2 or self._inflight.get(req.side, 0) < self.per_stream
+        return req.dim in self.cohort_dims or self._inflight.get(req.side, 0) < self.per_stream
 
     def _create(self, req: Request, stream):
         from workloads import mode_fields
@@ -111,7 +117,12 @@ class DeviceBackend:
         setup = getattr(self._local, "stream", None)
         if setup is None:
             setup = self._local.stream = self.torch.cuda.Stream()
-        p = Problem(req.dim, req.n, req.r, stream=setup, **self.settings)
+        kw = dict(self.settings)
+        if req.dim == 3 and 3 in self.cohort_dims:
+            # a 3D cohort changes often: its steps are launched directly
+            from ._lib import FLAG_DIRECT
+            kw["flags"] = kw.get("flags", 0) | FLAG_DIRECT
+        p = Problem(req.dim, req.n, req.r, stream=setup, **kw)
         t1 = time.perf_counter()
         h = 1.0 / req.n
         init = mode_fields(req.dim, req.n, req.k, 0.0, req.r * h / 2, amp=req.amp)
@@ -119,7 +130,7 @@ class DeviceBackend:
         for name in p.fields():
             p.set(name, init[name])
         t3 = time.perf_counter()
-        if req.dim == 3:                        # the graphs of its chunk lengths
+        if req.dim == 3 and 3 not in self.cohort_dims:     # the graphs of its chunk lengths
             p.prepare(min(self.chunk, req.steps))
             if req.steps % self.chunk:
                 p.prepare(req.steps % self.chunk)
@@ -137,20 +148,21 @@ class DeviceBackend:
         returns the event that marks its end."""
         from .batch import Batch
         t = time.perf_counter()
-        if reqs[0].dim == 2:
+        dim = reqs[0].dim
+        if dim in self.cohort_dims:
+            stream = self.main if dim == 2 else self.main3
             key = tuple(id(r.handle) for r in reqs)
-            if key != self._members:
-                if self._batch is not None:
-                    self._batch.close()
-                self._batch = Batch.from_problems([r.handle for r in reqs], stream=self.main)
-                self._members = key
+            if key != self._members.get(dim):
+                if self._batch.get(dim) is not None:
+                    self._batch[dim].close()
+                self._batch[dim] = Batch.from_problems([r.handle for r in reqs], stream=stream)
+                self._members[dim] = key
                 self.reforms += 1
                 t1 = time.perf_counter()
-                self.host_s["reform_2d"] += t1 - t
+                self.host_s["reform_%dd" % dim] = self.host_s.get("reform_%dd" % dim, 0.0) + t1 - t
                 t = t1
-            self._batch.step(k)
-            stream = self.main
-            self.host_s["launch_2d"] += time.perf_counter() - t
+            self._batch[dim].step(k)
+            self.host_s["launch_%dd" % dim] = self.host_s.get("launch_%dd" % dim, 0.0) + time.perf_counter() - t
         else:
             reqs[0].handle.step(k)
             stream = reqs[0].handle.stream
@@ -158,7 +170,7 @@ class DeviceBackend:
             self.host_s["launch_3d"] += time.perf_counter() - t
         ev = self.torch.cuda.Event()
         ev.record(stream)
-        return (ev, reqs[0].side if reqs[0].dim == 3 else None)
+        return (ev, None if dim in self.cohort_dims else reqs[0].side)
 
     def done(self, token) -> bool:
         ev, side = token
@@ -187,30 +199,33 @@ class DeviceBackend:
         names = ["ez", "hx", "hy"] if req.dim == 2 else ["ex", "ey", "ez", "hx", "hy", "hz"]
         if keep:
             req.result = {a: req.handle.get(a) for a in names}
-        if self._batch is not None and id(req.handle) in self._members:
-            self._batch.close()                 # the batch references this problem
-            self._batch = None
-            self._members = ()
+        b = self._batch.get(req.dim)
+        if b is not None and id(req.handle) in self._members.get(req.dim, ()):
+            b.close()                           # the batch references this problem
+            self._batch[req.dim] = None
+            self._members[req.dim] = ()
         req.handle.close()
         req.handle = None
 
     def close(self):
         self._pool.shutdown(wait=True)
-        if self._batch is not None:
-            self._batch.close()
-            self._batch = None
-            self._members = ()
+        for dim, b in self._batch.items():
+            if b is not None:
+                b.close()
+        self._batch = {}
+        self._members = {}
 
 
 class Server:
     def __init__(self, backend, hbm_budget: int, chunk: int = 50, max_active: int = 32, max_skip: int = 8,
-                 admit_per_poll: int = 4, clock=time.perf_counter):
+                 admit_per_poll: int = 4, clock=time.perf_counter, chunk_3d: int | None = None):
         self.backend = backend
         self.budget = int(hbm_budget)
         self.chunk = int(chunk)
         self.max_active = int(max_active)
         self.max_skip = int(max_skip)
         self.admit_per_poll = int(admit_per_poll)
+        self.chunk_3d = int(chunk_3d) if chunk_3d else self.chunk
         self.clock = clock
         self.in_use = 0
         self.peak_in_use = 0
@@ -222,7 +237,7 @@ class Server:
         queue, done = [], []
         active2, active3 = [], []
         starting = []               # admitted, set-up still running (backend futures)
-        flight = {}                 # unit key -> (token, members, k); key 0 = 2D cohort, else 3D request id + 1
+        flight = {}                 # unit key -> (token, members, k); -dim: a cohort, request id + 1: one request
         footprint = {}
         t0 = self.clock()
         i = 0
@@ -295,18 +310,23 @@ class Server:
                     if skipped > self.max_skip:
                         break
                     j += 1
-            # launch every idle unit
-            if active2 and 0 not in flight:
-                k = min(self.chunk, min(r.remaining for r in active2))
-                flight[0] = (self.backend.launch(list(active2), k), list(active2), k)
-                chunks += 1
-                progressed = True
-            for r in active3:
-                if r.id + 1 not in flight and self.backend.can_launch(r):
-                    k = min(self.chunk, r.remaining)
-                    flight[r.id + 1] = (self.backend.launch([r], k), [r], k)
-                    chunks += 1
-                    progressed = True
+            # launch every idle unit: a cohort per batched dimension, else
+            # one unit per request
+            cohorts = getattr(self.backend, "cohort_dims", (2,))
+            for dim, members in ((2, active2), (3, active3)):
+                if dim in cohorts:
+                    if members and -dim not in flight:
+                        k = min(self.chunk_for(dim), min(r.remaining for r in members))
+                        flight[-dim] = (self.backend.launch(list(members), k), list(members), k)
+                        chunks += 1
+                        progressed = True
+                    continue
+                for r in members:
+                    if r.id + 1 not in flight and self.backend.can_launch(r):
+                        k = min(self.chunk_for(dim), r.remaining)
+                        flight[r.id + 1] = (self.backend.launch([r], k), [r], k)
+                        chunks += 1
+                        progressed = True
             if not progressed:
                 if not flight and i < len(pending):       # idle until the next arrival
                     wait = pending[i].t_arrive - (self.clock() - t0)
@@ -337,6 +357,9 @@ class Server:
             "queued_or_active_at_end": len(requests) - len(done),
             "peak_hbm_bytes": self.peak_in_use, "done": done,
         }
+
+    def chunk_for(self, dim: int) -> int:
+        return self.chunk_3d if dim == 3 else self.chunk
 
     def _sleep(self, dt):
         if self.clock is time.perf_counter:

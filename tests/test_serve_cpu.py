@@ -23,8 +23,9 @@ class VirtualClock:
 class FakeBackend:
     """Oracle problems; every step advances the virtual clock by its cost."""
 
-    def __init__(self, clock, cost_per_cell_step=1e-9, bytes_per_cell=64):
+    def __init__(self, clock, cost_per_cell_step=1e-9, bytes_per_cell=64, cohort_dims=(2,)):
         self.clock = clock
+        self.cohort_dims = cohort_dims
         self.cost = cost_per_cell_step
         self.bpc = bytes_per_cell
         self.steps_done = {}
@@ -49,7 +50,7 @@ class FakeBackend:
 
     def launch(self, reqs, k):
         assert k >= 1
-        assert len({r.dim for r in reqs}) == 1 and (reqs[0].dim == 2 or len(reqs) == 1)
+        assert len({r.dim for r in reqs}) == 1 and (reqs[0].dim in self.cohort_dims or len(reqs) == 1)
         for r in reqs:
             assert self.steps_done[r.id] + k <= r.steps          # never overshoots
             r.handle.step(k)
@@ -173,3 +174,22 @@ def test_time_limit_releases_unfinished_requests():
     assert out["completed"] < len(reqs)
     assert srv.in_use == 0 and not be.live
     assert out["queued_or_active_at_end"] == len(reqs) - out["completed"]
+
+
+def test_3d_cohort_exact_steps_and_results():
+    # 3D requests batched as a cohort (as the device backend does) reach
+    # exactly their step counts and the result each would reach alone
+    clock = VirtualClock()
+    be = FakeBackend(clock, cohort_dims=(2, 3))
+    reqs = _mix(10, seed=9)
+    out = Server(be, hbm_budget=10 ** 9, chunk=4, chunk_3d=3, clock=clock).run(reqs)
+    assert out["completed"] == len(reqs)
+    for r in out["done"]:
+        assert be.steps_done[r.id] == r.steps
+        alone = oracle.OracleProblem(r.dim, r.n, r.r)
+        h = 1.0 / r.n
+        for name, v in mode_fields(r.dim, r.n, r.k, 0.0, r.r * h / 2, amp=r.amp).items():
+            alone.set(name, v)
+        alone.step(r.steps)
+        for a, v in r.result.items():
+            assert np.array_equal(v, alone.get(a)), (r.id, a)
