@@ -307,7 +307,7 @@ def main():
                     help="serving: rate of the full-mix run (default 70%% of the measured capacity)")
     ap.add_argument("--serve-chunk", type=int, default=96)
     ap.add_argument("--serve-chunk3", type=int, default=32, help="serving: steps per chunk of the 3D cohort")
-    ap.add_argument("--serve-active", type=int, default=32, help="serving: requests active at once")
+    ap.add_argument("--serve-active", type=int, default=128, help="serving: requests active at once")
     ap.add_argument("--serve-streams", type=int, default=8, help="serving: side streams of the 3D requests")
     ap.add_argument("--serve-queues", type=int, default=16, help="serving: HIP hardware queues of the process")
     ap.add_argument("--serve-skip-full", action="store_true", help="serving: only the 200/s run")
