@@ -96,18 +96,21 @@ CLASS_KERNELS = {
 
 # 3D kernel classes: the Pade line terms of each half-step and the
 # Chebyshev passes of both (the same kernels), per component launch group
+# (every line term reads a raw source in both half-steps, so the counters
+# attribute the right-hand sides of Step 1 and Step 2 together)
 CLASS_PATTERNS_3D = {
-    "rhs_e": r"k_term3<\d, [01]>",
-    "rhs_h": r"k_term3<\d, [23]>",
+    "rhs": r"k_term3<|k_march3<|k_condition3<",
     "solve": r"k_cheb3t<",
 }
 KERNELS_3D = {
-    "rhs": "k_term3<axis, mode> (one Pade line term of a right-hand side; 4 per E component, 2 per H)",
+    "rhs": "k_condition3 (conditioned sources, once per half-step), k_term3<0, raw> (x-line terms) and "
+           "k_march3<1|2, raw> (y/z-line terms): 4 terms per E component, 2 per H",
     "solve": "k_cheb3t<...> (one application of M in the three-term Chebyshev recurrence; K per component, "
              "the last writes the field and G_E updates)",
 }
-# component launch groups per step of each 3D class
-CALLS_3D = {"rhs_e": 3, "rhs_h": 3, "solve": 6}
+# component launch groups per step of each 3D class (the rhs figure is the
+# mean over the three Step 1 and three Step 2 groups)
+CALLS_3D = {"rhs": 6, "solve": 6}
 
 # kernel-class -> kernel-name pattern of the batched form (strip stage
 # launches, the single launch per step, the column-tile form)
@@ -747,7 +750,7 @@ def bench_3d(args):
     dom_ach = per[dom]["alg_bytes"] / (per[dom]["avg_us"] * 1e-6) / 1e9
     step_alg = sum(per[c]["alg_bytes"] * per[c]["launches"] for c in per) / steps
     key = f"3d_n{n}_{args.closure}_{args.lap}_{args.precision}_{args.solver}"
-    traffic = measured_traffic("solve" if dom.startswith("solve") else dom, key)
+    traffic = measured_traffic("solve" if dom.startswith("solve") else "rhs", key)
     roofline = {"bound": "hbm", "achieved": round(dom_ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(dom_ach / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                 "kernels": KERNELS_3D.get(dom.split("_")[0]), "avg_us": round(per[dom]["avg_us"], 3),

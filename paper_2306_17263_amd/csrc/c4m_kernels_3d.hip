@@ -1,22 +1,23 @@
 // c4m_kernels_3d.hip -- gfx950 kernels of the full 3D step (Ex..Hz).
 //
-// Step 1 (Section 3.4), per E component s (s1 = s+1, s2 = s+2 mod 3):
-//   b   = Z (delta_{s1} G(H_{s2}) - delta_{s2} G(H_{s1}))      k_term3 twice
-//   c   = delta_{s1} H_{s2} - delta_{s2} H_{s1}                 (carried l) k_term3 twice
-//   Phi = M^{-1} b (19-point M), E_s += r Phi, G_E += ...       k_cheb3t
+// Step 1 (Section 3.4): the conditioned sources G(H_j) once (k_condition3),
+// then per E component s (s1 = s+1, s2 = s+2 mod 3):
+//   b   = Z (delta_{s1} G(H_{s2}) - delta_{s2} G(H_{s1}))      two line terms
+//   c   = delta_{s1} H_{s2} - delta_{s2} H_{s1}                 (carried l) two more
+//   Phi = M^{-1} b (19-point M), E_s += r Phi, G_E += ...       K Chebyshev passes
 // Step 2, per H component s:
-//   b   = -(1/Z) (delta_{s1} G_{E,s2} - delta_{s2} G_{E,s1}),   H_s += r M^{-1} b.
+//   b   = -(1/Z) (delta_{s1} G_{E,s2} - delta_{s2} G_{E,s1}),   H_s += r M^{-1} b
+// (G_E stored, or G(E_j) conditioned once for the discrete Laplacian).
 //
-// k_term3: one Pade line derivative along axis D, accumulated into the
-// target's right-hand side.  A tile holds A lines of the target (32 rows
-// along y for D = x, 64 columns along x otherwise) with 32 or 64 outputs
-// each; the conditioned source values of the tile's line windows are staged
-// in LDS (coalesced loads), then every thread runs the truncated Pade FIR
-// over a register window of 8 consecutive outputs.
-//
-// Chebyshev: three-term form, one z-marching launch per application of M
-// with the planes of the iterate staged in LDS (k_cheb3t); the FP32-refined
-// form runs the same passes with FP32 iterates around one FP64 residual.
+// Line terms: along x, k_term3 stages the line windows of a tile in LDS
+// (coalesced loads) and runs the truncated Pade FIR over a register window
+// of 8 outputs per thread; along y and z, k_march3 streams each wave along
+// its lines with a register window.  Chebyshev: three-term form, one
+// z-marching launch per application of M with the planes of the iterate in
+// an LDS ring (k_cheb3t); the FP32-refined form runs the same passes with
+// FP32 iterates around one FP64 residual.  The FP64 Chebyshev step is
+// recorded as a list of launches (plan_step3) that a single problem replays
+// and a batch runs over all its members (the *_b kernels).
 #include <string.h>
 
 #include "c4m_internal.h"
