@@ -76,6 +76,29 @@ def test_batch_class_patterns_attribute_each_kernel_to_one_class():
         assert not any(rx.search(name) for rx in pats.values()), name
 
 
+NAMES_3D = {
+    "rhs": ["void c4m::k_condition3<1>(c4m::Term3, double)",
+            "void c4m::k_term3<0, 0>(c4m::Term3, double, c4m::PadeTaps, c4m::PadeLine)",
+            "void c4m::k_march3<1, 0>(c4m::Term3, double, c4m::PadeTaps, c4m::PadeLine, int)",
+            "void c4m::k_march3<2, 0>(c4m::Term3, double, c4m::PadeTaps, c4m::PadeLine, int)"],
+    "solve": ["void c4m::k_cheb3t<double, double, double, false, 0>(c4m::Cheb3T<double, double>)",
+              "void c4m::k_cheb3t<double, double, double, true, 1>(c4m::Cheb3T<double, double>)"],
+}
+
+
+def test_3d_class_patterns_attribute_each_kernel_to_one_class():
+    b = _bench()
+    pats = {c: re.compile(p) for c, p in b.CLASS_PATTERNS_3D.items()}
+    assert set(pats) == set(NAMES_3D) == set(b.CALLS_3D)
+    for cls, names in NAMES_3D.items():
+        for name in names:
+            hits = [c for c, rx in pats.items() if rx.search(name)]
+            assert hits == [cls], (name, hits)
+    others = OTHERS[:3] + [n for v in NAMES.values() for n in v]
+    for name in others:
+        assert not any(rx.search(name) for rx in pats.values()), name
+
+
 def test_source_hash_is_stable_and_hex():
     b = _bench()
     h = b.kernel_source_hash()

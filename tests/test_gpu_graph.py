@@ -88,3 +88,24 @@ def test_prepare_and_set_stream_change_nothing(dim, n):
         assert np.array_equal(a.get(name), b.get(name)), name
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("dim,n", [(2, 90), (3, 24)])
+def test_direct_flag_equals_graphs(dim, n):
+    # C4M_FLAG_DIRECT launches every step directly: same bits as graph replay
+    import torch
+    from paper_2306_17263_amd import FLAG_DIRECT, Problem
+    init = random_fields(dim, n, seed=3 * n)
+    st = torch.cuda.Stream()
+    g = Problem(dim, n, 0.4, stream=st)
+    d = Problem(dim, n, 0.4, stream=st, flags=FLAG_DIRECT)
+    for p in (g, d):
+        for name in p.fields():
+            p.set(name, init[name])
+    for k in (5, 40):
+        g.step(k)
+        d.step(k)
+    for name in g.fields():
+        assert np.array_equal(g.get(name), d.get(name)), name
+    g.close()
+    d.close()
