@@ -111,7 +111,8 @@ typedef struct {
     int32_t lap_mode;   /* C4M_LAP_*                                                   */
     int32_t precision;  /* C4M_FP64 or C4M_FP32_REFINED                                */
     int32_t solver;     /* C4M_SOLVER_*                                                */
-    int32_t sweeps;     /* Chebyshev M-applications per solve (0 = enough for 1e-16)   */
+    int32_t sweeps;     /* Chebyshev M-applications per solve (0 = the fewest whose    *
+                         * contraction is below 4e-16: 5 at 2D r = 0.5, 4 at 3D r = 0.4) */
     int32_t max_iter;   /* PCG iteration cap per solve (0 = 16)                         */
     double rtol;        /* PCG relative residual target (0 = 1e-14)                    */
     int32_t tile_x;     /* column kernel shape, 0..4 (0 = built-in, see below)         */

@@ -10,7 +10,7 @@ Tunables (fields of c4m_config):
   tile_y  batched form only: persistent-grid multiplier (workgroups per
           launch = multiplier x what fits on the device at once).
 The halo depth of the column tiles equals the number of Chebyshev sweeps,
-which the accuracy target fixes (the smallest count reaching 1e-16 on the
+which the accuracy target fixes (the smallest count reaching 4e-16 on the
 spectral bounds of M); the tuner keeps it and picks the shape.
 
 Candidates are timed on the caller's workload with HIP events on a private

@@ -624,7 +624,7 @@ int config_sweeps(const c4m_config& c)
     const double lmin = alpha, lmax = alpha + 16.0 / 3.0 * beta;
     const double sigma = (lmax + lmin) / (lmax - lmin);
     int k = 1;
-    while (k < MAX_SWEEPS && 1.0 / cosh((k + 1) * acosh(sigma)) > 1e-16) ++k;
+    while (k < MAX_SWEEPS && 1.0 / cosh((k + 1) * acosh(sigma)) > CHEB_TOL) ++k;
     return k;
 }
 

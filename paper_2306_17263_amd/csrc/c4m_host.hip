@@ -1004,10 +1004,10 @@ c4m_status c4m_create(const c4m_config* cfg_in, void* d_workspace, size_t bytes,
         // two FP32 rounds of s applications around one FP64 residual; the
         // tile halo (and ChebSchedule::sweeps) is 2 s + 1
         const int s_round = cfg->sweeps > 0 ? cfg->sweeps : 2;
-        p->cheb = chebyshev(p->coef.alpha, p->coef.beta, 2 * s_round + 1, 1e-16);
+        p->cheb = chebyshev(p->coef.alpha, p->coef.beta, 2 * s_round + 1, CHEB_TOL);
         p->cheb.sweeps = 2 * s_round + 1;
     } else {
-        p->cheb = chebyshev(p->coef.alpha, p->coef.beta, cfg->sweeps, 1e-16);
+        p->cheb = chebyshev(p->coef.alpha, p->coef.beta, cfg->sweeps, CHEB_TOL);
     }
     set_alg_bytes(p);
 

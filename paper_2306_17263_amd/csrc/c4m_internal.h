@@ -54,6 +54,11 @@ struct PadeLine {
 // Spectral bounds of M = alpha I - beta L9: [alpha, alpha + 16/3 beta]
 // (symbol S in [0, 16/3], Appendix A.2); Chebyshev schedule on them.
 constexpr int MAX_SWEEPS = 8;
+// Default number of applications: the fewest whose Chebyshev contraction
+// 1 / T_{K+1}(sigma) is below CHEB_TOL, about two units in the last place
+// of FP64 (below the CG tolerance of the paper's solver, so the solve is
+// exact to rounding): five at r = 0.5 in 2D, four at r = 0.4 in 3D.
+constexpr double CHEB_TOL = 4e-16;
 struct ChebSchedule {
     double inv_theta;                // 1 / theta, theta = (lmax + lmin) / 2
     double c1[MAX_SWEEPS];           // d <- c1 d + c2 r after apply k
