@@ -236,6 +236,56 @@ c4m_status c4m_set_stream(c4m_problem* p, void* stream);
  * NC scheme. */
 c4m_status c4m_init_h_taylor(c4m_problem* p);
 
+/* Sources (Section 3.1: eq:mh, Table tab:spec; Section 3.3: the ghost values
+ * of Method 2, eq:gst2), 2D TM problems with a current J = (0, 0, Jz).  The
+ * caller supplies J and the derivatives that the scheme's formulas need,
+ * sampled at the right times; the library forms the source terms, the ghost
+ * values and the solves.  Every pointer is device memory (FP64, dense, x
+ * fastest, the layout of c4m_set_field); NULL stands for zeros.  Readings
+ * followed (the printed source terms disagree with the derivation that
+ * precedes them; the derivation is followed):
+ *   Step 1 adds F_J = -Z (Jz + (h_t^2/24) d2Jz/dt2) to F, Step 2 adds
+ *   (h_t^2/24) curl dJ/dt; each with its Laplacian as given (the eq:helm2
+ *   form); ghosts along a half-point axis phi(-h/2) = phi(h/2) - h q,
+ *   q = phi_n + (h^2/24) phi_nnn (eq:gst2), for H in G(H) (Step 1) and for
+ *   delta_t H in the rows of M next to the walls (Step 2); on the E walls
+ *   G_E = (h^2/12) Z dJz/dt (there Delta Ez = Z dJz/dt). */
+typedef struct c4m_source_tm {
+    /* Step 1, at tau^{n+1/2}, on the Ez grid ((N+1) x (N+1)) */
+    const double* jz;            /* Jz */
+    const double* jz_tt;         /* d2 Jz / dtau2 */
+    const double* jz_lap;        /* Delta Jz */
+    const double* jz_tt_lap;     /* Delta d2 Jz / dtau2 */
+    /* H at tau^{n+1/2} on its half-point walls, N+1 values along the wall
+     * (node points): hx_wall[w][0] = dHx/dy, hx_wall[w][1] = d3Hx/dy3 at
+     * y = w; hy_wall[w][0] = dHy/dx, hy_wall[w][1] = d3Hy/dx3 at x = w */
+    const double* hx_wall[2][2];
+    const double* hy_wall[2][2];
+    /* Step 2, at tau^{n+1} */
+    const double* jz_t;          /* dJz/dtau on the Ez grid (read on the walls) */
+    const double* kx;            /* (curl dJ/dtau)_x = d/dy dJz/dtau, Hx grid (N x (N+1)) */
+    const double* kx_lap;        /* its Laplacian */
+    const double* ky;            /* (curl dJ/dtau)_y = -d/dx dJz/dtau, Hy grid ((N+1) x N) */
+    const double* ky_lap;
+    const double* dhx_wall[2][2];   /* as hx_wall and hy_wall, of dH/dtau */
+    const double* dhy_wall[2][2];
+} c4m_source_tm;
+
+/* Device bytes of the `work` argument of c4m_step_source (0 for a problem
+ * that cannot take sources). */
+size_t c4m_source_work_bytes(const c4m_problem* p);
+
+/* One step with sources (asynchronous, on the problem's stream): the step
+ * of c4m_step plus, in each half-step, the solve of M for the source part
+ * of the right-hand side (M's Chebyshev iteration in FP64, the problem's
+ * schedule), added to the field before the next half-step reads it.  `work`:
+ * device memory of at least c4m_source_work_bytes(p) bytes, 256-byte
+ * aligned, the caller's; the source arrays and `work` must stay valid until
+ * the stream has run the step.  EINVAL unless 2D, the compact scheme and
+ * the PAPER closure (the REFLECT rows assume homogeneous Neumann data), or
+ * for a short `work`; ESTATE for a batch member. */
+c4m_status c4m_step_source(c4m_problem* p, const c4m_source_tm* src, void* work, size_t work_bytes);
+
 /* Counters and sticky flags; synchronises the stream when PCG statistics
  * or the finite check are involved. */
 c4m_status c4m_get_info(c4m_problem* p, c4m_info* info);

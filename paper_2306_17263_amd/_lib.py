@@ -27,8 +27,19 @@ EXPORTS = [
     "c4m_set_stream", "c4m_get_info", "c4m_destroy",
     "c4m_batch_workspace_bytes", "c4m_batch_create", "c4m_batch_problem", "c4m_batch_step",
     "c4m_batch_check", "c4m_batch_get_info", "c4m_batch_destroy", "c4m_batch_tables_bytes", "c4m_batch_create_from",
-    "c4m_step_fields_noalloc", "c4m_status_string", "c4m_last_error",
+    "c4m_step_fields_noalloc", "c4m_source_work_bytes", "c4m_step_source", "c4m_status_string", "c4m_last_error",
 ]
+
+
+_Wall = (ctypes.c_void_p * 2) * 2
+
+
+class C4mSourceTM(ctypes.Structure):
+    """c4m_source_tm: device pointers of one sourced 2D step (NULL = zeros)."""
+    _fields_ = [("jz", ctypes.c_void_p), ("jz_tt", ctypes.c_void_p), ("jz_lap", ctypes.c_void_p),
+                ("jz_tt_lap", ctypes.c_void_p), ("hx_wall", _Wall), ("hy_wall", _Wall),
+                ("jz_t", ctypes.c_void_p), ("kx", ctypes.c_void_p), ("kx_lap", ctypes.c_void_p),
+                ("ky", ctypes.c_void_p), ("ky_lap", ctypes.c_void_p), ("dhx_wall", _Wall), ("dhy_wall", _Wall)]
 
 
 class C4mConfig(ctypes.Structure):
@@ -95,8 +106,11 @@ def load():
     lib.c4m_batch_tables_bytes.argtypes = [ctypes.POINTER(vp), i32, ctypes.POINTER(sz)]
     lib.c4m_batch_create_from.argtypes = [ctypes.POINTER(vp), i32, vp, sz, vp, ctypes.POINTER(vp)]
     lib.c4m_step_fields_noalloc.argtypes = [cfgp, ctypes.POINTER(vp), i64, vp]
+    lib.c4m_source_work_bytes.argtypes = [vp]
+    lib.c4m_source_work_bytes.restype = sz
+    lib.c4m_step_source.argtypes = [vp, ctypes.POINTER(C4mSourceTM), vp, sz]
     for name in EXPORTS:
-        if name in ("c4m_status_string", "c4m_last_error"):
+        if name in ("c4m_status_string", "c4m_last_error", "c4m_source_work_bytes"):
             continue
         getattr(lib, name).restype = ctypes.c_int
     lib.c4m_status_string.argtypes = [ctypes.c_int]

@@ -10,6 +10,7 @@
 #include <vector>
 
 #include "c4m_internal.h"
+#include "c4m_source.h"
 
 namespace c4m {
 
@@ -339,6 +340,7 @@ struct c4m_problem {
     std::map<int64_t, std::pair<hipGraph_t, hipGraphExec_t>> graphs;   // captured runs of steps
     bool direct = false;                // launch steps without graphs (no-allocation call)
     std::vector<Launch3> plan3;         // 3D FP64 Chebyshev step as recorded launches (built on first use)
+    std::vector<double> src_cols;       // sourced step: column 0 of A^{-1}, half->node (N-1) then node->half (N)
 };
 
 namespace {
@@ -710,10 +712,87 @@ c4m_status step3(c4m_problem* p)
     return s;
 }
 
-c4m_status step_once(c4m_problem* p)
+// 2D: the strip form's band table (filled by the x-line launches) when the
+// configuration runs strips, else nullptr.  One buffer resource spans the
+// arrays a strip touches, so the used part of the workspace must stay below
+// 4 GiB.
+double* band_2d(c4m_problem* p)
+{
+    return (p->cfg.solver == C4M_SOLVER_CHEBYSHEV && p->yband && p->used < (size_t)0xFFFFF000u &&
+            strip_form_2d(p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, p->cheb.sweeps))
+               ? p->yband
+               : nullptr;
+}
+
+// 2D Step 1 (Section 3.4): right-hand side and solve of Ez, with its update.
+c4m_status step_e_2d(c4m_problem* p)
 {
     const int N = p->N, P = p->P;
     const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+    double *hx = p->f[C4M_HX], *hy = p->f[C4M_HY], *ez = p->f[C4M_EZ], *ge = p->ge[2];
+    double *t0 = p->tmp[0], *t1 = p->tmp[1];
+    const bool pcg = p->cfg.solver == C4M_SOLVER_PCG;
+    const bool tsolve = p->cfg.solver == C4M_SOLVER_TRANSFORM;
+    double* yb = band_2d(p);
+    c4m_status s = timed(p, C4M_K_RHS_E, "rhs E", [&] {
+        return launch_rhs_e_2d(p->stream, tracked, hx, hy, t0, t1, N, P, p->coef,
+                               p->pade_host[1].taps, p->line[1], yb);
+    });
+    if (s == C4M_OK && tsolve)
+        s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
+            return launch_tsolve_e_2d(p->stream, tracked, hx, ez, ge, t0, t1, N, P, p->coef, p->pade_host[1].taps,
+                                      p->line[1], p->cheb, p->tmp + 2, p->tt);
+        });
+    else if (s == C4M_OK && pcg)
+        s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
+            return launch_pcg_e_2d(p->stream, tracked, hx, ez, ge, t0, t1, N, P, p->coef, p->pade_host[1].taps,
+                                   p->line[1], p->cheb, p->tmp + 2, p->pcg_part, p->pcg_state, pcg_rtol(p),
+                                   pcg_max_iter(p));
+        });
+    else if (s == C4M_OK)
+        s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
+            return launch_solve_e_2d(p->stream, p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, tracked, hx, ez, ge, t0, t1, N, P, p->coef,
+                                     p->pade_host[1].taps, p->line[1], p->cheb, yb);
+        });
+    return s;
+}
+
+// 2D Step 2 (Section 3.4): right-hand sides and solves of Hx and Hy.
+c4m_status step_h_2d(c4m_problem* p)
+{
+    const int N = p->N, P = p->P;
+    const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+    double *hx = p->f[C4M_HX], *hy = p->f[C4M_HY], *ez = p->f[C4M_EZ], *ge = p->ge[2];
+    double *t0 = p->tmp[0], *t1 = p->tmp[1];
+    const bool pcg = p->cfg.solver == C4M_SOLVER_PCG;
+    const bool tsolve = p->cfg.solver == C4M_SOLVER_TRANSFORM;
+    double* yb = band_2d(p);
+    c4m_status s = timed(p, C4M_K_RHS_H, "rhs H", [&] {
+        return launch_rhs_h_2d(p->stream, tracked, tracked ? ge : ez, t0, t1, N, P, p->coef,
+                               p->pade_host[0].taps, p->line[0], yb);
+    });
+    if (s == C4M_OK && tsolve)
+        s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
+            return launch_tsolve_h_2d(p->stream, tracked, tracked ? ge : ez, hx, hy, t1, N, P, p->coef,
+                                      p->pade_host[0].taps, p->line[0], p->cheb, p->tmp + 2, p->tt);
+        });
+    else if (s == C4M_OK && pcg)
+        s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
+            return launch_pcg_h_2d(p->stream, tracked, tracked ? ge : ez, hx, hy, t1, N, P, p->coef,
+                                   p->pade_host[0].taps, p->line[0], p->cheb, p->tmp + 2, p->pcg_part,
+                                   p->pcg_state, pcg_rtol(p), pcg_max_iter(p));
+        });
+    else if (s == C4M_OK)
+        s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
+            return launch_solve_h_2d(p->stream, p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, tracked, tracked ? ge : ez, hx, hy, t1, N, P,
+                                     p->coef, p->pade_host[0].taps, p->line[0], p->cheb, yb);
+        });
+    return s;
+}
+
+c4m_status step_once(c4m_problem* p)
+{
+    const int N = p->N, P = p->P;
     if (p->cfg.scheme == C4M_SCHEME_NC) {
         // the comparison scheme NC (Section 5.2): Yee update with K4 at a = 0
         double *ez = p->f[C4M_EZ], *hx = p->f[C4M_HX], *hy = p->f[C4M_HY];
@@ -727,59 +806,8 @@ c4m_status step_once(c4m_problem* p)
         return s;
     }
     if (p->dim == 2) {
-        double *hx = p->f[C4M_HX], *hy = p->f[C4M_HY], *ez = p->f[C4M_EZ], *ge = p->ge[2];
-        double *t0 = p->tmp[0], *t1 = p->tmp[1];
-        const bool pcg = p->cfg.solver == C4M_SOLVER_PCG;
-        // the strip form (band table filled by the x-line launches): one
-        // buffer resource spans the arrays it touches, so the used part of
-        // the workspace must stay below 4 GiB
-        double* yb = (p->cfg.solver == C4M_SOLVER_CHEBYSHEV && p->yband && p->used < (size_t)0xFFFFF000u &&
-                      strip_form_2d(p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, p->cheb.sweeps))
-                         ? p->yband
-                         : nullptr;
-        c4m_status s = timed(p, C4M_K_RHS_E, "rhs E", [&] {
-            return launch_rhs_e_2d(p->stream, tracked, hx, hy, t0, t1, N, P, p->coef,
-                                   p->pade_host[1].taps, p->line[1], yb);
-        });
-        const bool tsolve = p->cfg.solver == C4M_SOLVER_TRANSFORM;
-        if (s == C4M_OK && tsolve)
-            s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
-                return launch_tsolve_e_2d(p->stream, tracked, hx, ez, ge, t0, t1, N, P, p->coef, p->pade_host[1].taps,
-                                          p->line[1], p->cheb, p->tmp + 2, p->tt);
-            });
-        else if (s == C4M_OK && pcg)
-            s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
-                return launch_pcg_e_2d(p->stream, tracked, hx, ez, ge, t0, t1, N, P, p->coef, p->pade_host[1].taps,
-                                       p->line[1], p->cheb, p->tmp + 2, p->pcg_part, p->pcg_state, pcg_rtol(p),
-                                       pcg_max_iter(p));
-            });
-        else if (s == C4M_OK)
-            s = timed(p, C4M_K_SOLVE_E, "solve E", [&] {
-                return launch_solve_e_2d(p->stream, p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, tracked, hx, ez, ge, t0, t1, N, P, p->coef,
-                                         p->pade_host[1].taps, p->line[1], p->cheb, yb);
-            });
-        if (s == C4M_OK)
-            s = timed(p, C4M_K_RHS_H, "rhs H", [&] {
-                return launch_rhs_h_2d(p->stream, tracked, tracked ? ge : ez, t0, t1, N, P, p->coef,
-                                       p->pade_host[0].taps, p->line[0], yb);
-            });
-        if (s == C4M_OK && tsolve)
-            s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
-                return launch_tsolve_h_2d(p->stream, tracked, tracked ? ge : ez, hx, hy, t1, N, P, p->coef,
-                                          p->pade_host[0].taps, p->line[0], p->cheb, p->tmp + 2, p->tt);
-            });
-        else if (s == C4M_OK && pcg)
-            s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
-                return launch_pcg_h_2d(p->stream, tracked, tracked ? ge : ez, hx, hy, t1, N, P, p->coef,
-                                       p->pade_host[0].taps, p->line[0], p->cheb, p->tmp + 2, p->pcg_part,
-                                       p->pcg_state, pcg_rtol(p), pcg_max_iter(p));
-            });
-        else if (s == C4M_OK)
-            s = timed(p, C4M_K_SOLVE_H, "solve H", [&] {
-                return launch_solve_h_2d(p->stream, p->cfg.tile_x, p->cfg.precision == C4M_FP32_REFINED, tracked, tracked ? ge : ez, hx, hy, t1, N, P,
-                                         p->coef, p->pade_host[0].taps, p->line[0], p->cheb, yb);
-            });
-        return s;
+        c4m_status s = step_e_2d(p);
+        return s == C4M_OK ? step_h_2d(p) : s;
     }
     return step3(p);
 }
@@ -1269,6 +1297,110 @@ c4m_status c4m_init_h_taylor(c4m_problem* p)
         if (e == hipSuccess) e = launch_taylor_combine(p->stream, h, cu, lh, bh, p->P, p->plane, c);
         if (e != hipSuccess) return hip_fail(e, "Taylor start");
     }
+    return C4M_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Sources (2D TM): the step of c4m_step with the correction of each
+// half-step's right-hand side for J (c4m_source.hip).
+// ---------------------------------------------------------------------------
+static bool takes_sources(const c4m_problem* p)
+{
+    return p && p->dim == 2 && p->cfg.scheme == C4M_SCHEME_C4 && p->cfg.closure == C4M_CLOSURE_PAPER;
+}
+
+// b, two iterates (one array each, the fields' pitch), then the two Pade
+// columns
+struct SrcWork {
+    size_t arr_bytes, cols_off, total;
+};
+
+static SrcWork src_work(const c4m_problem* p)
+{
+    SrcWork w{};
+    w.arr_bytes = (p->arr * sizeof(double) + 255) & ~(size_t)255;
+    w.cols_off = 3 * w.arr_bytes;
+    w.total = w.cols_off + (((size_t)(2 * p->N - 1) * sizeof(double) + 255) & ~(size_t)255);
+    return w;
+}
+
+static ChebGeom src_geom(const c4m_problem* p, int comp)
+{
+    const Box& bx = p->box[comp];
+    ChebGeom g{};
+    for (int d = 0; d < 2; ++d) {
+        g.n[d] = bx.n[d];
+        g.half[d] = bx.half[d];
+        g.lo[d] = bx.half[d] ? 0 : 1;
+        g.hi[d] = bx.half[d] ? bx.n[d] - 1 : bx.n[d] - 2;
+    }
+    g.P = p->P;
+    g.alpha = p->coef.alpha;
+    g.beta = p->coef.beta;
+    g.inv_theta = p->cheb.inv_theta;
+    return g;
+}
+
+size_t c4m_source_work_bytes(const c4m_problem* p)
+{
+    return takes_sources(p) ? src_work(p).total : 0;
+}
+
+c4m_status c4m_step_source(c4m_problem* p, const c4m_source_tm* src, void* work, size_t work_bytes)
+{
+    if (!p || !src) return fail(C4M_EINVAL, "null argument");
+    if (p->owned_by_batch) return fail(C4M_ESTATE, "problem belongs to a batch");
+    if (!takes_sources(p)) return fail(C4M_EINVAL, "sources take a 2D problem of the compact scheme with the PAPER closure");
+    const SrcWork w = src_work(p);
+    if (!work || work_bytes < w.total || ((uintptr_t)work & 255)) return fail(C4M_EINVAL, "work buffer too small or not 256-byte aligned");
+    const int N = p->N;
+    if (p->src_cols.empty()) {
+        // column 0 of A^{-1} for the two line kinds of the 2D curl (eq:lhs)
+        std::vector<double> col;
+        BandLU a = pade_matrix(N - 1, C4M_CLOSURE_PAPER, false);
+        inverse_column(a, 0, col);
+        p->src_cols = col;
+        BandLU c = pade_matrix(N, C4M_CLOSURE_PAPER, true);
+        inverse_column(c, 0, col);
+        p->src_cols.insert(p->src_cols.end(), col.begin(), col.end());
+    }
+    char* base = (char*)work;
+    double* b = (double*)base;
+    double* xa = (double*)(base + w.arr_bytes);
+    double* xb = (double*)(base + 2 * w.arr_bytes);
+    double* wc = (double*)(base + w.cols_off);
+    double* vc = wc + (N - 1);
+    hipError_t e = hipMemcpyAsync(wc, p->src_cols.data(), p->src_cols.size() * sizeof(double),
+                                  hipMemcpyHostToDevice, p->stream);
+    if (e != hipSuccess) return hip_fail(e, "source tables");
+    c4m_status s = ensure_ge(p);
+    if (s != C4M_OK) return s;
+    const double r = p->cfg.cfl, z = p->cfg.z, h = 1.0 / N;
+    SrcCoef c{h, (r * h) * (r * h) / 24.0, h * h / 24.0, p->coef.alpha, p->coef.beta, z};
+    const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+    // Step 1: the step's E half, then Phi_J of Ez
+    s = step_e_2d(p);
+    if (s != C4M_OK) return s;
+    e = launch_src_rhs_e(p->stream, b, *src, wc, N, p->P, c);
+    if (e == hipSuccess) {
+        SrcUpdate u{p->f[C4M_EZ], tracked ? p->ge[2] : nullptr, src->jz, src->jz_tt, r, z, c.ht2,
+                    p->coef.ge_gain, 2.0 / r * h};
+        e = launch_src_solve(p->stream, b, xa, xb, src_geom(p, C4M_EZ), p->cheb, u);
+    }
+    if (e != hipSuccess) return hip_fail(e, "source E");
+    // Step 2: the step's H half, then Phi_J of Hx and Hy
+    s = step_h_2d(p);
+    if (s != C4M_OK) return s;
+    for (int comp = 0; comp < 2 && e == hipSuccess; ++comp) {
+        const int f = comp == 0 ? C4M_HX : C4M_HY;
+        e = launch_src_rhs_h(p->stream, b, *src, vc, comp, N, p->P, c);
+        if (e == hipSuccess) {
+            SrcUpdate u{p->f[f], nullptr, nullptr, nullptr, r, z, c.ht2, 0.0, 0.0};
+            e = launch_src_solve(p->stream, b, xa, xb, src_geom(p, f), p->cheb, u);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(e, "source H");
+    ++p->steps;
     return C4M_OK;
 }
 

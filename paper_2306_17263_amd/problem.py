@@ -8,6 +8,7 @@ import numpy as np
 import torch
 
 from . import _lib as L
+from contextlib import nullcontext as _nullctx
 
 
 def make_config(dim: int = 2, n: int = 64, cfl: float = 0.5, z: float = 1.0,
@@ -127,6 +128,50 @@ class Problem:
     def init_h_taylor(self):
         """Replace H (set at tau = 0) by H at tau = h_tau/2 (Taylor start)."""
         L.check(self._lib.c4m_init_h_taylor(self._h), "c4m_init_h_taylor")
+
+    SOURCE_ARRAYS = ("jz", "jz_tt", "jz_lap", "jz_tt_lap", "jz_t", "kx", "kx_lap", "ky", "ky_lap")
+    SOURCE_WALLS = ("hx_wall", "hy_wall", "dhx_wall", "dhy_wall")
+
+    def step_source(self, data: dict):
+        """One step with a current J = (0, 0, Jz) (2D, compact scheme, PAPER
+        closure): `data` maps the member names of c4m_source_tm to arrays
+        (numpy or CUDA tensors; a wall entry is [[first, third] at wall 0,
+        [first, third] at wall 1]); a missing name stands for zeros.  The
+        arrays are moved to the device on the problem's stream."""
+        n = self.n
+        shapes = {"kx": (n, n + 1), "kx_lap": (n, n + 1), "ky": (n + 1, n), "ky_lap": (n + 1, n)}
+        keep = []
+        src = L.C4mSourceTM()
+        ctx = torch.cuda.stream(self.stream) if isinstance(self.stream, torch.cuda.Stream) else _nullctx()
+        with ctx:
+            def dev(a, shape):
+                t = torch.as_tensor(np.asarray(a) if not isinstance(a, torch.Tensor) else a)
+                t = t.to(device=self.device, dtype=torch.float64).contiguous()
+                if t.numel() != int(np.prod(shape)):
+                    raise ValueError(f"source array of {t.numel()} values, expected shape {shape}")
+                keep.append(t)
+                return t.data_ptr()
+
+            for name in self.SOURCE_ARRAYS:
+                if data.get(name) is not None:
+                    setattr(src, name, dev(data[name], shapes.get(name, (n + 1, n + 1))))
+            for name in self.SOURCE_WALLS:
+                walls = data.get(name)
+                if walls is None:
+                    continue
+                slot = getattr(src, name)
+                for w in (0, 1):
+                    for d in (0, 1):
+                        if walls[w][d] is not None:
+                            slot[w][d] = dev(walls[w][d], (n + 1,))
+            need = int(self._lib.c4m_source_work_bytes(self._h))
+            if need == 0:
+                raise L.C4mError(1, "c4m_step_source", "this problem takes no sources")
+            if getattr(self, "_src_work", None) is None or self._src_work.numel() < need:
+                self._src_work = torch.empty(need, dtype=torch.uint8, device=self.device)
+        L.check(self._lib.c4m_step_source(self._h, ctypes.byref(src), ctypes.c_void_p(self._src_work.data_ptr()),
+                                          need), "c4m_step_source")
+        self._src_keep = keep   # released after the next call, stream-ordered
 
     def prepare(self, nsteps: int):
         """Capture the graphs that step(nsteps) replays, without running them."""
