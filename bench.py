@@ -300,7 +300,7 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=256)
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="batch", choices=["2d", "batch", "3d", "serve", "sweep", "nc"],
+    ap.add_argument("--workload", default="batch", choices=["2d", "batch", "3d", "serve", "sweep", "nc", "source"],
                     help="batch: 512 seeded 2D cavities of uneven N (default); 2d: the N=2048 "
                          "refinement-sweep cavity; 3d: the cube cavity")
     ap.add_argument("--count", type=int, default=512)
@@ -341,6 +341,8 @@ def main():
         return bench_sweep(args)
     if args.workload == "nc":
         return bench_nc(args)
+    if args.workload == "source":
+        return bench_source(args)
 
     import torch
     if not torch.cuda.is_available():
@@ -842,6 +844,87 @@ def bench_nc(args):
                      "per_kernel_avg_us": {c: round(v["avg_us"], 3) for c, v in per.items()}},
         "runs": runs,
         "error_ratio_nc_over_c4": runs["nc"]["l2_vs_exact"] / runs["c4"]["l2_vs_exact"],
+    }
+    print(json.dumps(line), flush=True)
+
+
+def bench_source(args):
+    """The 2D step with a current Jz (c4m_step_source) on the driven cavity
+    (N = 2048, CFL 0.5; the source arrays of one instant, resident on the
+    device and reused every step), next to the plain step of the same
+    problem: throughput, and the source correction's roofline (one launch
+    group per field component: its right-hand side and the Chebyshev
+    applications of M, against the compulsory bytes of the group)."""
+    import torch
+    from paper_2306_17263_amd import Problem
+    from paper_2306_17263_amd import _lib as L
+    from workloads.driven import DrivenTM
+    n, cfl = args.n, args.cfl
+    ht = cfl / n
+    steps = args.steps if args.steps is not None else 200
+    drv = DrivenTM()
+    init = drv.fields(n, 0.0, ht / 2)
+    st = torch.cuda.Stream()
+    data = dict(drv.step1_data(n, 0.25))
+    data.update(drv.step2_data(n, 0.25))
+
+    def on_dev(v):
+        if isinstance(v, list):
+            return [[torch.as_tensor(a).to("cuda") for a in w] for w in v]
+        return torch.as_tensor(v).to("cuda").contiguous()
+
+    with torch.cuda.stream(st):
+        dev = {k: on_dev(v) for k, v in data.items()}
+    torch.cuda.synchronize()
+    runs = {}
+    for mode in ("source", "plain"):
+        p = Problem(2, n, cfl, stream=st)
+        for name in p.fields():
+            p.set(name, init[name])
+        go = (lambda k: [p.step_source(dev) for _ in range(k)]) if mode == "source" else p.step
+        go(args.warmup)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(st)
+        go(steps)
+        ev1.record(st)
+        torch.cuda.synchronize()
+        el = max(time.perf_counter() - t0, ev0.elapsed_time(ev1) / 1e3)
+        runs[mode] = {"ms_per_step": round(el * 1e3 / steps, 5), "mcell_steps_per_s": round(n * n * steps / el / 1e6, 2)}
+        p.close()
+    # per-class averages from a separate profiled run (events around every launch group)
+    p = Problem(2, n, cfl, stream=st, flags=L.FLAG_PROFILE)
+    for name in p.fields():
+        p.set(name, init[name])
+    for _ in range(args.warmup):
+        p.step_source(dev)
+    w0 = p.info()
+    for _ in range(min(steps, args.profile_steps)):
+        p.step_source(dev)
+    inf = p.info()
+    per = {}
+    for ci, cname in enumerate(L.KERNEL_CLASSES):
+        cnt = inf["kernel_launches"][ci] - w0["kernel_launches"][ci]
+        if cnt:
+            per[cname] = {"avg_us": 1e3 * (inf["kernel_ms"][ci] - w0["kernel_ms"][ci]) / cnt,
+                          "alg_bytes": inf["kernel_alg_bytes"][ci]}
+    p.close()
+    src = per["other"]
+    ach = src["alg_bytes"] / (src["avg_us"] * 1e-6) / 1e9
+    line = {
+        "metric": "sourced 2D step throughput", "value": runs["source"]["mcell_steps_per_s"], "unit": "Mcell-steps/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": runs["source"]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (the driven-cavity current and wall data of one instant, resident and reused every step)",
+        "config": {"workload": f"2D TM PEC cavity driven by a current Jz, N={n}, CFL {cfl}", "n": n},
+        "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "other",
+                     "kernels": "k_src_tile (one launch per field component: its source right-hand side and K applications of M on an LDS window, then the update)",
+                     "avg_us": round(src["avg_us"], 3), "alg_bytes_per_launch": src["alg_bytes"],
+                     "per_class_avg_us": {c: round(v["avg_us"], 3) for c, v in per.items()}},
+        "runs": runs,
+        "source_overhead_ms_per_step": round(runs["source"]["ms_per_step"] - runs["plain"]["ms_per_step"], 5),
     }
     print(json.dumps(line), flush=True)
 

@@ -17,7 +17,8 @@
  *                               or recomputed as L5 E in the DISCRETE variant).
  * Boundary treatment: tangential E = 0 on the walls (eq:bc_E=0), normal H
  * constant in time (eq:BC_H), even ghosts for the Neumann directions
- * (Corollary cor:ghost_cor).  Only J = rho = 0 is supported.
+ * (Corollary cor:ghost_cor).  c4m_step takes J = rho = 0; c4m_step_source
+ * steps a 2D (TM) problem driven by a current Jz (Section 3.1).
  *
  * Memory and streams: the caller owns the device workspace (size from
  * c4m_workspace_bytes, 256-byte aligned) and the HIP stream; the library
@@ -97,7 +98,8 @@ enum { C4M_K_RHS_E = 0,      /* Pade curl of G(H): Step 1 right-hand side       
        C4M_K_SOLVE_H = 3,    /* compact solve + H update                           */
        C4M_K_STEP_E = 4,     /* fused Step 1 (right-hand side, solve, update)      */
        C4M_K_STEP_H = 5,     /* fused Step 2                                       */
-       C4M_K_OTHER = 6,      /* everything else (conversions, reductions)          */
+       C4M_K_OTHER = 6,      /* everything else; the source corrections of        *
+                              * c4m_step_source (one group per component)        */
        C4M_K_STEP = 7,       /* a whole step in one launch (batched strip form)    */
        C4M_K_COUNT = 8 };
 

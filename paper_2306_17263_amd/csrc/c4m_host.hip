@@ -1309,19 +1309,10 @@ static bool takes_sources(const c4m_problem* p)
     return p && p->dim == 2 && p->cfg.scheme == C4M_SCHEME_C4 && p->cfg.closure == C4M_CLOSURE_PAPER;
 }
 
-// b, two iterates (one array each, the fields' pitch), then the two Pade
-// columns
-struct SrcWork {
-    size_t arr_bytes, cols_off, total;
-};
-
-static SrcWork src_work(const c4m_problem* p)
+// the two Pade columns of the correction's right-hand sides
+static size_t src_work_bytes(const c4m_problem* p)
 {
-    SrcWork w{};
-    w.arr_bytes = (p->arr * sizeof(double) + 255) & ~(size_t)255;
-    w.cols_off = 3 * w.arr_bytes;
-    w.total = w.cols_off + (((size_t)(2 * p->N - 1) * sizeof(double) + 255) & ~(size_t)255);
-    return w;
+    return ((size_t)(2 * p->N - 1) * sizeof(double) + 255) & ~(size_t)255;
 }
 
 static ChebGeom src_geom(const c4m_problem* p, int comp)
@@ -1343,7 +1334,7 @@ static ChebGeom src_geom(const c4m_problem* p, int comp)
 
 size_t c4m_source_work_bytes(const c4m_problem* p)
 {
-    return takes_sources(p) ? src_work(p).total : 0;
+    return takes_sources(p) ? src_work_bytes(p) : 0;
 }
 
 c4m_status c4m_step_source(c4m_problem* p, const c4m_source_tm* src, void* work, size_t work_bytes)
@@ -1351,8 +1342,8 @@ c4m_status c4m_step_source(c4m_problem* p, const c4m_source_tm* src, void* work,
     if (!p || !src) return fail(C4M_EINVAL, "null argument");
     if (p->owned_by_batch) return fail(C4M_ESTATE, "problem belongs to a batch");
     if (!takes_sources(p)) return fail(C4M_EINVAL, "sources take a 2D problem of the compact scheme with the PAPER closure");
-    const SrcWork w = src_work(p);
-    if (!work || work_bytes < w.total || ((uintptr_t)work & 255)) return fail(C4M_EINVAL, "work buffer too small or not 256-byte aligned");
+    if (!work || work_bytes < src_work_bytes(p) || ((uintptr_t)work & 255))
+        return fail(C4M_EINVAL, "work buffer too small or not 256-byte aligned");
     const int N = p->N;
     if (p->src_cols.empty()) {
         // column 0 of A^{-1} for the two line kinds of the 2D curl (eq:lhs)
@@ -1364,11 +1355,7 @@ c4m_status c4m_step_source(c4m_problem* p, const c4m_source_tm* src, void* work,
         inverse_column(c, 0, col);
         p->src_cols.insert(p->src_cols.end(), col.begin(), col.end());
     }
-    char* base = (char*)work;
-    double* b = (double*)base;
-    double* xa = (double*)(base + w.arr_bytes);
-    double* xb = (double*)(base + 2 * w.arr_bytes);
-    double* wc = (double*)(base + w.cols_off);
+    double* wc = (double*)work;
     double* vc = wc + (N - 1);
     hipError_t e = hipMemcpyAsync(wc, p->src_cols.data(), p->src_cols.size() * sizeof(double),
                                   hipMemcpyHostToDevice, p->stream);
@@ -1376,30 +1363,44 @@ c4m_status c4m_step_source(c4m_problem* p, const c4m_source_tm* src, void* work,
     c4m_status s = ensure_ge(p);
     if (s != C4M_OK) return s;
     const double r = p->cfg.cfl, z = p->cfg.z, h = 1.0 / N;
-    SrcCoef c{h, (r * h) * (r * h) / 24.0, h * h / 24.0, p->coef.alpha, p->coef.beta, z};
     const bool tracked = p->cfg.lap_mode == C4M_LAP_TRACKED;
+    auto group = [&](int f) {
+        SrcTile a{};
+        a.s = *src;
+        a.cols = f == C4M_EZ ? wc : vc;
+        a.c = SrcCoef{h, (r * h) * (r * h) / 24.0, h * h / 24.0, p->coef.alpha, p->coef.beta, z};
+        a.g = src_geom(p, f);
+        a.u = SrcUpdate{p->f[f], nullptr, nullptr, nullptr, r, z, a.c.ht2, 0.0, 0.0};
+        if (f == C4M_EZ && tracked) {
+            a.u.ge = p->ge[2];
+            a.u.jz = src->jz;
+            a.u.jz_tt = src->jz_tt;
+            a.u.ge_gain = p->coef.ge_gain;
+            a.u.ge_src = 2.0 / r * h;
+        }
+        a.comp = f == C4M_EZ ? 2 : f - C4M_HX;
+        a.N = N;
+        a.K = p->cheb.sweeps;
+        for (int k = 0; k < a.K && k < MAX_SWEEPS; ++k) {
+            a.c1[k] = p->cheb.c1[k];
+            a.c2[k] = p->cheb.c2[k];
+        }
+        return launch_src_group(p->stream, a);
+    };
+    // Compulsory bytes of one correction group (its source arrays read once,
+    // the field, and G_E with the carried Laplacian, read and written),
+    // averaged over the three groups of a step: the E group reads four
+    // arrays, each H group two.
+    const double cells = (double)N * N;
+    p->alg_bytes[C4M_K_OTHER] = 8.0 * cells * ((4 + (tracked ? 4 : 2)) + 2 * (2 + 2)) / 3.0;
     // Step 1: the step's E half, then Phi_J of Ez
     s = step_e_2d(p);
-    if (s != C4M_OK) return s;
-    e = launch_src_rhs_e(p->stream, b, *src, wc, N, p->P, c);
-    if (e == hipSuccess) {
-        SrcUpdate u{p->f[C4M_EZ], tracked ? p->ge[2] : nullptr, src->jz, src->jz_tt, r, z, c.ht2,
-                    p->coef.ge_gain, 2.0 / r * h};
-        e = launch_src_solve(p->stream, b, xa, xb, src_geom(p, C4M_EZ), p->cheb, u);
-    }
-    if (e != hipSuccess) return hip_fail(e, "source E");
+    if (s == C4M_OK) s = timed(p, C4M_K_OTHER, "source E", [&] { return group(C4M_EZ); });
     // Step 2: the step's H half, then Phi_J of Hx and Hy
-    s = step_h_2d(p);
+    if (s == C4M_OK) s = step_h_2d(p);
+    if (s == C4M_OK) s = timed(p, C4M_K_OTHER, "source Hx", [&] { return group(C4M_HX); });
+    if (s == C4M_OK) s = timed(p, C4M_K_OTHER, "source Hy", [&] { return group(C4M_HY); });
     if (s != C4M_OK) return s;
-    for (int comp = 0; comp < 2 && e == hipSuccess; ++comp) {
-        const int f = comp == 0 ? C4M_HX : C4M_HY;
-        e = launch_src_rhs_h(p->stream, b, *src, vc, comp, N, p->P, c);
-        if (e == hipSuccess) {
-            SrcUpdate u{p->f[f], nullptr, nullptr, nullptr, r, z, c.ht2, 0.0, 0.0};
-            e = launch_src_solve(p->stream, b, xa, xb, src_geom(p, f), p->cheb, u);
-        }
-    }
-    if (e != hipSuccess) return hip_fail(e, "source H");
     ++p->steps;
     return C4M_OK;
 }

@@ -14,7 +14,7 @@ struct SrcCoef {
 };
 
 // One component grid of the correction solve: extents, half flags, the
-// unknown box (inclusive) and the M / Chebyshev constants.
+// unknown box (inclusive), the pitch and the M / Chebyshev constants.
 struct ChebGeom {
     int n[2], half[2], lo[2], hi[2], P;
     double alpha, beta, inv_theta;
@@ -29,11 +29,17 @@ struct SrcUpdate {
     double r, z, ht2, ge_gain, ge_src;
 };
 
-hipError_t launch_src_rhs_e(hipStream_t st, double* b, const SourceTM& s, const double* wc, int N, int P,
-                            const SrcCoef& c);
-hipError_t launch_src_rhs_h(hipStream_t st, double* b, const SourceTM& s, const double* vc, int comp, int N,
-                            int P, const SrcCoef& c);
-hipError_t launch_src_solve(hipStream_t st, const double* b, double* xa, double* xb, const ChebGeom& g,
-                            const ChebSchedule& cs, const SrcUpdate& u);
+// Arguments of one component's correction launch (comp 2: Ez, 0: Hx, 1: Hy).
+struct SrcTile {
+    SourceTM s;
+    const double* cols;         // Ez: column 0 of A^{-1}, half->node; Hx, Hy: node->half
+    SrcCoef c;
+    ChebGeom g;
+    SrcUpdate u;
+    int comp, N, K;
+    double c1[MAX_SWEEPS], c2[MAX_SWEEPS];
+};
+
+hipError_t launch_src_group(hipStream_t st, const SrcTile& a);
 
 }  // namespace c4m
