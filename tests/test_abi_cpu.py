@@ -61,3 +61,18 @@ def test_status_strings():
     L, lib = _lib()
     for s in range(0, -8, -1):
         assert lib.c4m_status_string(s)
+
+
+def test_source_entry_points_without_device():
+    """c4m_source_work_bytes / c4m_step_source reject a missing problem or
+    source before any device call; the ctypes struct matches the header's
+    member list."""
+    L, lib = _lib()
+    assert lib.c4m_source_work_bytes(None) == 0
+    src = L.C4mSourceTM()
+    assert lib.c4m_step_source(None, ctypes.byref(src), None, 0) == L.EINVAL
+    header = open(os.path.join(ROOT, "include", "c4m.h")).read()
+    body = header[header.index("typedef struct c4m_source_tm {"):header.index("} c4m_source_tm;")]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    members = re.findall(r"\b(\w+)(?:\[2\]\[2\])?;", body)
+    assert members == [f[0] for f in L.C4mSourceTM._fields_]
