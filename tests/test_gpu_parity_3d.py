@@ -64,3 +64,11 @@ def test_interior_taps_fp32_refined_3d(lap, closure):
 def test_interior_taps_pcg_3d(lap, closure):
     gf, of = run_pair(3, 64, 0.4, 3, closure=closure, lap=lap, k=(2, 3, 4), solver="pcg")
     check_fields(gf, of)
+
+
+def test_full_size_3d_one_step():
+    """N = 256 (the 3D workload's size, CFL 0.4, FP64 Chebyshev, the recorded
+    step the bench times): one step of seeded random data against the
+    oracle, element by element."""
+    gf, of = run_pair(3, 256, 0.4, 1, closure="paper", lap="tracked", seed=256)
+    check_fields(gf, of)
