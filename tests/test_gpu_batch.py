@@ -169,3 +169,45 @@ def test_batch_check_quiet_and_forced_give_up():
     assert ei.value.status == EDEVICE
     b.check()
     b.close()
+
+
+def test_full_batch_workload_sampled():
+    """The whole 512-cavity workload the bench times (seed 2306, N 64..768,
+    the default form), three steps; the largest, the smallest and a middle
+    member against the oracle element by element, and the same members
+    stepped alone bit for bit."""
+    import torch
+    from paper_2306_17263_amd import Batch, Problem
+    from workloads import batch_mix, mode_fields
+    specs = batch_mix(count=512)
+    steps = 3
+    st = torch.cuda.Stream()
+    b = Batch([{"n": s["n"]} for s in specs], stream=st)
+    order = sorted(range(len(specs)), key=lambda i: specs[i]["n"])
+    picks = {order[0], order[len(order) // 2], order[-1]}
+    inits = {}
+    for i, (p, s) in enumerate(zip(b.problems, specs)):
+        init = mode_fields(2, s["n"], s["k"], 0.0, s["r"] / s["n"] / 2, amp=s["amp"])
+        for name in p.fields():
+            p.set(name, init[name])
+        if i in picks:
+            inits[i] = init
+    b.step(steps)
+    names = ["ez", "hx", "hy"]
+    for i in sorted(picks):
+        s = specs[i]
+        gf = {a: b.problems[i].get(a) for a in names}
+        alone = Problem(2, s["n"], s["r"], stream=st)
+        o = oracle.OracleProblem(2, s["n"], s["r"], 1.0)
+        for name in alone.fields():
+            alone.set(name, inits[i][name])
+            o.set(name, inits[i][name])
+        alone.step(steps)
+        o.step(steps)
+        for a in names:
+            assert np.array_equal(gf[a], alone.get(a)), (s["n"], a)
+        check_fields(gf, {a: o.get(a) for a in names})
+        alone.close()
+        o.close()
+    b.check()
+    b.close()
