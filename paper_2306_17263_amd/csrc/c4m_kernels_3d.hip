@@ -743,9 +743,21 @@ void plan_step3(const Plan3In& in, std::vector<Launch3>& out)
         }
         out.push_back(r);
     };
+    // The solve in the first-order form x_{k+1} = x_k + w_k (b - M x_k),
+    // x_1 = w_0 b, with w_j = 1 / mu_j at the K + 1 roots mu_j of the
+    // Chebyshev polynomial on [alpha, alpha + 16 beta / 3]: the same residual
+    // polynomial as the three-term recurrence (whose K applications also give
+    // x_{K+1}), without reading x_{k-1}.  Every factor 1 - lambda w_j stays
+    // below 3e-3 in size on the spectrum, so the order of the steps is free.
+    const int K = in.cheb.sweeps;
+    double w[MAX_SWEEPS + 1];
+    {
+        const double lmin = in.coef.alpha, lmax = in.coef.alpha + 16.0 / 3.0 * in.coef.beta;
+        const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+        for (int j = 0; j <= K; ++j) w[j] = 1.0 / (theta - delta * cos((2 * j + 1) * M_PI / (2.0 * (K + 1))));
+    }
     auto solve = [&](int comp, double* field, double* ge, const double* cr, int cls, int group) {
         double* bufs[3] = {x, d0, d1};
-        const int K = in.cheb.sweeps;
         for (int k = 1; k <= K; ++k) {
             Launch3 r{};
             r.kind = L3_CHEB;
@@ -757,7 +769,7 @@ void plan_step3(const Plan3In& in, std::vector<Launch3>& out)
             Cheb3T<double, double>& a = r.c;
             a.b = b;
             a.xk = bufs[k % 3];
-            a.xkm1 = k == 2 ? nullptr : bufs[(k - 1) % 3];
+            a.xkm1 = nullptr;                 // not read: c1 = 0
             a.xout = bufs[(k + 1) % 3];
             a.field = last ? field : nullptr;
             a.ge = last ? ge : nullptr;
@@ -765,9 +777,9 @@ void plan_step3(const Plan3In& in, std::vector<Launch3>& out)
             a.g = in.ug[comp];
             a.P = in.P;
             a.plane = in.plane;
-            a.inv_theta = in.cheb.inv_theta;
-            a.c1 = in.cheb.c1[k - 1];
-            a.c2 = in.cheb.c2[k - 1];
+            a.inv_theta = w[0];               // x_1 = w_0 b
+            a.c1 = 0.0;
+            a.c2 = w[k];
             a.cf = in.coef;
             const dim3 g = cheb3_grid(a.g);
             r.gx = g.x;
