@@ -285,7 +285,8 @@ size_t c4m_source_work_bytes(const c4m_problem* p);
  * aligned, the caller's; the source arrays and `work` must stay valid until
  * the stream has run the step.  EINVAL unless 2D, the compact scheme and
  * the PAPER closure (the REFLECT rows assume homogeneous Neumann data), or
- * for a short `work`; ESTATE for a batch member. */
+ * for a short `work`; ESTATE for a batch member.  With C4M_FLAG_CHECK_FINITE
+ * the call scans the fields afterwards as c4m_step does. */
 c4m_status c4m_step_source(c4m_problem* p, const c4m_source_tm* src, void* work, size_t work_bytes);
 
 /* Counters and sticky flags; synchronises the stream when PCG statistics

@@ -1220,6 +1220,25 @@ c4m_status c4m_get_field(c4m_problem* p, c4m_field f, double* dst, int dst_on_de
     return copy_field(p, (double*)srcp, p->box[c], dst, false, dst_on_device != 0);
 }
 
+// With C4M_FLAG_CHECK_FINITE: scan the fields for NaN / Inf, wait, and
+// report ENONFINITE (sticky in c4m_info).
+static c4m_status finite_check(c4m_problem* p)
+{
+    if (!(p->cfg.flags & C4M_FLAG_CHECK_FINITE)) return C4M_OK;
+    hipError_t e = hipMemsetAsync(p->counter, 0, sizeof(int), p->stream);
+    for (int c = 0; c < 6 && e == hipSuccess; ++c)
+        if (p->f[c]) e = launch_count_nonfinite(p->stream, p->f[c], p->box[c], p->P, p->plane, p->counter);
+    int h = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&h, p->counter, sizeof(int), hipMemcpyDeviceToHost, p->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
+    if (e != hipSuccess) return hip_fail(e, "finite check");
+    if (h) {
+        p->nonfinite = 1;
+        return fail(C4M_ENONFINITE, "non-finite field values");
+    }
+    return C4M_OK;
+}
+
 c4m_status c4m_step(c4m_problem* p, int64_t nsteps)
 {
     if (!p || nsteps < 0) return fail(C4M_EINVAL, "bad step count");
@@ -1228,22 +1247,7 @@ c4m_status c4m_step(c4m_problem* p, int64_t nsteps)
     if (s != C4M_OK) return s;
     s = run_steps(p, nsteps);
     if (s != C4M_OK) return s;
-    if (p->cfg.flags & C4M_FLAG_CHECK_FINITE) {
-        hipError_t e = hipMemsetAsync(p->counter, 0, sizeof(int), p->stream);
-        for (int c = 0; c < 6 && e == hipSuccess; ++c)
-            if (p->f[c])
-                e = launch_count_nonfinite(p->stream, p->f[c], p->box[c], p->P, p->plane, p->counter);
-        int h = 0;
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(&h, p->counter, sizeof(int), hipMemcpyDeviceToHost, p->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(p->stream);
-        if (e != hipSuccess) return hip_fail(e, "finite check");
-        if (h) {
-            p->nonfinite = 1;
-            return fail(C4M_ENONFINITE, "non-finite field values");
-        }
-    }
-    return C4M_OK;
+    return finite_check(p);
 }
 
 c4m_status c4m_prepare(c4m_problem* p, int64_t nsteps)
@@ -1402,7 +1406,7 @@ c4m_status c4m_step_source(c4m_problem* p, const c4m_source_tm* src, void* work,
     if (s == C4M_OK) s = timed(p, C4M_K_OTHER, "source Hy", [&] { return group(C4M_HY); });
     if (s != C4M_OK) return s;
     ++p->steps;
-    return C4M_OK;
+    return finite_check(p);
 }
 
 c4m_status c4m_get_info(c4m_problem* p, c4m_info* info)

@@ -175,3 +175,29 @@ def test_refusals():
     assert lib.c4m_step_source(p._h, ctypes.byref(src), ctypes.c_void_p(w.data_ptr()), need) == 0
     torch.cuda.synchronize()
     p.close()
+
+
+def test_check_finite_flag():
+    """With C4M_FLAG_CHECK_FINITE a sourced step scans the fields: an
+    infinite source value gives ENONFINITE (sticky), finite data passes."""
+    from paper_2306_17263_amd import ENONFINITE, FLAG_CHECK_FINITE, C4mError, Problem
+    n = 24
+    init = _random_init(n, 4)
+    p = Problem(2, n, 0.5, flags=FLAG_CHECK_FINITE)
+    for k in ("ez", "hx", "hy", "lz"):
+        p.set(k, init[k])
+    rng = np.random.default_rng(4)
+    d1, d2 = _random_data(n, rng)
+    good = dict(d1)
+    good.update(d2)
+    p.step_source(good)
+    assert p.info()["nonfinite"] == 0
+    bad = dict(good)
+    jz = good["jz"].copy()
+    jz[0, n // 2, n // 2] = np.inf
+    bad["jz"] = jz
+    with pytest.raises(C4mError) as ei:
+        p.step_source(bad)
+    assert ei.value.status == ENONFINITE
+    assert p.info()["nonfinite"] == 1
+    p.close()
