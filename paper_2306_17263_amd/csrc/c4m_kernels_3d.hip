@@ -445,21 +445,37 @@ static dim3 cheb3_grid(const UGrid& g)
                 (unsigned)((g.hi[2] - g.lo[2] + C3_CZ - 1) / C3_CZ));
 }
 
-// One Chebyshev round of K passes on M x = b with the iterates rotating
-// through bufs[0..2].  Without a field the last pass stores x_{K+1} and the
+// Step sizes of the first-order Chebyshev form of K applications of M:
+// x_1 = w_0 b, x_{k+1} = x_k + w_k (b - M x_k), w_j = 1 / mu_j at the K + 1
+// roots mu_j of the Chebyshev polynomial on [alpha, alpha + 16 beta / 3].
+// Its residual polynomial is that of the three-term recurrence with the
+// same K applications, and no x_{k-1} is read.  Every factor 1 - lambda w_j
+// stays below 3e-3 in size on the spectrum, so the order of the steps is
+// free.
+static void cheb_steps(const Coef& cf, int K, double* w)
+{
+    const double lmin = cf.alpha, lmax = cf.alpha + 16.0 / 3.0 * cf.beta;
+    const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
+    for (int j = 0; j <= K; ++j) w[j] = 1.0 / (theta - delta * cos((2 * j + 1) * M_PI / (2.0 * (K + 1))));
+}
+
+// One Chebyshev round of K passes on M x = b (the first-order form) with
+// the iterates rotating through bufs[0..2].  Without a field the last pass stores x_{K+1} and the
 // buffer holding it is returned; with a field the last pass applies
 // field += cfl (x_{K+1} + xadd) and null is returned.
 template <class TX, class TB, class TC>
-static TX* cheb3_round(hipStream_t st, const Cheb3& c, const TB* b, TX* const* bufs, int K, const ChebSchedule& cs,
+static TX* cheb3_round(hipStream_t st, const Cheb3& c, const TB* b, TX* const* bufs, int K,
                        const Coef& cf, const TX* xadd, double* field, double* ge, const double* cur)
 {
     const dim3 grid = cheb3_grid(c.g);
     TX* result = nullptr;
+    double w[MAX_SWEEPS + 1];
+    cheb_steps(cf, K, w);
     for (int k = 1; k <= K; ++k) {
         Cheb3T<TX, TB> a{};
         a.b = b;
         a.xk = bufs[k % 3];
-        a.xkm1 = k == 2 ? nullptr : bufs[(k - 1) % 3];   // x_1 is never stored
+        a.xkm1 = nullptr;                                 // not read: c1 = 0
         a.xout = bufs[(k + 1) % 3];
         a.xadd = xadd;
         a.field = field;
@@ -468,9 +484,9 @@ static TX* cheb3_round(hipStream_t st, const Cheb3& c, const TB* b, TX* const* b
         a.g = c.g;
         a.P = c.P;
         a.plane = c.plane;
-        a.inv_theta = cs.inv_theta;
-        a.c1 = cs.c1[k - 1];
-        a.c2 = cs.c2[k - 1];
+        a.inv_theta = w[0];                               // x_1 = w_0 b
+        a.c1 = 0.0;
+        a.c2 = w[k];
         a.cf = cf;
         const bool first = k == 1, last = k == K;
         if (last && field) {
@@ -498,7 +514,7 @@ hipError_t launch_solve3_mixed(hipStream_t st, const Cheb3& c, size_t arr, doubl
     f[5] = f[4] + arr;
     const int s_round = (cs.sweeps - 1) / 2;
     float* r1[3] = {f[0], f[1], f[2]};
-    float* x1 = cheb3_round<float, double, float>(st, c, c.r, r1, s_round, cs, cf, nullptr, nullptr, nullptr,
+    float* x1 = cheb3_round<float, double, float>(st, c, c.r, r1, s_round, cf, nullptr, nullptr, nullptr,
                                                    nullptr);
     // res = b - M x1 in FP64 (x1 is exact in FP64), kept as FP32
     float* res = f[3];
@@ -519,7 +535,7 @@ hipError_t launch_solve3_mixed(hipStream_t st, const Cheb3& c, size_t arr, doubl
     int n = 0;
     for (float* q : {f[0], f[1], f[2], f[4], f[5]})
         if (q != x1 && n < 3) r2[n++] = q;
-    cheb3_round<float, float, float>(st, c, res, r2, s_round, cs, cf, x1, field, ge, cur);
+    cheb3_round<float, float, float>(st, c, res, r2, s_round, cf, x1, field, ge, cur);
     return hipGetLastError();
 }
 
@@ -609,7 +625,7 @@ hipError_t launch_solve3(hipStream_t st, const Cheb3& c, double* field, double* 
 {
     // x_k rotates through three arrays: x, d0, d1 (b stays in r)
     double* bufs[3] = {c.x, c.d0, c.d1};
-    cheb3_round<double, double, double>(st, c, c.r, bufs, cs.sweeps, cs, cf, nullptr, field, ge, cur);
+    cheb3_round<double, double, double>(st, c, c.r, bufs, cs.sweeps, cf, nullptr, field, ge, cur);
     return hipGetLastError();
 }
 
@@ -743,19 +759,10 @@ void plan_step3(const Plan3In& in, std::vector<Launch3>& out)
         }
         out.push_back(r);
     };
-    // The solve in the first-order form x_{k+1} = x_k + w_k (b - M x_k),
-    // x_1 = w_0 b, with w_j = 1 / mu_j at the K + 1 roots mu_j of the
-    // Chebyshev polynomial on [alpha, alpha + 16 beta / 3]: the same residual
-    // polynomial as the three-term recurrence (whose K applications also give
-    // x_{K+1}), without reading x_{k-1}.  Every factor 1 - lambda w_j stays
-    // below 3e-3 in size on the spectrum, so the order of the steps is free.
+    // the solve in the first-order form (cheb_steps)
     const int K = in.cheb.sweeps;
     double w[MAX_SWEEPS + 1];
-    {
-        const double lmin = in.coef.alpha, lmax = in.coef.alpha + 16.0 / 3.0 * in.coef.beta;
-        const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
-        for (int j = 0; j <= K; ++j) w[j] = 1.0 / (theta - delta * cos((2 * j + 1) * M_PI / (2.0 * (K + 1))));
-    }
+    cheb_steps(in.coef, K, w);
     auto solve = [&](int comp, double* field, double* ge, const double* cr, int cls, int group) {
         double* bufs[3] = {x, d0, d1};
         for (int k = 1; k <= K; ++k) {
