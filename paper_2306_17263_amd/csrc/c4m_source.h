@@ -37,7 +37,8 @@ struct SrcTile {
     ChebGeom g;
     SrcUpdate u;
     int comp, N, K;
-    double c1[MAX_SWEEPS], c2[MAX_SWEEPS];
+    double c1[MAX_SWEEPS], c2[MAX_SWEEPS];   // the problem's schedule (the host fills it)
+    double w[MAX_SWEEPS + 1];   // step sizes of the first-order form (the launcher fills them)
 };
 
 hipError_t launch_src_group(hipStream_t st, const SrcTile& a);

@@ -107,10 +107,11 @@ __device__ double rhs_h_at(const SourceTM& s, const double* vc, int comp, int N,
 // One component's correction on a T x T tile (see the top of the file).
 // Window: W = T + 2K points per side around the tile, in storage indices
 // from (rx, ry), holding b and two iterates.  Application k (1..K) of the
-// recurrence
-//   x_{k+1} = x_k + c1 (x_k - x_{k-1}) + c2 (b - M x_k),  x_0 = 0, x_1 = b / theta,
-// runs on window points k .. W-1-k; x_{k+1} goes to buf[(k+1) % 2] (over
-// x_{k-1}, which each point reads first), the last one into the field.
+// first-order Chebyshev form (the residual polynomial of the three-term
+// recurrence with the same K applications, no x_{k-1} read)
+//   x_{k+1} = x_k + w_k (b - M x_k),  x_1 = w_0 b,
+// runs on window points k .. W-1-k; x_{k+1} goes to buf[(k+1) % 2], the last
+// one into the field.
 // M = alpha I - beta L9 with the homogeneous wall rules is a plain 9-point
 // stencil on the window because the window holds them explicitly: zero on
 // the node walls (never written), and at the first point beyond a half-axis
@@ -159,9 +160,9 @@ __global__ __launch_bounds__(NT) void k_src_tile(SrcTile a)
     const bool half_x = g.half[0] != 0, half_y = g.half[1] != 0;
     for (int k = 1; k <= K; ++k) {
         const double* xk = k == 1 ? sb : buf[k % 2];
-        const double sc = k == 1 ? g.inv_theta : 1.0;
+        const double sc = k == 1 ? a.w[0] : 1.0;
         double* out = buf[(k + 1) % 2];
-        const double c1 = a.c1[k - 1], c2 = a.c2[k - 1];
+        const double wk = a.w[k];
         const int span = W - 2 * k;
         const int run = (span + RS - 1) / RS;
         const int li = k + tx;
@@ -183,8 +184,7 @@ __global__ __launch_bounds__(NT) void k_src_tile(SrcTile a)
                     const int wp = lj * W + li;
                     const double bo = sb[wp];
                     const double mx = fma(g.alpha, xc, -g.beta * l9);
-                    const double xp = k == 1 ? 0.0 : (k == 2 ? bo * g.inv_theta : out[wp]);
-                    const double xn = xc + c1 * (xc - xp) + c2 * (bo - mx);
+                    const double xn = fma(wk, bo - mx, xc);
                     if (k < K) {
                         out[wp] = xn;
                         // mirror ghosts (first point beyond a half-axis wall)
@@ -221,9 +221,14 @@ size_t src_tile_lds(int K)
     return 3 * w * w * sizeof(double);
 }
 
-hipError_t launch_src_group(hipStream_t st, const SrcTile& a)
+hipError_t launch_src_group(hipStream_t st, const SrcTile& a0)
 {
-    if (a.K < 1 || a.K > MAX_SWEEPS) return hipErrorInvalidValue;
+    if (a0.K < 1 || a0.K > MAX_SWEEPS) return hipErrorInvalidValue;
+    // w_j = 1 / mu_j at the K + 1 Chebyshev roots on [alpha, alpha + 16 beta / 3]
+    SrcTile a = a0;
+    const double lmin = a.g.alpha, lmax = a.g.alpha + 16.0 / 3.0 * a.g.beta;
+    for (int j = 0; j <= a.K; ++j)
+        a.w[j] = 1.0 / (0.5 * (lmax + lmin) - 0.5 * (lmax - lmin) * cos((2 * j + 1) * M_PI / (2.0 * (a.K + 1))));
     const int nx = a.g.hi[0] - a.g.lo[0] + 1, ny = a.g.hi[1] - a.g.lo[1] + 1;
     const dim3 grid((unsigned)((nx + SRC_TILE - 1) / SRC_TILE), (unsigned)((ny + SRC_TILE - 1) / SRC_TILE));
     hipLaunchKernelGGL((k_src_tile<SRC_TILE, SRC_THREADS>), grid, dim3(SRC_THREADS), src_tile_lds(a.K), st, a);
