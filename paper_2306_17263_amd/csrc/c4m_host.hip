@@ -1332,7 +1332,6 @@ static ChebGeom src_geom(const c4m_problem* p, int comp)
     g.P = p->P;
     g.alpha = p->coef.alpha;
     g.beta = p->coef.beta;
-    g.inv_theta = p->cheb.inv_theta;
     return g;
 }
 
@@ -1385,10 +1384,6 @@ c4m_status c4m_step_source(c4m_problem* p, const c4m_source_tm* src, void* work,
         a.comp = f == C4M_EZ ? 2 : f - C4M_HX;
         a.N = N;
         a.K = p->cheb.sweeps;
-        for (int k = 0; k < a.K && k < MAX_SWEEPS; ++k) {
-            a.c1[k] = p->cheb.c1[k];
-            a.c2[k] = p->cheb.c2[k];
-        }
         return launch_src_group(p->stream, a);
     };
     // Compulsory bytes of one correction group (its source arrays read once,

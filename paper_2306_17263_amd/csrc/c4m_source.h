@@ -14,10 +14,10 @@ struct SrcCoef {
 };
 
 // One component grid of the correction solve: extents, half flags, the
-// unknown box (inclusive), the pitch and the M / Chebyshev constants.
+// unknown box (inclusive), the pitch and the constants of M.
 struct ChebGeom {
     int n[2], half[2], lo[2], hi[2], P;
-    double alpha, beta, inv_theta;
+    double alpha, beta;
 };
 
 // Field update of the last Chebyshev application (field == nullptr: none).
@@ -36,8 +36,7 @@ struct SrcTile {
     SrcCoef c;
     ChebGeom g;
     SrcUpdate u;
-    int comp, N, K;
-    double c1[MAX_SWEEPS], c2[MAX_SWEEPS];   // the problem's schedule (the host fills it)
+    int comp, N, K;             // K: applications of M (the problem's schedule)
     double w[MAX_SWEEPS + 1];   // step sizes of the first-order form (the launcher fills them)
 };
 
