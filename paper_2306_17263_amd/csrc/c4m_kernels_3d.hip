@@ -212,9 +212,11 @@ __global__ __launch_bounds__(256) void k_term3(Term3 t, double alpha, PadeTaps t
 template <int MODE>
 __device__ __forceinline__ void condition3_body(const Term3& t, double alpha, uint3 blk)
 {
-    const int i = blk.x * 256 + threadIdx.x;
-    const int j = blk.y, k = blk.z;
-    if (i >= t.sb.n[0]) return;
+    // 64 x 4 points of a plane per workgroup (a row of 257 points leaves
+    // one lane busy in its last block, not 255 idle)
+    const int i = blk.x * 64 + (threadIdx.x & 63);
+    const int j = blk.y * 4 + (threadIdx.x >> 6), k = blk.z;
+    if (i >= t.sb.n[0] || j >= t.sb.n[1]) return;
     double raw;
     t.out[(size_t)k * t.plane + (size_t)j * t.P + i] = src_value<MODE>(t, i, j, k, alpha, true, raw);
 }
@@ -606,7 +608,7 @@ hipError_t launch_condition3(hipStream_t st, int mode, const double* src, double
     t.sb = bx;
     t.P = P;
     t.plane = plane;
-    const dim3 grid((bx.n[0] + 255) / 256, bx.n[1], bx.n[2]);
+    const dim3 grid((bx.n[0] + 63) / 64, (bx.n[1] + 3) / 4, bx.n[2]);
     if (mode == SRC_G) hipLaunchKernelGGL((k_condition3<SRC_G>), grid, dim3(256), 0, st, t, alpha);
     else hipLaunchKernelGGL((k_condition3<SRC_GE_DISCRETE>), grid, dim3(256), 0, st, t, alpha);
     return hipGetLastError();
@@ -726,8 +728,8 @@ void plan_step3(const Plan3In& in, std::vector<Launch3>& out)
             r.t.P = in.P;
             r.t.plane = in.plane;
             const Box& bx = in.box[first_src + j];
-            r.gx = (unsigned)((bx.n[0] + 255) / 256);
-            r.gy = (unsigned)bx.n[1];
+            r.gx = (unsigned)((bx.n[0] + 63) / 64);
+            r.gy = (unsigned)((bx.n[1] + 3) / 4);
             r.gz = (unsigned)bx.n[2];
             out.push_back(r);
         }
