@@ -282,7 +282,10 @@ size_t c4m_source_work_bytes(const c4m_problem* p);
  * of the right-hand side (M's Chebyshev iteration in FP64, the problem's
  * schedule), added to the field before the next half-step reads it.  `work`:
  * device memory of at least c4m_source_work_bytes(p) bytes, 256-byte
- * aligned, the caller's; the source arrays and `work` must stay valid until
+ * aligned, the caller's; the first call with a buffer writes the library's
+ * tables into it (an asynchronous copy from host memory), later calls with
+ * the same pointer use them as they are, so the caller leaves its contents
+ * alone between calls and gives each problem a buffer of its own.  The source arrays and `work` must stay valid until
  * the stream has run the step.  EINVAL unless 2D, the compact scheme and
  * the PAPER closure (the REFLECT rows assume homogeneous Neumann data), or
  * for a short `work`; ESTATE for a batch member.  With C4M_FLAG_CHECK_FINITE

@@ -341,6 +341,7 @@ struct c4m_problem {
     bool direct = false;                // launch steps without graphs (no-allocation call)
     std::vector<Launch3> plan3;         // 3D FP64 Chebyshev step as recorded launches (built on first use)
     std::vector<double> src_cols;       // sourced step: column 0 of A^{-1}, half->node (N-1) then node->half (N)
+    void* src_work = nullptr;           // the work buffer that holds them on the device
 };
 
 namespace {
@@ -1360,9 +1361,13 @@ c4m_status c4m_step_source(c4m_problem* p, const c4m_source_tm* src, void* work,
     }
     double* wc = (double*)work;
     double* vc = wc + (N - 1);
-    hipError_t e = hipMemcpyAsync(wc, p->src_cols.data(), p->src_cols.size() * sizeof(double),
-                                  hipMemcpyHostToDevice, p->stream);
-    if (e != hipSuccess) return hip_fail(e, "source tables");
+    if (work != p->src_work) {
+        // the tables go to a work buffer once; later calls with it find them there
+        hipError_t e = hipMemcpyAsync(wc, p->src_cols.data(), p->src_cols.size() * sizeof(double),
+                                      hipMemcpyHostToDevice, p->stream);
+        if (e != hipSuccess) return hip_fail(e, "source tables");
+        p->src_work = work;
+    }
     c4m_status s = ensure_ge(p);
     if (s != C4M_OK) return s;
     const double r = p->cfg.cfl, z = p->cfg.z, h = 1.0 / N;

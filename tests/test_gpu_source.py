@@ -201,3 +201,49 @@ def test_check_finite_flag():
     assert ei.value.status == ENONFINITE
     assert p.info()["nonfinite"] == 1
     p.close()
+
+
+def test_work_buffer_kept_between_calls():
+    """The tables go to a work buffer on its first call; later calls reuse
+    them, a new buffer gets them again, and the results do not depend on
+    which: three steps with one buffer equal three steps alternating two."""
+    import ctypes
+
+    import torch
+
+    from paper_2306_17263_amd import Problem
+    from paper_2306_17263_amd import _lib as L
+    n = 40
+    init = _random_init(n, 21)
+    rng = np.random.default_rng(21)
+    data = [_random_data(n, rng) for _ in range(3)]
+    out = []
+    for alternate in (False, True):
+        p = Problem(2, n, 0.5)
+        for k in ("ez", "hx", "hy", "lz"):
+            p.set(k, init[k])
+        lib = L.load()
+        need = lib.c4m_source_work_bytes(p._h)
+        bufs = [torch.empty(need, dtype=torch.uint8, device=p.device) for _ in range(2)]
+        keep = []
+        for m in range(3):
+            dd = dict(data[m][0])
+            dd.update(data[m][1])
+            src = L.C4mSourceTM()
+            for name in Problem.SOURCE_ARRAYS:
+                t = torch.as_tensor(dd[name]).to(p.device).contiguous()
+                keep.append(t)
+                setattr(src, name, t.data_ptr())
+            for name in Problem.SOURCE_WALLS:
+                slot = getattr(src, name)
+                for w in (0, 1):
+                    for d in (0, 1):
+                        t = torch.as_tensor(dd[name][w][d]).to(p.device).contiguous()
+                        keep.append(t)
+                        slot[w][d] = t.data_ptr()
+            wb = bufs[m % 2] if alternate else bufs[0]
+            assert lib.c4m_step_source(p._h, ctypes.byref(src), ctypes.c_void_p(wb.data_ptr()), need) == 0
+        out.append({k: p.get(k) for k in ("ez", "hx", "hy")})
+        p.close()
+    for k in ("ez", "hx", "hy"):
+        assert np.array_equal(out[0][k], out[1][k]), k
